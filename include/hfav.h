@@ -1,0 +1,287 @@
+/*
+ * hfav.h - fused stencil-chain execution on AMD Instinct MI355X (gfx950).
+ *
+ * A chain is stated the way the paper states its problems (Introduction,
+ * "Contributions"; Implementation, "Inference"): AXIOMS are the input arrays,
+ * GOALS the outputs, and RULES the kernels, each rule reading named terms at
+ * constant relative offsets (the translation-free frame of Design,
+ * "Fundamentals") and producing named terms at offset zero.  The library
+ *
+ *   hfav_chain_create  records and validates the chain (dataflow DAG: rule
+ *                      call sites as vertices, terms as edges; Design,
+ *                      "Dataflow"; one producer per term, Related Work),
+ *   hfav_plan          builds the iteration-nest DAG, fuses it (Design,
+ *                      "Fusion", both fuse_inest_dag and fuse_inest), places
+ *                      0-D broadcasts and reductions in prologue / epilogue
+ *                      phases (Design, "Reductions & broadcasts & splits"),
+ *                      derives every term's extent by Minkowski sums of the
+ *                      offsets (Design, "Variables and storage"), and the
+ *                      rolling-window depth of every intermediate from its
+ *                      reuse span (Design, "Contraction"); it then selects a
+ *                      hand-written fused gfx950 kernel family and its tile
+ *                      configuration, or the unfused one-kernel-per-rule path,
+ *   hfav_execute       enqueues the chain on a HIP stream.
+ *
+ * All functions are thread-compatible (one handle per thread at a time),
+ * never abort and never throw; they return an hfav_status.  Strings returned
+ * by the library stay valid until the next call on the same thread.
+ *
+ * Memory: every array argument is a DEVICE pointer owned by the caller.
+ * Grid terms are dense, C order, innermost axis i (x) fastest:
+ * element (i, j, k) of an (nx, ny, nz) grid is at ((k*ny + j)*nx + i).
+ * 0-D terms (rank 0) are device pointers to one element.  The element type
+ * of every term is the chain's dtype (hfav_chain_desc.dtype); 0-D terms are
+ * always double.
+ */
+#ifndef HFAV_H
+#define HFAV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status */
+typedef enum {
+    HFAV_OK = 0,
+    HFAV_EINVAL = 1,   /* null or ill-formed argument, unknown op, wrong arity,
+                          bad dims, ndim not in {2,3} */
+    HFAV_EUNSAT = 2,   /* a goal (or a rule input) is not derivable from the
+                          axioms through the rules (Implementation, "Inference") */
+    HFAV_EDUP = 3,     /* two rules produce the same term, or a rule produces an
+                          axiom: one producer per term (Related Work) */
+    HFAV_ECYCLE = 4,   /* the dataflow graph has a cycle (Design, "Dataflow") */
+    HFAV_EUNSUP = 5,   /* valid chain but no kernel can run it in the requested
+                          mode / precision */
+    HFAV_EALIAS = 6,   /* an output buffer overlaps an input buffer; aliasing is
+                          not declared by this interface (Design, "In/out
+                          chaining") */
+    HFAV_ENOPLAN = 7,  /* execute before a successful plan, or a missing
+                          workspace */
+    HFAV_EDEVICE = 8   /* HIP runtime or launch error; text in hfav_last_error */
+} hfav_status;
+
+/* ------------------------------------------------------------------ enums */
+typedef enum { HFAV_F64 = 0, HFAV_F32 = 1 } hfav_dtype;
+
+/* Rule catalogue.  The kernels themselves are compiled into the library; a
+ * rule names one and binds its arguments BY POSITION (Implementation: only
+ * the function name and argument positions matter).  "in" lists the input
+ * references in argument order, "out" the produced terms.  Offsets are
+ * (di, dj, dk).  Params are doubles. */
+typedef enum {
+    /* COSMO horizontal diffusion (Performance, "COSMO Micro-Kernels") */
+    HFAV_OP_HDIFF_LAP = 1,   /* in: u(c), u(+i), u(-i), u(+j), u(-j) -> lap
+                                lap = (e+w) + (n+s) - 4c                        */
+    HFAV_OP_HDIFF_FLX = 2,   /* in: lap(0), lap(+i), u(0), u(+i) -> flx
+                                flx = lap(+i)-lap(0); 0 if flx*(u(+i)-u(0)) > 0 */
+    HFAV_OP_HDIFF_FLY = 3,   /* same along j: lap(0), lap(+j), u(0), u(+j) -> fly */
+    HFAV_OP_HDIFF_OUT = 4,   /* in: u, flx(0), flx(-i), fly(0), fly(-j) -> out;
+                                param[0] = coeff;
+                                out = u - coeff*((flx-flx(-i)) + (fly-fly(-j)))  */
+    /* Directionally split Godunov sweep (Performance, "Hydro2D").  Fields of
+     * a sweep are ordered (rho, normal momentum, transverse momentum, E);
+     * the same rules with offsets along j and swapped momenta give the y
+     * pass, as the paper describes for its dimensionally split operator. */
+    HFAV_OP_EULER_PRIM = 10,   /* in: rho, mn, mt, E (offset 0) -> r, un, ut, p, c;
+                                  param[0] = gamma (constoprim + eos)             */
+    HFAV_OP_EULER_SLOPE = 11,  /* in: r(-1), r(0), r(+1), un(..), ut(..), p(..)
+                                  (12 refs, offsets along the sweep) -> dr, dun,
+                                  dut, dp (van Leer limited)                       */
+    HFAV_OP_EULER_TRACE = 12,  /* in: r, un, ut, p, c, dr, dun, dut, dp, dt (0-D)
+                                  -> 4 plus-face values (rho, un, ut, p) at m+1/2,
+                                  then 4 minus-face values at m-1/2               */
+    HFAV_OP_EULER_RIEMANN = 13,/* in: 4 plus-face values at offset 0, 4 minus-face
+                                  values at offset +1 (qleftright) -> Godunov
+                                  state (rho, un, ut, p) at x/t = 0;
+                                  param[0] = gamma, param[1] = Newton iterations  */
+    HFAV_OP_EULER_FLUX = 14,   /* in: Godunov state -> 4 fluxes; param[0] = gamma */
+    HFAV_OP_EULER_UPDATE = 15, /* in: 4 conserved (0), 4 fluxes (0), 4 fluxes (-1),
+                                  dt (0-D) -> 4 conserved                          */
+    HFAV_OP_EULER_SMAX = 16,   /* in: rho, mx, my, E -> smax (0-D, reduce MAX):
+                                  max over cells of max(|u|+c, |v|+c); gamma      */
+    HFAV_OP_EULER_DT = 17,     /* 0-D: in: smax -> dt = param[0](CFL)/smax        */
+    /* Linear stencils */
+    HFAV_OP_LAP7 = 20,         /* in: u(0), u(+i), u(-i), u(+j), u(-j), u(+k), u(-k)
+                                  -> ((e+w)+(n+s))+(t+b) - 6c                      */
+    HFAV_OP_AXPY = 21,         /* in: a, b -> a + param[0]*b                       */
+    HFAV_OP_STAR = 22          /* in: n refs -> sum_q param[q]*ref_q, accumulated
+                                  in reference order from zero                    */
+} hfav_op;
+
+typedef enum { HFAV_REDUCE_NONE = 0, HFAV_REDUCE_MAX = 1 } hfav_reduce;
+typedef enum { HFAV_BC_PERIODIC = 0, HFAV_BC_TRANSMISSIVE = 1 } hfav_bc;
+typedef enum { HFAV_MODE_AUTO = 0, HFAV_MODE_FUSED = 1, HFAV_MODE_UNFUSED = 2 } hfav_mode;
+typedef enum {
+    HFAV_PREC_NATIVE = 0,     /* all arithmetic in the chain dtype */
+    HFAV_PREC_F32_F64ACC = 1  /* F32 storage and arithmetic, except the Riemann
+                                 pressure iteration and the conservative update
+                                 accumulation, which run in F64 */
+} hfav_precision;
+typedef enum {
+    HFAV_CONFIG_DEFAULT = 0,  /* built-in per-family default */
+    HFAV_CONFIG_TUNED = 1,    /* tuning table (hfav_set_tuning), else default */
+    HFAV_CONFIG_MODEL = 2,    /* learned cost model (hfav_set_cost_model), else default */
+    HFAV_CONFIG_FORCED = 3    /* hfav_plan_opts.forced */
+} hfav_config_source;
+
+typedef enum {
+    HFAV_FAMILY_NONE = 0,     /* no fused kernel: unfused path */
+    HFAV_FAMILY_HDIFF = 1,
+    HFAV_FAMILY_EULER_X = 2,
+    HFAV_FAMILY_EULER_Y = 3,
+    HFAV_FAMILY_LAP7_CHAIN = 4,
+    HFAV_FAMILY_STAR_CHAIN = 5,
+    HFAV_FAMILY_SMAX = 6
+} hfav_family;
+
+typedef enum {
+    HFAV_STORE_FULL = 0,       /* full array in HBM (axiom, goal, or split) */
+    HFAV_STORE_REGISTER = 1,   /* window of 1: a value in a register */
+    HFAV_STORE_INNER = 2,      /* rolling window along the innermost axis only
+                                  ("inner" rotation, Design "Contraction") */
+    HFAV_STORE_OUTER = 3,      /* rolling window of slabs along an outer axis
+                                  ("outer" rotation) */
+    HFAV_STORE_SCALAR = 4      /* 0-D term */
+} hfav_storage;
+
+/* --------------------------------------------------------------- the chain */
+typedef struct {
+    const char *term;   /* term name */
+    int off[3];         /* (di, dj, dk) relative offset */
+} hfav_ref;
+
+typedef struct {
+    int op;                     /* hfav_op */
+    int n_in;                   /* number of input references */
+    const hfav_ref *in;
+    int n_out;                  /* number of produced terms */
+    const char *const *out;     /* produced term names (offset 0) */
+    int n_param;
+    const double *param;
+    int reduce;                 /* hfav_reduce: MAX makes the (single) output a
+                                   0-D term accumulated over the iteration space */
+} hfav_rule;
+
+typedef struct {
+    const char *name;
+    int rank;                   /* 0 for a scalar (device pointer to one double),
+                                   otherwise the grid rank (must equal ndim) */
+} hfav_term_decl;
+
+typedef struct {
+    int ndim;                   /* 2 or 3 */
+    const char *loop_order;     /* axis letters outermost first, e.g. "kji" or
+                                   "ji"; NULL means "kji" / "ji" (Design,
+                                   "Fundamentals": user-selected global order) */
+    int dtype;                  /* hfav_dtype of every grid term */
+    int n_axiom;
+    const hfav_term_decl *axioms;
+    int n_goal;
+    const char *const *goals;
+    int n_rule;
+    const hfav_rule *rules;
+} hfav_chain_desc;
+
+typedef struct hfav_chain hfav_chain;   /* opaque */
+
+/* Fused-kernel tile configuration (autotuner / cost-model search space). */
+typedef struct {
+    int block;      /* threads per workgroup (64, 128, 256, 512) */
+    int tile_y;     /* rows of the tile across lanes (2-D tiles), or 1 */
+    int seg;        /* cells streamed per thread along the streamed axis */
+    int variant;    /* family-specific kernel variant, 0 = default */
+} hfav_config;
+
+typedef struct {
+    int dims[3];                /* nx, ny, nz (nz = 1 for ndim 2) */
+    int boundary[3];            /* hfav_bc per axis (i, j, k) */
+    int mode;                   /* hfav_mode */
+    int precision;              /* hfav_precision */
+    int config_source;          /* hfav_config_source */
+    hfav_config forced;         /* used when config_source = FORCED */
+} hfav_plan_opts;
+
+#define HFAV_MAX_RULES 64
+#define HFAV_MAX_NESTS 8
+
+typedef struct {
+    int n_rules;                        /* rules kept after pruning dead ones */
+    int rule_order[HFAV_MAX_RULES];     /* topological order (descriptor indices) */
+    int n_nests;                        /* iteration nests after fusion */
+    int nest_of_rule[HFAV_MAX_RULES];   /* nest index per descriptor rule, -1 if pruned */
+    int phase_of_rule[HFAV_MAX_RULES];  /* 0 prologue, 1 steady state, 2 epilogue */
+    int family;                         /* hfav_family chosen (NONE = unfused) */
+    int fused;                          /* 1 if hfav_execute runs a fused kernel */
+    int streamed_axis;                  /* axis streamed by the fused kernel (0 i, 1 j, 2 k) */
+    hfav_config config;                 /* tile configuration chosen */
+    int config_source;                  /* where the configuration came from */
+    int64_t footprint_unfused;          /* elements of all intermediates as full arrays */
+    int64_t footprint_contracted;       /* elements of all intermediates after contraction */
+    int max_window;                     /* largest window depth (slabs or elements) */
+    double bytes_per_cell_fused;        /* compulsory HBM bytes per cell: axioms once + goals once */
+    double bytes_per_cell_unfused;      /* HBM bytes per cell of the one-kernel-per-rule path */
+    size_t workspace_bytes;             /* device workspace hfav_execute needs (0 for most fused) */
+} hfav_plan_info;
+
+typedef struct {
+    const char *name;
+    int kind;                   /* 0 axiom, 1 intermediate, 2 goal */
+    int rank;
+    int producer;               /* descriptor rule index, -1 for an axiom */
+    int ext_lo[3], ext_hi[3];   /* Minkowski extent relative to the nest point */
+    int storage;                /* hfav_storage */
+    int window_axis;            /* axis of the rolling window (0 i, 1 j, 2 k), -1 none */
+    int window;                 /* window depth: slabs (OUTER) or elements (INNER) */
+} hfav_term_info;
+
+/* ------------------------------------------------------------- the calls */
+
+/* Record and validate a chain.  The descriptor and everything it points to
+ * are copied; the caller keeps ownership.  Rules not needed for any goal are
+ * pruned (inference works backward from the goals).
+ * Errors: EINVAL, EUNSAT, EDUP, ECYCLE.  *out is NULL on error. */
+int hfav_chain_create(const hfav_chain_desc *desc, hfav_chain **out);
+
+/* Plan the chain for a grid size and boundary: fusion, extents, windows,
+ * kernel family and tile configuration.  Host only, deterministic, allocates
+ * no device memory.  `info` may be NULL.  Re-planning replaces the plan.
+ * Errors: EINVAL (bad dims / boundary), EUNSUP (mode or precision not
+ * available for this chain). */
+int hfav_plan(hfav_chain *chain, const hfav_plan_opts *opts, hfav_plan_info *info);
+
+/* Enqueue the planned chain on `stream` (a hipStream_t; NULL = default
+ * stream).  axioms[] and goals[] are device pointers in declaration order.
+ * `workspace` must hold info.workspace_bytes (it may be NULL when that is 0);
+ * it is caller-owned device memory the call may overwrite.  Asynchronous: no
+ * allocation, no synchronisation, no device-to-host read, so it can be
+ * captured in a HIP graph.  Kernel faults surface at the caller's next
+ * synchronisation.
+ * Errors: ENOPLAN, EINVAL (null pointer), EALIAS, EDEVICE. */
+int hfav_execute(hfav_chain *chain, const void *const *axioms, void *const *goals,
+                 void *workspace, void *stream);
+
+/* Release a chain (NULL is allowed). */
+void hfav_chain_destroy(hfav_chain *chain);
+
+/* Text of the last error on this thread ("" if none). */
+const char *hfav_last_error(void);
+
+/* Library version string. */
+const char *hfav_version(void);
+
+/* Per-term plan details (extent, storage class, window), term index in
+ * [0, hfav_num_terms).  Errors: ENOPLAN, EINVAL. */
+int hfav_num_terms(const hfav_chain *chain);
+int hfav_plan_term(const hfav_chain *chain, int index, hfav_term_info *info);
+
+/* The plan as a JSON document (nests, phases, extents, windows, family,
+ * configuration); valid until the next call on this thread.  NULL on error. */
+const char *hfav_plan_json(const hfav_chain *chain);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HFAV_H */

@@ -1,0 +1,189 @@
+// hfav_execute: enqueue the planned chain.  Fused families launch their
+// hand-written kernel (plus a one-lane initialisation of a fused reduction
+// goal: the "init" phase of a reduction, Design "Reductions & broadcasts &
+// splits"); the unfused path launches one kernel per rule in topological
+// order with intermediates in the caller's workspace.  No allocation, no
+// synchronisation, no device-to-host traffic.
+#include <cstring>
+#include <string>
+
+#include "internal.h"
+#include "kernels.h"
+
+namespace {
+
+struct Bind {
+    const hfav_chain *c;
+    const void *const *ax;
+    void *const *go;
+    char *ws;
+    const void *ptr(int t) const {
+        const HTerm &T = c->terms[t];
+        if (T.kind == TK_AXIOM) return ax[T.axiom_slot];
+        if (T.kind == TK_GOAL) return go[T.goal_slot];
+        const int64_t off = c->plan.ws_off[t];
+        return off < 0 ? nullptr : ws + off;
+    }
+    void *wptr(int t) const { return const_cast<void *>(ptr(t)); }
+};
+
+int dev_err(hipError_t e, const char *what) {
+    if (e == hipSuccess) return HFAV_OK;
+    return hfav_fail(HFAV_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+size_t term_bytes(const hfav_chain *c, int t) {
+    if (c->terms[t].rank == 0) return 8;
+    const int *d = c->plan.opts.dims;
+    return (size_t)d[0] * d[1] * d[2] * (c->dtype == HFAV_F64 ? 8 : 4);
+}
+
+bool overlap(const void *a, size_t na, const void *b, size_t nb) {
+    const char *pa = (const char *)a, *pb = (const char *)b;
+    return pa < pb + nb && pb < pa + na;
+}
+
+int run_fused(const hfav_chain *c, const Bind &B, hipStream_t s) {
+    const HPlan &p = c->plan;
+    const int *d = p.opts.dims;
+    switch (p.family) {
+    case HFAV_FAMILY_HDIFF: {
+        hfav::HdiffLaunch L;
+        L.in = B.ptr(p.fam_in[0]);
+        L.out = B.wptr(p.fam_out[0]);
+        L.ni = d[0]; L.nj = d[1]; L.nk = d[2];
+        L.coeff = p.fam_param[0];
+        L.dtype = c->dtype;
+        L.cfg = p.info.config;
+        return dev_err(hfav::launch_hdiff(L, s), "hdiff kernel launch");
+    }
+    case HFAV_FAMILY_EULER_X:
+    case HFAV_FAMILY_EULER_Y: {
+        hfav::EulerLaunch L;
+        for (int q = 0; q < 4; ++q) { L.in[q] = B.ptr(p.fam_in[q]); L.out[q] = B.wptr(p.fam_out[q]); }
+        L.nx = d[0]; L.ny = d[1];
+        const int dir = p.family == HFAV_FAMILY_EULER_X ? 0 : 1;
+        L.bc = p.opts.boundary[dir];
+        L.gamma = p.fam_param[0];
+        L.niter = (int)p.fam_param[1];
+        L.dt_src = (const double *)B.ptr(p.fam_dt_term);
+        L.dt_mode = p.fam_dt_mode == 1 ? hfav::DT_FROM_SMAX : hfav::DT_VALUE;
+        L.cfl = p.fam_cfl;
+        L.smax_out = p.fam_smax_goal >= 0 ? (double *)B.wptr(p.fam_smax_goal) : nullptr;
+        L.dtype = c->dtype;
+        L.precision = p.opts.precision;
+        L.cfg = p.info.config;
+        if (L.smax_out) {
+            int rc = dev_err(hfav::launch_fill_scalar(L.smax_out, 0.0, s), "reduction init");
+            if (rc) return rc;
+        }
+        return dev_err(dir == 0 ? hfav::launch_euler_x(L, s) : hfav::launch_euler_y(L, s), "euler sweep launch");
+    }
+    case HFAV_FAMILY_LAP7_CHAIN: {
+        hfav::Lap7ChainLaunch L;
+        L.in = B.ptr(p.fam_in[0]);
+        L.out = B.wptr(p.fam_out[0]);
+        L.nx = d[0]; L.ny = d[1]; L.nz = d[2];
+        L.alpha = p.fam_param[0];
+        L.dtype = c->dtype;
+        L.cfg = p.info.config;
+        return dev_err(hfav::launch_lap7_chain(L, s), "lap7 chain launch");
+    }
+    case HFAV_FAMILY_SMAX: {
+        const void *U[4];
+        for (int q = 0; q < 4; ++q) U[q] = B.ptr(p.fam_in[q]);
+        double *out = (double *)B.wptr(p.fam_out[0]);
+        int rc = dev_err(hfav::launch_fill_scalar(out, 0.0, s), "reduction init");
+        if (rc) return rc;
+        return dev_err(hfav::launch_euler_smax(U, d[0] * d[1] * d[2], p.fam_param[0], out, c->dtype, s),
+                       "smax launch");
+    }
+    default:
+        return hfav_fail(HFAV_EUNSUP, "no fused family");
+    }
+}
+
+int run_unfused(const hfav_chain *c, const Bind &B, hipStream_t s) {
+    const HPlan &p = c->plan;
+    const int *d = p.opts.dims;
+    for (int r : p.exec_order) {
+        const HRule &R = c->rules[r];
+        if (R.op == HFAV_OP_STAR) {
+            std::vector<const void *> ptrs(R.in.size());
+            std::vector<int> offs(3 * R.in.size());
+            for (size_t q = 0; q < R.in.size(); ++q) {
+                ptrs[q] = B.ptr(R.in[q].term);
+                for (int ax = 0; ax < 3; ++ax) offs[3 * q + ax] = R.in[q].off[ax];
+            }
+            hfav::StarRule S;
+            S.n_in = (int)R.in.size();
+            S.in = ptrs.data();
+            S.off = offs.data();
+            S.coeff = R.param.data();
+            S.out = B.wptr(R.out[0]);
+            S.nx = d[0]; S.ny = d[1]; S.nz = d[2];
+            for (int ax = 0; ax < 3; ++ax) S.bc[ax] = p.opts.boundary[ax];
+            S.dtype = c->dtype;
+            int rc = dev_err(hfav::launch_star_rule(S, s), "star rule launch");
+            if (rc) return rc;
+            continue;
+        }
+        hfav::UnfusedRule U;
+        memset(&U, 0, sizeof(U));
+        U.op = R.op;
+        U.n_in = (int)R.in.size();
+        U.n_out = (int)R.out.size();
+        for (size_t q = 0; q < R.in.size(); ++q) {
+            U.in[q] = B.ptr(R.in[q].term);
+            U.in_rank[q] = c->terms[R.in[q].term].rank;
+            for (int ax = 0; ax < 3; ++ax) U.off[q][ax] = R.in[q].off[ax];
+        }
+        for (size_t q = 0; q < R.out.size(); ++q) U.out[q] = B.wptr(R.out[q]);
+        U.out_rank = c->terms[R.out[0]].rank;
+        for (size_t q = 0; q < R.param.size() && q < hfav::UF_MAX_PARAM; ++q) U.param[q] = R.param[q];
+        U.nx = d[0]; U.ny = d[1]; U.nz = d[2];
+        for (int ax = 0; ax < 3; ++ax) U.bc[ax] = p.opts.boundary[ax];
+        U.dtype = c->dtype;
+        U.precision = p.opts.precision;
+        if (R.op == HFAV_OP_EULER_SMAX) {
+            int rc = dev_err(hfav::launch_fill_scalar((double *)U.out[0], 0.0, s), "reduction init");
+            if (rc) return rc;
+        }
+        int rc = dev_err(hfav::launch_unfused_rule(U, s), "rule kernel launch");
+        if (rc) return rc;
+    }
+    return HFAV_OK;
+}
+
+}  // namespace
+
+extern "C" int hfav_execute(hfav_chain *c, const void *const *axioms, void *const *goals, void *workspace,
+                            void *stream) {
+    if (!c) return hfav_fail(HFAV_EINVAL, "null chain");
+    if (!c->plan.valid) return hfav_fail(HFAV_ENOPLAN, "hfav_execute before a successful hfav_plan");
+    if (!axioms || !goals) return hfav_fail(HFAV_EINVAL, "null axiom or goal array");
+    for (size_t q = 0; q < c->axioms.size(); ++q)
+        if (!axioms[q]) return hfav_fail(HFAV_EINVAL, "null axiom pointer " + std::to_string(q));
+    for (size_t q = 0; q < c->goals.size(); ++q)
+        if (!goals[q]) return hfav_fail(HFAV_EINVAL, "null goal pointer " + std::to_string(q));
+    if (c->plan.ws_bytes > 0 && !workspace)
+        return hfav_fail(HFAV_ENOPLAN, "this plan needs a workspace of " + std::to_string(c->plan.ws_bytes) + " bytes");
+    for (size_t g = 0; g < c->goals.size(); ++g) {
+        const size_t ng = term_bytes(c, c->goals[g]);
+        for (size_t a = 0; a < c->axioms.size(); ++a)
+            if (overlap(goals[g], ng, axioms[a], term_bytes(c, c->axioms[a])))
+                return hfav_fail(HFAV_EALIAS, "goal " + c->terms[c->goals[g]].name + " overlaps axiom " +
+                                                  c->terms[c->axioms[a]].name);
+        for (size_t h = g + 1; h < c->goals.size(); ++h)
+            if (overlap(goals[g], ng, goals[h], term_bytes(c, c->goals[h])))
+                return hfav_fail(HFAV_EALIAS, "goals " + c->terms[c->goals[g]].name + " and " +
+                                                  c->terms[c->goals[h]].name + " overlap");
+    }
+    Bind B{c, axioms, goals, (char *)workspace};
+    hipStream_t s = (hipStream_t)stream;
+    try {
+        return c->plan.info.fused ? run_fused(c, B, s) : run_unfused(c, B, s);
+    } catch (...) {
+        return hfav_fail(HFAV_EINVAL, "host exception while executing");
+    }
+}

@@ -1,0 +1,105 @@
+// Host-side representation of a chain and its plan.
+#pragma once
+#include <array>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hfav.h"
+
+struct HRef {
+    int term;
+    int off[3];
+};
+
+struct HRule {
+    int op;
+    std::vector<HRef> in;
+    std::vector<int> out;        // term ids
+    std::vector<double> param;
+    int reduce;
+    int rank;                    // iteration-space rank: 0 (scalar rule) or ndim
+};
+
+enum { TK_AXIOM = 0, TK_INTER = 1, TK_GOAL = 2 };
+
+struct HTerm {
+    std::string name;
+    int kind;                    // TK_*
+    int rank;
+    int producer;                // rule index, -1 for axioms
+    int axiom_slot;              // position in the axiom list, -1
+    int goal_slot;               // position in the goal list, -1
+    int out_pos;                 // output position within its producer
+};
+
+// An iteration nest with its three phases (Design, "Iteration nests").
+// Perfect nests have only a steady state.
+struct HNest {
+    int rank;                    // 0 for a scalar nest
+    std::vector<int> prologue, steady, epilogue;   // rule indices
+};
+
+struct HTermPlan {
+    int lo[3], hi[3];            // Minkowski extent
+    bool has_ext;
+    int storage;
+    int window_axis;
+    int window;
+};
+
+struct HPlan {
+    bool valid = false;
+    hfav_plan_opts opts{};
+    hfav_plan_info info{};
+    std::vector<HNest> nests;
+    std::vector<HTermPlan> terms;
+    int family = HFAV_FAMILY_NONE;
+    // family bindings: term ids in the family's canonical argument order
+    std::vector<int> fam_in, fam_out;
+    int fam_dt_term = -1;        // 0-D term feeding dt (axiom), -1
+    int fam_dt_mode = 0;         // 0: term is dt, 1: term is smax (dt = cfl/smax)
+    double fam_cfl = 0.0;
+    int fam_smax_goal = -1;      // 0-D goal of a fused reduction, -1
+    std::vector<double> fam_param;
+    // unfused: workspace offset per term (-1 = not in workspace)
+    std::vector<int64_t> ws_off;
+    size_t ws_bytes = 0;
+    std::vector<int> exec_order; // rule order for the unfused path
+    std::string json;
+};
+
+struct hfav_chain {
+    int ndim = 2;
+    int order[3] = {2, 1, 0};    // axis ids outermost first (0 = i, 1 = j, 2 = k)
+    int dtype = HFAV_F64;
+    std::vector<HTerm> terms;
+    std::vector<HRule> rules;    // descriptor order
+    std::vector<bool> live;      // rule needed for some goal
+    std::vector<int> topo;       // topological order of live rules
+    std::vector<int> axioms, goals;  // term ids in declaration order
+    HPlan plan;
+};
+
+// error reporting (thread-local text)
+int hfav_fail(int code, const std::string &msg);
+
+// planner entry (plan.cpp)
+int hfav_plan_impl(hfav_chain *c, const hfav_plan_opts *o, hfav_plan_info *info);
+
+// op table (chain.cpp)
+struct OpSpec {
+    int op;
+    const char *name;
+    int n_in;          // -1 = any (>= 1)
+    int n_out;
+    int n_param;       // minimum number of params
+    int scalar_in;     // index of a 0-D input, -1 none
+    int out_rank0;     // 1 if the output is 0-D
+};
+const OpSpec *op_spec(int op);
+
+// tuning hooks (tune.cpp)
+bool hfav_tuned_config(int family, int dtype, const int dims[3], hfav_config *cfg);
+bool hfav_model_config(const hfav_chain *c, int family, const int dims[3], hfav_config *cfg);
+hfav_config hfav_default_config(int family, int dtype, const int dims[3]);

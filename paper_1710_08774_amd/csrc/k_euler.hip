@@ -1,0 +1,334 @@
+// Fused directionally split Godunov sweeps for gfx950 (Performance,
+// "Hydro2D": constoprim + equation_of_state, slope, trace, qleftright,
+// riemann, cmpflx and update_cons_vars fused into one iteration nest per
+// pass, all intermediates contracted to rolling windows; Design,
+// "Contraction").
+//
+// x pass (dependencies along the contiguous axis): one workgroup walks a row
+// in chunks of B cells, one lane per cell.  The contracted windows along i
+// (primitive state 3 cells, plus-face state 2 cells, flux 2 interfaces) are
+// LDS rings of 2B entries, so every value is produced once and read by its
+// neighbour lanes: no halo recomputation except two cells per row.  Each
+// lane solves exactly one Riemann problem per chunk.
+//
+// y pass (dependencies along the strided axis): one lane per column, lanes
+// along i give coalesced row loads, and each lane streams down a segment of
+// rows keeping the windows in registers (the "outer" rotation).  A segment
+// recomputes two halo cells and one interface at its top.  The CFL
+// reduction of the updated state is fused into this pass (wave reduction,
+// then one atomic max per workgroup).
+#include <hip/hip_runtime.h>
+#include "kernels.h"
+#include "ops.h"
+
+namespace hfav {
+
+template <class T>
+struct EArgs {
+    const T *rho, *mn, *mt, *E;
+    T *orho, *omn, *omt, *oE;
+    int nx, ny, bc;
+    double g;
+    int niter;
+    const double *dt_src;
+    int dt_mode;
+    double cfl;
+    double *smax_out;
+    int seg;
+};
+
+__device__ __forceinline__ int bwrap(int i, int n, int bc) {
+    if (bc == HFAV_BC_PERIODIC) {
+        i %= n;
+        return i < 0 ? i + n : i;
+    }
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+__device__ __forceinline__ double read_dt(const double *src, int mode, double cfl) {
+    double v = *src;
+    return mode == DT_VALUE ? v : cfl / v;
+}
+
+// Slopes and trace for one cell from its primitive window (m-1, m, m+1).
+template <class T>
+__device__ __forceinline__ void slope_trace(const Prim<T> &wm, const Prim<T> &w0, const Prim<T> &wp,
+                                            T nu, T *plus, T *minus) {
+    T dr = vanleer(wm.r, w0.r, wp.r);
+    T du = vanleer(wm.un, w0.un, wp.un);
+    T dv = vanleer(wm.ut, w0.ut, wp.ut);
+    T dp = vanleer(wm.p, w0.p, wp.p);
+    euler_trace(w0, dr, du, dv, dp, nu, plus, minus);
+}
+
+// ------------------------------------------------------------------ x pass
+template <class T, class A, bool G14, int B>
+__global__ __launch_bounds__(B) void euler_x_kernel(EArgs<T> a) {
+    constexpr int R = 2 * B, M = R - 1;
+    __shared__ T s_w[5][R];     // primitive window ring (r, un, ut, p, c)
+    __shared__ T s_f[4][R];     // plus-face ring
+    __shared__ T s_F[4][R];     // interface flux ring: slot p holds F(p-1/2)
+    __shared__ T s_F0[4];       // F(-1/2) for the periodic wrap
+    __shared__ T s_Fn[4];       // F(nx-1/2) for a transmissive right end
+
+    const int nx = a.nx;
+    const int t = threadIdx.x;
+    const size_t row = (size_t)blockIdx.x * nx;
+    const T g = (T)a.g;
+    const double dt = read_dt(a.dt_src, a.dt_mode, a.cfl);
+    const T nu = (T)dt;
+    const A nuA = (A)dt;
+
+    auto put_prim = [&](int cell) {
+        const int q = bwrap(cell, nx, a.bc);
+        const size_t o = row + q;
+        Prim<T> w = euler_prim(a.rho[o], a.mn[o], a.mt[o], a.E[o], g);
+        const int sl = cell & M;
+        s_w[0][sl] = w.r; s_w[1][sl] = w.un; s_w[2][sl] = w.ut; s_w[3][sl] = w.p; s_w[4][sl] = w.c;
+    };
+    auto get_prim = [&](int cell) {
+        const int sl = cell & M;
+        Prim<T> w;
+        w.r = s_w[0][sl]; w.un = s_w[1][sl]; w.ut = s_w[2][sl]; w.p = s_w[3][sl]; w.c = s_w[4][sl];
+        return w;
+    };
+
+    // prologue: cells -2, -1, 0 and the plus face of cell -1
+    if (t < 3) put_prim(t - 2);
+    __syncthreads();
+    if (t == 0) {
+        T plus[4], minus[4];
+        slope_trace(get_prim(-2), get_prim(-1), get_prim(0), nu, plus, minus);
+        const int sl = (-1) & M;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s_f[q][sl] = plus[q];
+    }
+    __syncthreads();
+
+    for (int c0 = 0; c0 < nx; c0 += B) {
+        const int p = c0 + t;
+        const bool act = p < nx;
+        // stage 1: primitive state of the cell entering the window
+        if (act) put_prim(p + 1);
+        __syncthreads();
+        // stage 2: slopes + trace of cell p; the plus face goes to its right
+        // neighbour through LDS, the minus face stays in registers
+        T minus[4];
+        if (act) {
+            T plus[4];
+            slope_trace(get_prim(p - 1), get_prim(p), get_prim(p + 1), nu, plus, minus);
+            const int sl = p & M;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) s_f[q][sl] = plus[q];
+        }
+        __syncthreads();
+        // stage 3: Riemann problem and flux at interface p-1/2
+        if (act) {
+            T L[4], G[4], F[4];
+            const int sl = (p - 1) & M;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) L[q] = s_f[q][sl];
+            riemann_T<T, G14>(L, minus, g, a.niter, G);
+            euler_flux(G, g, F);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) s_F[q][p & M] = F[q];
+            if (p == 0) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) s_F0[q] = F[q];
+            }
+            if (a.bc != HFAV_BC_PERIODIC && p == nx - 1) {
+                // right ghost cell copies cell nx-1 and has zero slopes, so
+                // its minus face is the primitive state of cell nx-1
+                T Lr[4], Rr[4], Gr[4];
+                const int sp = p & M;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) Lr[q] = s_f[q][sp];
+                Rr[0] = s_w[0][sp]; Rr[1] = s_w[1][sp]; Rr[2] = s_w[2][sp]; Rr[3] = s_w[3][sp];
+                riemann_T<T, G14>(Lr, Rr, g, a.niter, Gr);
+                euler_flux(Gr, g, s_Fn);
+            }
+        }
+        __syncthreads();
+        // stage 4: conservative update of cell p-1 (and of cell nx-1 at the end)
+        if (act && p >= 1) {
+            const size_t o = row + (p - 1);
+            const int s1 = (p - 1) & M, s2 = p & M;
+            a.orho[o] = euler_update(a.rho[o], s_F[0][s2], s_F[0][s1], nuA);
+            a.omn[o] = euler_update(a.mn[o], s_F[1][s2], s_F[1][s1], nuA);
+            a.omt[o] = euler_update(a.mt[o], s_F[2][s2], s_F[2][s1], nuA);
+            a.oE[o] = euler_update(a.E[o], s_F[3][s2], s_F[3][s1], nuA);
+        }
+        if (act && p == nx - 1) {
+            const size_t o = row + p;
+            const int s1 = p & M;
+            const T *Fp = a.bc == HFAV_BC_PERIODIC ? s_F0 : s_Fn;
+            a.orho[o] = euler_update(a.rho[o], Fp[0], s_F[0][s1], nuA);
+            a.omn[o] = euler_update(a.mn[o], Fp[1], s_F[1][s1], nuA);
+            a.omt[o] = euler_update(a.mt[o], Fp[2], s_F[2][s1], nuA);
+            a.oE[o] = euler_update(a.E[o], Fp[3], s_F[3][s1], nuA);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ y pass
+template <int B>
+__device__ __forceinline__ void block_max_to(double v, double *out) {
+    __shared__ double red[B / 64];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red[0];
+#pragma unroll
+        for (int q = 1; q < B / 64; ++q) m = fmax(m, red[q]);
+        atomic_max_nonneg(out, m);
+    }
+}
+
+template <class T, class A, bool G14, int B>
+__global__ __launch_bounds__(B) void euler_y_kernel(EArgs<T> a) {
+    const int nx = a.nx, ny = a.ny;
+    const int i = blockIdx.x * B + threadIdx.x;
+    const int j0 = blockIdx.y * a.seg;
+    const int j1 = min(j0 + a.seg, ny);
+    const T g = (T)a.g;
+    const double dt = read_dt(a.dt_src, a.dt_mode, a.cfl);
+    const T nu = (T)dt;
+    const A nuA = (A)dt;
+    double smax = 0.0;
+    if (i < nx) {
+        auto P = [&](int jj) {
+            const size_t o = (size_t)bwrap(jj, ny, a.bc) * nx + i;
+            return euler_prim(a.rho[o], a.mn[o], a.mt[o], a.E[o], g);
+        };
+        Prim<T> w0 = P(j0 - 2), w1 = P(j0 - 1), w2 = P(j0);
+        T fp[4], Fm[4];
+        {
+            T minus[4];
+            slope_trace(w0, w1, w2, nu, fp, minus);     // plus face of cell j0-1
+        }
+        // window: w1 = cell j-1, w2 = cell j
+        for (int j = j0; j <= j1; ++j) {
+            const Prim<T> w3 = P(j + 1);
+            T plus[4], minus[4], G[4], F[4];
+            slope_trace(w1, w2, w3, nu, plus, minus);
+            riemann_T<T, G14>(fp, minus, g, a.niter, G);
+            euler_flux(G, g, F);                         // flux at j-1/2
+            if (j > j0) {
+                const size_t o = (size_t)(j - 1) * nx + i;
+                const T r = euler_update(a.rho[o], F[0], Fm[0], nuA);
+                const T mn = euler_update(a.mn[o], F[1], Fm[1], nuA);
+                const T mt = euler_update(a.mt[o], F[2], Fm[2], nuA);
+                const T e = euler_update(a.E[o], F[3], Fm[3], nuA);
+                a.orho[o] = r; a.omn[o] = mn; a.omt[o] = mt; a.oE[o] = e;
+                if (a.smax_out) smax = fmax(smax, (double)euler_speed(r, mt, mn, e, g));
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) { Fm[q] = F[q]; fp[q] = plus[q]; }
+            w1 = w2;
+            w2 = w3;
+        }
+    }
+    if (a.smax_out) block_max_to<B>(smax, a.smax_out);
+}
+
+// ------------------------------------------------------------------ smax
+template <class T, int B>
+__global__ __launch_bounds__(B) void euler_smax_kernel(const T *rho, const T *mx, const T *my,
+                                                       const T *E, int n, double g, double *out) {
+    double m = 0.0;
+    for (int q = blockIdx.x * B + threadIdx.x; q < n; q += gridDim.x * B)
+        m = fmax(m, (double)euler_speed(rho[q], mx[q], my[q], E[q], (T)g));
+    block_max_to<B>(m, out);
+}
+
+__global__ void fill_scalar_kernel(double *p, double v) { *p = v; }
+__global__ void dt_from_smax_kernel(const double *smax, double cfl, double *out) { *out = cfl / *smax; }
+
+// ------------------------------------------------------------------ launchers
+template <class T>
+static EArgs<T> make_args(const EulerLaunch &L) {
+    EArgs<T> a;
+    a.rho = (const T *)L.in[0]; a.mn = (const T *)L.in[1]; a.mt = (const T *)L.in[2]; a.E = (const T *)L.in[3];
+    a.orho = (T *)L.out[0]; a.omn = (T *)L.out[1]; a.omt = (T *)L.out[2]; a.oE = (T *)L.out[3];
+    a.nx = L.nx; a.ny = L.ny; a.bc = L.bc;
+    a.g = L.gamma; a.niter = L.niter;
+    a.dt_src = L.dt_src; a.dt_mode = L.dt_mode; a.cfl = L.cfl;
+    a.smax_out = L.smax_out;
+    a.seg = L.cfg.seg > 0 ? L.cfg.seg : 16;
+    return a;
+}
+
+template <class T, class A, bool G14>
+static hipError_t euler_x_dispatch(const EulerLaunch &L, hipStream_t s) {
+    EArgs<T> a = make_args<T>(L);
+    dim3 grid(L.ny);
+    switch (L.cfg.block) {
+    case 64: hipLaunchKernelGGL((euler_x_kernel<T, A, G14, 64>), grid, dim3(64), 0, s, a); break;
+    case 128: hipLaunchKernelGGL((euler_x_kernel<T, A, G14, 128>), grid, dim3(128), 0, s, a); break;
+    default: hipLaunchKernelGGL((euler_x_kernel<T, A, G14, 256>), grid, dim3(256), 0, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+template <class T, class A, bool G14>
+static hipError_t euler_y_dispatch(const EulerLaunch &L, hipStream_t s) {
+    EArgs<T> a = make_args<T>(L);
+    const int B = (L.cfg.block == 64 || L.cfg.block == 128 || L.cfg.block == 256) ? L.cfg.block : 64;
+    dim3 grid((L.nx + B - 1) / B, (L.ny + a.seg - 1) / a.seg);
+    switch (B) {
+    case 128: hipLaunchKernelGGL((euler_y_kernel<T, A, G14, 128>), grid, dim3(128), 0, s, a); break;
+    case 256: hipLaunchKernelGGL((euler_y_kernel<T, A, G14, 256>), grid, dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL((euler_y_kernel<T, A, G14, 64>), grid, dim3(64), 0, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+template <bool X>
+static hipError_t euler_dispatch(const EulerLaunch &L, hipStream_t s) {
+    const bool g14 = L.gamma == 1.4;
+    if (L.dtype == HFAV_F64) {
+        if (g14) return X ? euler_x_dispatch<double, double, true>(L, s) : euler_y_dispatch<double, double, true>(L, s);
+        return X ? euler_x_dispatch<double, double, false>(L, s) : euler_y_dispatch<double, double, false>(L, s);
+    }
+    if (L.precision == HFAV_PREC_F32_F64ACC) {
+        if (g14) return X ? euler_x_dispatch<float, double, true>(L, s) : euler_y_dispatch<float, double, true>(L, s);
+        return X ? euler_x_dispatch<float, double, false>(L, s) : euler_y_dispatch<float, double, false>(L, s);
+    }
+    if (g14) return X ? euler_x_dispatch<float, float, true>(L, s) : euler_y_dispatch<float, float, true>(L, s);
+    return X ? euler_x_dispatch<float, float, false>(L, s) : euler_y_dispatch<float, float, false>(L, s);
+}
+
+hipError_t launch_euler_x(const EulerLaunch &L, hipStream_t s) { return euler_dispatch<true>(L, s); }
+hipError_t launch_euler_y(const EulerLaunch &L, hipStream_t s) { return euler_dispatch<false>(L, s); }
+
+hipError_t launch_euler_smax(const void *const *U, int n, double gamma, double *out, int dtype,
+                             hipStream_t s) {
+    const int B = 256;
+    int nb = (n + B - 1) / B;
+    if (nb > 4096) nb = 4096;
+    if (nb < 1) nb = 1;
+    if (dtype == HFAV_F64)
+        hipLaunchKernelGGL((euler_smax_kernel<double, B>), dim3(nb), dim3(B), 0, s,
+                           (const double *)U[0], (const double *)U[1], (const double *)U[2],
+                           (const double *)U[3], n, gamma, out);
+    else
+        hipLaunchKernelGGL((euler_smax_kernel<float, B>), dim3(nb), dim3(B), 0, s,
+                           (const float *)U[0], (const float *)U[1], (const float *)U[2],
+                           (const float *)U[3], n, gamma, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_scalar(double *p, double v, hipStream_t s) {
+    hipLaunchKernelGGL(fill_scalar_kernel, dim3(1), dim3(1), 0, s, p, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_dt_from_smax(const double *smax, double cfl, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(dt_from_smax_kernel, dim3(1), dim3(1), 0, s, smax, cfl, out);
+    return hipGetLastError();
+}
+
+}  // namespace hfav

@@ -1,0 +1,222 @@
+// Unfused execution: one kernel per rule over the full iteration space,
+// every intermediate a full array in HBM (the starting point the paper
+// transforms: Design, "Dataflow"; the "autovec" baselines of the Performance
+// section).  Each kernel evaluates the same device rule body as the fused
+// families, one lane per cell, reading every input reference at its offset
+// with the boundary applied as index arithmetic.
+#include <hip/hip_runtime.h>
+#include "kernels.h"
+#include "ops.h"
+
+namespace hfav {
+
+struct UArgs {
+    const void *in[UF_MAX_IN];
+    int off[UF_MAX_IN][3];
+    void *out[UF_MAX_OUT];
+    double param[UF_MAX_PARAM];
+    int nx, ny, nz;
+    int bc[3];
+};
+
+__device__ __forceinline__ int uwrap(int i, int n, int bc) {
+    if (bc == HFAV_BC_PERIODIC) {
+        i %= n;
+        return i < 0 ? i + n : i;
+    }
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+template <class T>
+__device__ __forceinline__ T ld(const UArgs &a, int r, int i, int j, int k) {
+    const int ii = uwrap(i + a.off[r][0], a.nx, a.bc[0]);
+    const int jj = uwrap(j + a.off[r][1], a.ny, a.bc[1]);
+    const int kk = uwrap(k + a.off[r][2], a.nz, a.bc[2]);
+    return ((const T *)a.in[r])[((size_t)kk * a.ny + jj) * a.nx + ii];
+}
+__device__ __forceinline__ double lds0(const UArgs &a, int r) { return *(const double *)a.in[r]; }
+
+template <class T>
+__device__ __forceinline__ void st(const UArgs &a, int o, size_t idx, T v) { ((T *)a.out[o])[idx] = v; }
+
+template <int OP, class T, class A, bool G14>
+__global__ __launch_bounds__(256) void rule_kernel(UArgs a) {
+    const size_t n = (size_t)a.nx * a.ny * a.nz;
+    const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= n) return;
+    const int i = (int)(idx % a.nx);
+    const int j = (int)((idx / a.nx) % a.ny);
+    const int k = (int)(idx / ((size_t)a.nx * a.ny));
+#define IN(r) ld<T>(a, r, i, j, k)
+    if constexpr (OP == HFAV_OP_HDIFF_LAP) {
+        st<T>(a, 0, idx, hdiff_lap(IN(0), IN(1), IN(2), IN(3), IN(4)));
+    } else if constexpr (OP == HFAV_OP_HDIFF_FLX || OP == HFAV_OP_HDIFF_FLY) {
+        st<T>(a, 0, idx, hdiff_flux(IN(0), IN(1), IN(2), IN(3)));
+    } else if constexpr (OP == HFAV_OP_HDIFF_OUT) {
+        st<T>(a, 0, idx, hdiff_out(IN(0), IN(1), IN(2), IN(3), IN(4), (T)a.param[0]));
+    } else if constexpr (OP == HFAV_OP_EULER_PRIM) {
+        Prim<T> w = euler_prim(IN(0), IN(1), IN(2), IN(3), (T)a.param[0]);
+        st<T>(a, 0, idx, w.r); st<T>(a, 1, idx, w.un); st<T>(a, 2, idx, w.ut);
+        st<T>(a, 3, idx, w.p); st<T>(a, 4, idx, w.c);
+    } else if constexpr (OP == HFAV_OP_EULER_SLOPE) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) st<T>(a, q, idx, vanleer(IN(3 * q), IN(3 * q + 1), IN(3 * q + 2)));
+    } else if constexpr (OP == HFAV_OP_EULER_TRACE) {
+        Prim<T> w;
+        w.r = IN(0); w.un = IN(1); w.ut = IN(2); w.p = IN(3); w.c = IN(4);
+        T plus[4], minus[4];
+        euler_trace(w, IN(5), IN(6), IN(7), IN(8), (T)lds0(a, 9), plus, minus);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) { st<T>(a, q, idx, plus[q]); st<T>(a, 4 + q, idx, minus[q]); }
+    } else if constexpr (OP == HFAV_OP_EULER_RIEMANN) {
+        T L[4] = {IN(0), IN(1), IN(2), IN(3)};
+        T R[4] = {IN(4), IN(5), IN(6), IN(7)};
+        T G[4];
+        riemann_T<T, G14>(L, R, (T)a.param[0], (int)a.param[1], G);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) st<T>(a, q, idx, G[q]);
+    } else if constexpr (OP == HFAV_OP_EULER_FLUX) {
+        T G[4] = {IN(0), IN(1), IN(2), IN(3)};
+        T F[4];
+        euler_flux(G, (T)a.param[0], F);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) st<T>(a, q, idx, F[q]);
+    } else if constexpr (OP == HFAV_OP_EULER_UPDATE) {
+        const A nu = (A)lds0(a, 12);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) st<T>(a, q, idx, euler_update(IN(q), IN(4 + q), IN(8 + q), nu));
+    } else if constexpr (OP == HFAV_OP_LAP7) {
+        st<T>(a, 0, idx, lap7(IN(0), IN(1), IN(2), IN(3), IN(4), IN(5), IN(6)));
+    } else if constexpr (OP == HFAV_OP_AXPY) {
+        st<T>(a, 0, idx, axpy(IN(0), IN(1), (T)a.param[0]));
+    }
+#undef IN
+}
+
+// reduction rule: accumulate max(|u|+c, |v|+c) into a 0-D term
+template <class T>
+__global__ __launch_bounds__(256) void rule_smax_kernel(UArgs a) {
+    __shared__ double red[4];
+    const size_t n = (size_t)a.nx * a.ny * a.nz;
+    double m = 0.0;
+    for (size_t q = (size_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (size_t)gridDim.x * 256)
+        m = fmax(m, (double)euler_speed(((const T *)a.in[0])[q], ((const T *)a.in[1])[q],
+                                        ((const T *)a.in[2])[q], ((const T *)a.in[3])[q],
+                                        (T)a.param[0]));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) atomic_max_nonneg((double *)a.out[0], fmax(fmax(red[0], red[1]), fmax(red[2], red[3])));
+}
+
+__global__ void rule_dt_kernel(UArgs a) {
+    *(double *)a.out[0] = a.param[0] / *(const double *)a.in[0];
+}
+
+template <int OP, class T, class A, bool G14>
+static void launch_op(const UArgs &a, size_t n, hipStream_t s) {
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL((rule_kernel<OP, T, A, G14>), dim3(nb), dim3(256), 0, s, a);
+}
+
+template <class T, class A, bool G14>
+static hipError_t dispatch_rule(const UnfusedRule &R, const UArgs &a, hipStream_t s) {
+    const size_t n = (size_t)R.nx * R.ny * R.nz;
+    switch (R.op) {
+    case HFAV_OP_HDIFF_LAP: launch_op<HFAV_OP_HDIFF_LAP, T, A, G14>(a, n, s); break;
+    case HFAV_OP_HDIFF_FLX: launch_op<HFAV_OP_HDIFF_FLX, T, A, G14>(a, n, s); break;
+    case HFAV_OP_HDIFF_FLY: launch_op<HFAV_OP_HDIFF_FLY, T, A, G14>(a, n, s); break;
+    case HFAV_OP_HDIFF_OUT: launch_op<HFAV_OP_HDIFF_OUT, T, A, G14>(a, n, s); break;
+    case HFAV_OP_EULER_PRIM: launch_op<HFAV_OP_EULER_PRIM, T, A, G14>(a, n, s); break;
+    case HFAV_OP_EULER_SLOPE: launch_op<HFAV_OP_EULER_SLOPE, T, A, G14>(a, n, s); break;
+    case HFAV_OP_EULER_TRACE: launch_op<HFAV_OP_EULER_TRACE, T, A, G14>(a, n, s); break;
+    case HFAV_OP_EULER_RIEMANN: launch_op<HFAV_OP_EULER_RIEMANN, T, A, G14>(a, n, s); break;
+    case HFAV_OP_EULER_FLUX: launch_op<HFAV_OP_EULER_FLUX, T, A, G14>(a, n, s); break;
+    case HFAV_OP_EULER_UPDATE: launch_op<HFAV_OP_EULER_UPDATE, T, A, G14>(a, n, s); break;
+    case HFAV_OP_LAP7: launch_op<HFAV_OP_LAP7, T, A, G14>(a, n, s); break;
+    case HFAV_OP_AXPY: launch_op<HFAV_OP_AXPY, T, A, G14>(a, n, s); break;
+    case HFAV_OP_EULER_SMAX: {
+        unsigned nb = (unsigned)((n + 255) / 256);
+        if (nb > 4096) nb = 4096;
+        hipLaunchKernelGGL((rule_smax_kernel<T>), dim3(nb), dim3(256), 0, s, a);
+        break;
+    }
+    case HFAV_OP_EULER_DT:
+        hipLaunchKernelGGL(rule_dt_kernel, dim3(1), dim3(1), 0, s, a);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_unfused_rule(const UnfusedRule &R, hipStream_t s) {
+    UArgs a;
+    for (int r = 0; r < UF_MAX_IN; ++r) {
+        a.in[r] = r < R.n_in ? R.in[r] : nullptr;
+        for (int d = 0; d < 3; ++d) a.off[r][d] = r < R.n_in ? R.off[r][d] : 0;
+    }
+    for (int o = 0; o < UF_MAX_OUT; ++o) a.out[o] = o < R.n_out ? R.out[o] : nullptr;
+    for (int q = 0; q < UF_MAX_PARAM; ++q) a.param[q] = R.param[q];
+    a.nx = R.nx; a.ny = R.ny; a.nz = R.nz;
+    for (int d = 0; d < 3; ++d) a.bc[d] = R.bc[d];
+    double g = R.param[0];
+    const bool g14 = (R.op == HFAV_OP_EULER_RIEMANN) && g == 1.4;
+    if (R.dtype == HFAV_F64)
+        return g14 ? dispatch_rule<double, double, true>(R, a, s) : dispatch_rule<double, double, false>(R, a, s);
+    if (R.precision == HFAV_PREC_F32_F64ACC)
+        return g14 ? dispatch_rule<float, double, true>(R, a, s) : dispatch_rule<float, double, false>(R, a, s);
+    return g14 ? dispatch_rule<float, float, true>(R, a, s) : dispatch_rule<float, float, false>(R, a, s);
+}
+
+// ------------------------------------------------------------------ STAR
+enum { STAR_MAX = 96 };
+struct SArgs {
+    const void *in[STAR_MAX];
+    int off[STAR_MAX][3];
+    double coeff[STAR_MAX];
+    int n_in;
+    void *out;
+    int nx, ny, nz;
+    int bc[3];
+};
+
+template <class T>
+__global__ __launch_bounds__(256) void star_rule_kernel(SArgs a) {
+    const size_t n = (size_t)a.nx * a.ny * a.nz;
+    const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= n) return;
+    const int i = (int)(idx % a.nx);
+    const int j = (int)((idx / a.nx) % a.ny);
+    const int k = (int)(idx / ((size_t)a.nx * a.ny));
+    T acc = T(0);
+    for (int r = 0; r < a.n_in; ++r) {
+        const int ii = uwrap(i + a.off[r][0], a.nx, a.bc[0]);
+        const int jj = uwrap(j + a.off[r][1], a.ny, a.bc[1]);
+        const int kk = uwrap(k + a.off[r][2], a.nz, a.bc[2]);
+        acc += (T)a.coeff[r] * ((const T *)a.in[r])[((size_t)kk * a.ny + jj) * a.nx + ii];
+    }
+    ((T *)a.out)[idx] = acc;
+}
+
+hipError_t launch_star_rule(const StarRule &R, hipStream_t s) {
+    if (R.n_in < 1 || R.n_in > STAR_MAX) return hipErrorInvalidValue;
+    SArgs a;
+    a.n_in = R.n_in;
+    for (int r = 0; r < STAR_MAX; ++r) {
+        a.in[r] = r < R.n_in ? R.in[r] : nullptr;
+        for (int d = 0; d < 3; ++d) a.off[r][d] = r < R.n_in ? R.off[3 * r + d] : 0;
+        a.coeff[r] = r < R.n_in ? R.coeff[r] : 0.0;
+    }
+    a.out = R.out;
+    a.nx = R.nx; a.ny = R.ny; a.nz = R.nz;
+    for (int d = 0; d < 3; ++d) a.bc[d] = R.bc[d];
+    const size_t n = (size_t)R.nx * R.ny * R.nz;
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    if (R.dtype == HFAV_F64) hipLaunchKernelGGL((star_rule_kernel<double>), dim3(nb), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((star_rule_kernel<float>), dim3(nb), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace hfav

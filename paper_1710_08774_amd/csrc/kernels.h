@@ -1,0 +1,93 @@
+// Launch interface between the host planner/dispatcher and the HIP kernels.
+// Host-only declarations; every launcher enqueues on the given stream and
+// returns the HIP error of the launch.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include "../../include/hfav.h"
+
+namespace hfav {
+
+enum { DT_VALUE = 0, DT_FROM_SMAX = 1 };
+
+// One directional Godunov sweep, fused.  Pointers are in the sweep frame:
+// in[0..3] = (rho, normal momentum, transverse momentum, E).
+struct EulerLaunch {
+    const void *in[4];
+    void *out[4];
+    int nx, ny;            // grid (the sweep runs along x for EULER_X, y for EULER_Y)
+    int bc;                // hfav_bc along the sweep axis
+    double gamma;
+    int niter;
+    const double *dt_src;  // dt itself, or smax when dt_mode = DT_FROM_SMAX
+    int dt_mode;
+    double cfl;
+    double *smax_out;      // nullable: fused max(|u|+c,|v|+c) of the updated state
+    int dtype;             // hfav_dtype
+    int precision;         // hfav_precision
+    hfav_config cfg;
+};
+hipError_t launch_euler_x(const EulerLaunch &L, hipStream_t s);
+hipError_t launch_euler_y(const EulerLaunch &L, hipStream_t s);
+
+// smax = max over cells of max(|u|+c, |v|+c); *out must hold 0 beforehand.
+hipError_t launch_euler_smax(const void *const *U, int n, double gamma, double *out,
+                             int dtype, hipStream_t s);
+// *p = v for a 0-D term (a fill kernel rather than a memset, so that the
+// call can be captured in a graph)
+hipError_t launch_fill_scalar(double *p, double v, hipStream_t s);
+// *out = cfl / *smax
+hipError_t launch_dt_from_smax(const double *smax, double cfl, double *out, hipStream_t s);
+
+struct HdiffLaunch {
+    const void *in;
+    void *out;
+    int ni, nj, nk;
+    double coeff;
+    int dtype;
+    hfav_config cfg;
+};
+hipError_t launch_hdiff(const HdiffLaunch &L, hipStream_t s);
+
+struct Lap7ChainLaunch {
+    const void *in;
+    void *out;
+    int nx, ny, nz;
+    double alpha;          // out = u + alpha * lap7(lap7(u))
+    int dtype;
+    hfav_config cfg;
+};
+hipError_t launch_lap7_chain(const Lap7ChainLaunch &L, hipStream_t s);
+
+// ---- unfused path: one kernel per rule over full arrays
+enum { UF_MAX_IN = 24, UF_MAX_OUT = 8, UF_MAX_PARAM = 4 };
+struct UnfusedRule {
+    int op;
+    int n_in, n_out;
+    const void *in[UF_MAX_IN];        // grid inputs (rank > 0) or 0-D pointers
+    int off[UF_MAX_IN][3];
+    int in_rank[UF_MAX_IN];
+    void *out[UF_MAX_OUT];
+    int out_rank;                     // 0 for 0-D outputs
+    double param[UF_MAX_PARAM];
+    int nx, ny, nz;
+    int bc[3];
+    int dtype;
+    int precision;
+};
+hipError_t launch_unfused_rule(const UnfusedRule &R, hipStream_t s);
+
+// Generic linear star rule (any number of references), unfused.
+struct StarRule {
+    int n_in;
+    const void *const *in;   // host array of n_in device pointers
+    const int *off;          // host array (n_in, 3)
+    const double *coeff;     // host array n_in
+    void *out;
+    int nx, ny, nz;
+    int bc[3];
+    int dtype;
+};
+hipError_t launch_star_rule(const StarRule &R, hipStream_t s);
+
+}  // namespace hfav

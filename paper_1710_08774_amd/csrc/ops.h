@@ -1,0 +1,307 @@
+// Device-side rule bodies ("user kernels" in the paper's sense, Design
+// "Fundamentals": homogeneous, side-effect free, order agnostic).  The fused
+// kernel families and the unfused one-kernel-per-rule path call the same
+// functions, so the two paths evaluate identical arithmetic per cell.
+//
+// Template parameter T is the storage/arithmetic type (double or float).
+// In the F32_F64ACC precision the Riemann pressure iteration and the
+// conservative-update accumulation run in double whatever T is.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+namespace hfav {
+
+// ------------------------------------------------------------------ hdiff
+// COSMO horizontal diffusion (Performance, "COSMO Micro-Kernels").
+// These bandwidth-bound rules are evaluated without FMA contraction, in the
+// operation order written, so that a limiter decision never depends on
+// whether a multiply-add was fused.
+template <class T>
+__device__ __forceinline__ T hdiff_lap(T c, T e, T w, T n, T s) {
+#pragma clang fp contract(off)
+    return (e + w) + (n + s) - T(4) * c;
+}
+// forward difference of lap, zeroed when it points up the gradient of u
+template <class T>
+__device__ __forceinline__ T hdiff_flux(T l0, T l1, T u0, T u1) {
+#pragma clang fp contract(off)
+    T f = l1 - l0;
+    return (f * (u1 - u0) > T(0)) ? T(0) : f;
+}
+template <class T>
+__device__ __forceinline__ T hdiff_out(T u, T fx0, T fxm, T fy0, T fym, T coeff) {
+#pragma clang fp contract(off)
+    return u - coeff * ((fx0 - fxm) + (fy0 - fym));
+}
+
+// ------------------------------------------------------------------ lap7
+template <class T>
+__device__ __forceinline__ T lap7(T c, T e, T w, T n, T s, T t, T b) {
+#pragma clang fp contract(off)
+    return ((e + w) + (n + s)) + (t + b) - T(6) * c;
+}
+template <class T>
+__device__ __forceinline__ T axpy(T a, T b, T alpha) {
+#pragma clang fp contract(off)
+    return a + alpha * b;
+}
+
+// ------------------------------------------------------------------ euler
+// Primitive state of one cell: constoprim + equation_of_state.
+template <class T>
+struct Prim { T r, un, ut, p, c; };
+
+template <class T>
+__device__ __forceinline__ Prim<T> euler_prim(T rho, T mn, T mt, T E, T g) {
+    Prim<T> w;
+    w.r = rho;
+    w.un = mn / rho;
+    w.ut = mt / rho;
+    w.p = (g - T(1)) * (E - T(0.5) * rho * (w.un * w.un + w.ut * w.ut));
+    w.c = sqrt(g * w.p / rho);
+    return w;
+}
+
+// van Leer limited slope from the three cell values around m
+template <class T>
+__device__ __forceinline__ T vanleer(T wm, T w0, T wp) {
+    T a = w0 - wm, b = wp - w0;
+    return (a * b > T(0)) ? T(2) * a * b / (a + b) : T(0);
+}
+
+// Characteristic half-step trace to both faces.  A wave of speed >= 0
+// contributes to the plus face (m+1/2), a wave of speed <= 0 to the minus
+// face (m-1/2).  Outputs (rho, un, ut, p) for each face.
+template <class T>
+__device__ __forceinline__ void euler_trace(const Prim<T>& w, T dr, T du, T dv, T dp, T nu,
+                                            T* plus, T* minus) {
+    const T r = w.r, un = w.un, c = w.c;
+    const T ic2 = T(1) / (c * c);
+    const T lam0 = un - c, lam1 = un, lam3 = un + c;
+    const T a0 = T(0.5) * (dp * ic2 - r * du / c);
+    const T a1 = dr - dp * ic2;
+    const T a2 = dv;
+    const T a3 = T(0.5) * (dp * ic2 + r * du / c);
+    const T h = T(0.5);
+    T cp0 = lam0 >= T(0) ? h * (T(1) - nu * lam0) * a0 : T(0);
+    T cp1 = lam1 >= T(0) ? h * (T(1) - nu * lam1) * a1 : T(0);
+    T cp2 = lam1 >= T(0) ? h * (T(1) - nu * lam1) * a2 : T(0);
+    T cp3 = lam3 >= T(0) ? h * (T(1) - nu * lam3) * a3 : T(0);
+    T cm0 = lam0 <= T(0) ? h * (T(1) + nu * lam0) * a0 : T(0);
+    T cm1 = lam1 <= T(0) ? h * (T(1) + nu * lam1) * a1 : T(0);
+    T cm2 = lam1 <= T(0) ? h * (T(1) + nu * lam1) * a2 : T(0);
+    T cm3 = lam3 <= T(0) ? h * (T(1) + nu * lam3) * a3 : T(0);
+    const T cr = c / r, cc = c * c;
+    plus[0] = r + (cp0 + cp1 + cp3);
+    plus[1] = un + cr * (cp3 - cp0);
+    plus[2] = w.ut + cp2;
+    plus[3] = w.p + cc * (cp0 + cp3);
+    minus[0] = r - (cm0 + cm1 + cm3);
+    minus[1] = un - cr * (cm3 - cm0);
+    minus[2] = w.ut - cm2;
+    minus[3] = w.p - cc * (cm0 + cm3);
+}
+
+// x^(-1/7) for x > 0: a single-precision hardware log2/exp2 estimate
+// refined by two steps of the division-free Newton iteration for
+// w^-7 = x (w <- w + w(1 - x w^7)/7, quadratic convergence; the estimate's
+// 1e-7 relative error falls below double rounding after two steps).
+// Outside the single-precision normal range it defers to pow.
+__device__ __forceinline__ double rroot7(double x) {
+    if (!(x > 1e-30 && x < 1e30)) return pow(x, -1.0 / 7.0);
+    float l = __builtin_amdgcn_logf((float)x);            // log2
+    double w = (double)__builtin_amdgcn_exp2f(l * (-1.0f / 7.0f));
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        double w2 = w * w, w4 = w2 * w2, w7 = w4 * w2 * w;
+        double e = fma(-x, w7, 1.0);
+        w = fma(w * (1.0 / 7.0), e, w);
+    }
+    return w;
+}
+__device__ __forceinline__ float rroot7f(float x) {
+    if (!(x > 1e-30f && x < 1e30f)) return powf(x, -1.0f / 7.0f);
+    float w = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(x) * (-1.0f / 7.0f));
+    float w2 = w * w, w4 = w2 * w2, w7 = w4 * w2 * w;
+    return fmaf(w * (1.0f / 7.0f), fmaf(-x, w7, 1.0f), w);
+}
+
+// Pressure-function data of one side of the Riemann problem (Toro ch. 4).
+struct Side {
+    double r, u, p, c;
+    double ip;      // 1/p
+    double irc;     // 1/(rho c)
+    double sA;      // sqrt(A), A = 2/((g+1) rho)
+    double B;       // (g-1)/(g+1) p
+    double k2;      // 2c/(g-1)
+};
+
+template <bool G14>
+__device__ __forceinline__ Side make_side(double r, double u, double p, double g) {
+    Side s;
+    s.r = r; s.u = u; s.p = p;
+    s.c = sqrt(g * p / r);
+    s.ip = 1.0 / p;
+    s.irc = 1.0 / (r * s.c);
+    s.sA = sqrt(2.0 / ((g + 1.0) * r));
+    s.B = (g - 1.0) / (g + 1.0) * p;
+    s.k2 = 2.0 * s.c / (g - 1.0);
+    return s;
+}
+
+// f_K(p) and f_K'(p): shock branch for p > p_K, rarefaction otherwise.
+// For gamma = 7/5 the rarefaction exponents are 1/7 and -6/7, computed from
+// one reciprocal seventh root.
+template <bool G14>
+__device__ __forceinline__ void pres_fun(const Side& s, double p, double g, double& f, double& fd) {
+    if (p > s.p) {
+        double rs = rsqrt(p + s.B);           // 1/sqrt(p+B)
+        double q = s.sA * rs;
+        double dp = p - s.p;
+        f = dp * q;
+        fd = q * (1.0 - 0.5 * dp * (rs * rs));
+    } else {
+        double x = p * s.ip;
+        if (G14) {
+            double w = rroot7(x);
+            double w2 = w * w, w6 = w2 * w2 * w2;
+            f = s.k2 * (x * w6 - 1.0);
+            fd = s.irc * w6;
+        } else {
+            f = s.k2 * (pow(x, (g - 1.0) / (2.0 * g)) - 1.0);
+            fd = s.irc * pow(x, -(g + 1.0) / (2.0 * g));
+        }
+    }
+}
+
+// x^((g-1)/(2g)) and x^(1/g) for the sampling step.
+template <bool G14>
+__device__ __forceinline__ void pow_g1_ig(double x, double g, double& z, double& zig) {
+    if (G14) {
+        double w = rroot7(x);
+        double w2 = w * w;
+        z = x * (w2 * w2 * w2);        // x^(1/7)
+        double z2 = z * z;
+        zig = z2 * z2 * z;             // x^(5/7)
+    } else {
+        z = pow(x, (g - 1.0) / (2.0 * g));
+        zig = pow(x, 1.0 / g);
+    }
+}
+template <bool G14>
+__device__ __forceinline__ void pow_fan(double c, double g, double& c5, double& c7) {
+    if (G14) {
+        double c2 = c * c;
+        c5 = c2 * c2 * c;              // c^(2/(g-1))
+        c7 = c5 * c2;                  // c^(2g/(g-1))
+    } else {
+        c5 = pow(c, 2.0 / (g - 1.0));
+        c7 = pow(c, 2.0 * g / (g - 1.0));
+    }
+}
+
+// Exact Riemann solver sampled at x/t = 0: fixed `niter` Newton steps from
+// the PVRS guess, p kept above 1e-10.  Inputs/outputs (rho, un, ut, p) in
+// double.
+template <bool G14>
+__device__ __forceinline__ void riemann0(const double* L, const double* R, double g, int niter,
+                                         double* W) {
+    const Side sl = make_side<G14>(L[0], L[1], L[3], g);
+    const Side sr = make_side<G14>(R[0], R[1], R[3], g);
+    const double du = sr.u - sl.u;
+    double p = 0.5 * (sl.p + sr.p) - 0.125 * du * (sl.r + sr.r) * (sl.c + sr.c);
+    p = fmax(p, 1e-10);
+    for (int it = 0; it < niter; ++it) {
+        double fl, fdl, fr, fdr;
+        pres_fun<G14>(sl, p, g, fl, fdl);
+        pres_fun<G14>(sr, p, g, fr, fdr);
+        p = fmax(p - (fl + fr + du) / (fdl + fdr), 1e-10);
+    }
+    double fl, fdl, fr, fdr;
+    pres_fun<G14>(sl, p, g, fl, fdl);
+    pres_fun<G14>(sr, p, g, fr, fdr);
+    const double us = 0.5 * (sl.u + sr.u) + 0.5 * (fr - fl);
+    const double g1 = (g - 1.0) / (2.0 * g), g2 = (g + 1.0) / (2.0 * g);
+    const double g5 = 2.0 / (g + 1.0), g6 = (g - 1.0) / (g + 1.0), g7 = 0.5 * (g - 1.0);
+    // sample: left of the contact when 0 <= u*
+    const bool left = 0.0 <= us;
+    const Side& s = left ? sl : sr;
+    const double sg = left ? 1.0 : -1.0;     // mirror the right side onto the left case
+    const double uk = sg * s.u;              // velocity in the mirrored frame
+    const double ustar = sg * us;
+    W[2] = left ? L[2] : R[2];
+    double rr, uu, pp;
+    if (p > s.p) {                           // shock
+        double pm = p * s.ip;
+        double sk = uk - s.c * sqrt(g2 * pm + g1);
+        if (0.0 <= sk) { rr = s.r; uu = uk; pp = s.p; }
+        else { rr = s.r * (pm + g6) / (pm * g6 + 1.0); uu = ustar; pp = p; }
+    } else {                                 // rarefaction
+        double sh = uk - s.c;
+        if (0.0 <= sh) { rr = s.r; uu = uk; pp = s.p; }
+        else {
+            double z, zig;
+            pow_g1_ig<G14>(p * s.ip, g, z, zig);
+            double st = ustar - s.c * z;
+            if (0.0 > st) { rr = s.r * zig; uu = ustar; pp = p; }
+            else {
+                double cf = g5 + g6 / s.c * uk;
+                double c5, c7;
+                pow_fan<G14>(cf, g, c5, c7);
+                rr = s.r * c5;
+                uu = g5 * (s.c + g7 * uk);
+                pp = s.p * c7;
+            }
+        }
+    }
+    W[0] = rr;
+    W[1] = sg * uu;
+    W[3] = pp;
+}
+
+// Godunov flux from the sampled state (cmpflx); (rho, mn, mt, E) order.
+template <class T>
+__device__ __forceinline__ void euler_flux(const T* G, T g, T* F) {
+    const T r = G[0], un = G[1], ut = G[2], p = G[3];
+    const T et = p / (g - T(1)) + T(0.5) * r * (un * un + ut * ut);
+    F[0] = r * un;
+    F[1] = r * un * un + p;
+    F[2] = r * un * ut;
+    F[3] = un * (et + p);
+}
+
+// Conservative update U - nu (F(+1/2) - F(-1/2)); accumulation type A.
+template <class T, class A>
+__device__ __forceinline__ T euler_update(T u, T fp, T fm, A nu) {
+    return (T)((A)u - nu * ((A)fp - (A)fm));
+}
+
+// Largest signal speed of one cell, max(|u|+c, |v|+c).
+template <class T>
+__device__ __forceinline__ T euler_speed(T rho, T mx, T my, T E, T g) {
+    T u = mx / rho, v = my / rho;
+    T p = (g - T(1)) * (E - T(0.5) * rho * (u * u + v * v));
+    T c = sqrt(g * p / rho);
+    return fmax(fabs(u) + c, fabs(v) + c);
+}
+
+// Riemann problem on T-typed face states: promotes to double for the
+// pressure iteration and sampling; the result is rounded back to T.
+template <class T, bool G14>
+__device__ __forceinline__ void riemann_T(const T* L, const T* R, T g, int niter, T* G) {
+    double l[4] = {(double)L[0], (double)L[1], (double)L[2], (double)L[3]};
+    double r[4] = {(double)R[0], (double)R[1], (double)R[2], (double)R[3]};
+    double w[4];
+    riemann0<G14>(l, r, (double)g, niter, w);
+    G[0] = (T)w[0]; G[1] = (T)w[1]; G[2] = (T)w[2]; G[3] = (T)w[3];
+}
+
+// atomic max of a non-negative double through its bit pattern (the order of
+// non-negative IEEE doubles equals the order of their bit patterns)
+__device__ __forceinline__ void atomic_max_nonneg(double* addr, double v) {
+    atomicMax(reinterpret_cast<unsigned long long*>(addr),
+              (unsigned long long)__double_as_longlong(v));
+}
+
+}  // namespace hfav

@@ -1,0 +1,617 @@
+// Planner: iteration nests, fusion, extents, contraction, kernel family.
+//
+//  * one perfect iteration nest per rule call site, of the rule's rank
+//    (Design, "Iteration nests"; call sites are already grouped per rule);
+//  * fuse_inest_dag: walk the nests in topological order keeping a "fusing"
+//    nest; a nest that cannot be fused splits the DAG and starts a new one
+//    (Design, "Fusing the iteration nest DAG");
+//  * fuse_inest: equal ranks fuse phase by phase under the four dataflow
+//    ordering checks; a lower-rank nest goes into the prologue (broadcast) or
+//    the epilogue (after the steady state) of the higher one, otherwise it is
+//    unfusable (Design, "Fusing iteration nests", "Reductions & broadcasts &
+//    splits");
+//  * extents of every grid term are Minkowski sums of the offsets through
+//    which the goals reach it (Design, "Variables and storage");
+//  * the window of an intermediate is the span of its extent along the
+//    outermost axis in which it varies: slabs of that axis ("outer"
+//    rotation) or elements when only the innermost axis varies ("inner"
+//    rotation) (Design, "Contraction").
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <sstream>
+#include <string>
+
+#include "internal.h"
+
+namespace {
+
+struct Reach {
+    int n;
+    std::vector<char> m;   // m[a*n+b]: rule b depends on rule a (path a -> b)
+    bool path(int a, int b) const { return m[(size_t)a * n + b] != 0; }
+};
+
+Reach reachability(const hfav_chain *c) {
+    const int n = (int)c->rules.size();
+    Reach R{n, std::vector<char>((size_t)n * n, 0)};
+    // direct edges producer -> consumer, then closure in topological order
+    for (int pos = (int)c->topo.size() - 1; pos >= 0; --pos) {
+        int a = c->topo[pos];
+        for (int b : c->topo) {
+            if (b == a) continue;
+            bool direct = false;
+            for (const HRef &ref : c->rules[b].in)
+                if (c->terms[ref.term].producer == a) direct = true;
+            if (direct) {
+                R.m[(size_t)a * n + b] = 1;
+                for (int x = 0; x < n; ++x)
+                    if (R.m[(size_t)b * n + x]) R.m[(size_t)a * n + x] = 1;
+            }
+        }
+    }
+    return R;
+}
+
+// (R <= S | D): every rule of R can be ordered before every rule of S,
+// i.e. no rule of S reaches a rule of R.
+bool dataflow_le(const Reach &D, const std::vector<int> &R, const std::vector<int> &S) {
+    for (int s : S)
+        for (int r : R)
+            if (s == r || D.path(s, r)) return false;
+    return true;
+}
+
+std::vector<int> all_phases(const HNest &N) {
+    std::vector<int> v = N.prologue;
+    v.insert(v.end(), N.steady.begin(), N.steady.end());
+    v.insert(v.end(), N.epilogue.begin(), N.epilogue.end());
+    return v;
+}
+
+void append(std::vector<int> &a, const std::vector<int> &b) { a.insert(a.end(), b.begin(), b.end()); }
+
+// Returns false when the pair is unfusable.
+bool fuse_inest(const Reach &D, const HNest &A, const HNest &B, HNest &out) {
+    if (A.rank == B.rank) {
+        if (dataflow_le(D, A.prologue, B.steady) && dataflow_le(D, B.prologue, A.steady) &&
+            dataflow_le(D, A.steady, B.epilogue) && dataflow_le(D, B.steady, A.epilogue)) {
+            out.rank = A.rank;
+            out.prologue = A.prologue; append(out.prologue, B.prologue);
+            out.steady = A.steady; append(out.steady, B.steady);
+            out.epilogue = A.epilogue; append(out.epilogue, B.epilogue);
+            return true;
+        }
+        return false;
+    }
+    const HNest &lo = A.rank < B.rank ? A : B;
+    const HNest &hi = A.rank < B.rank ? B : A;
+    const std::vector<int> lo_all = all_phases(lo);
+    std::vector<int> hi_body = hi.steady;
+    append(hi_body, hi.epilogue);
+    std::vector<int> hi_head = hi.prologue;
+    append(hi_head, hi.steady);
+    const bool before = dataflow_le(D, lo_all, hi_body);
+    const bool after = dataflow_le(D, hi_head, lo_all);
+    out = hi;
+    if (before) {                       // broadcast: lower nest in the prologue
+        std::vector<int> p = lo_all;
+        append(p, hi.prologue);
+        out.prologue = p;
+        return true;
+    }
+    if (after) {                        // after the steady state: epilogue
+        append(out.epilogue, lo_all);
+        return true;
+    }
+    return false;
+}
+
+int phase_of(const HNest &N, int r) {
+    if (std::find(N.prologue.begin(), N.prologue.end(), r) != N.prologue.end()) return 0;
+    if (std::find(N.steady.begin(), N.steady.end(), r) != N.steady.end()) return 1;
+    return 2;
+}
+
+const char *storage_name(int s) {
+    switch (s) {
+    case HFAV_STORE_FULL: return "full";
+    case HFAV_STORE_REGISTER: return "register";
+    case HFAV_STORE_INNER: return "inner";
+    case HFAV_STORE_OUTER: return "outer";
+    default: return "scalar";
+    }
+}
+
+// ------------------------------------------------------------ family match
+// Reference checks used by the matchers.
+bool ref_is(const hfav_chain *c, const HRef &r, int term, int di, int dj, int dk) {
+    return r.term == term && r.off[0] == di && r.off[1] == dj && r.off[2] == dk;
+}
+int prod_out(const hfav_chain *c, int rule, int pos) { return c->rules[rule].out[pos]; }
+
+std::vector<int> live_rules(const hfav_chain *c) { return c->topo; }
+
+int find_op(const hfav_chain *c, int op) {
+    int found = -1;
+    for (int r : c->topo)
+        if (c->rules[r].op == op) {
+            if (found >= 0) return -2;   // more than one
+            found = r;
+        }
+    return found;
+}
+
+bool is_inter(const hfav_chain *c, int t) { return c->terms[t].kind == TK_INTER; }
+
+bool match_hdiff(const hfav_chain *c, HPlan &p) {
+    if (c->topo.size() != 4) return false;
+    int rl = find_op(c, HFAV_OP_HDIFF_LAP), rx = find_op(c, HFAV_OP_HDIFF_FLX);
+    int ry = find_op(c, HFAV_OP_HDIFF_FLY), ro = find_op(c, HFAV_OP_HDIFF_OUT);
+    if (rl < 0 || rx < 0 || ry < 0 || ro < 0) return false;
+    const HRule &L = c->rules[rl], &X = c->rules[rx], &Y = c->rules[ry], &O = c->rules[ro];
+    const int u = L.in[0].term, lap = L.out[0], flx = X.out[0], fly = Y.out[0];
+    if (c->terms[u].kind != TK_AXIOM || c->terms[u].rank != c->ndim) return false;
+    if (!is_inter(c, lap) || !is_inter(c, flx) || !is_inter(c, fly)) return false;
+    if (!(ref_is(c, L.in[0], u, 0, 0, 0) && ref_is(c, L.in[1], u, 1, 0, 0) && ref_is(c, L.in[2], u, -1, 0, 0) &&
+          ref_is(c, L.in[3], u, 0, 1, 0) && ref_is(c, L.in[4], u, 0, -1, 0)))
+        return false;
+    if (!(ref_is(c, X.in[0], lap, 0, 0, 0) && ref_is(c, X.in[1], lap, 1, 0, 0) && ref_is(c, X.in[2], u, 0, 0, 0) &&
+          ref_is(c, X.in[3], u, 1, 0, 0)))
+        return false;
+    if (!(ref_is(c, Y.in[0], lap, 0, 0, 0) && ref_is(c, Y.in[1], lap, 0, 1, 0) && ref_is(c, Y.in[2], u, 0, 0, 0) &&
+          ref_is(c, Y.in[3], u, 0, 1, 0)))
+        return false;
+    if (!(ref_is(c, O.in[0], u, 0, 0, 0) && ref_is(c, O.in[1], flx, 0, 0, 0) && ref_is(c, O.in[2], flx, -1, 0, 0) &&
+          ref_is(c, O.in[3], fly, 0, 0, 0) && ref_is(c, O.in[4], fly, 0, -1, 0)))
+        return false;
+    if (c->goals.size() != 1 || c->goals[0] != O.out[0]) return false;
+    if (p.opts.boundary[0] != HFAV_BC_PERIODIC || p.opts.boundary[1] != HFAV_BC_PERIODIC) return false;
+    p.fam_in = {u};
+    p.fam_out = {O.out[0]};
+    p.fam_param = {O.param[0]};
+    return true;
+}
+
+// Directionally split Godunov sweep along axis d.
+bool match_euler(const hfav_chain *c, HPlan &p, int &dir) {
+    if (c->ndim != 2) return false;
+    int rp = find_op(c, HFAV_OP_EULER_PRIM), rs = find_op(c, HFAV_OP_EULER_SLOPE);
+    int rt = find_op(c, HFAV_OP_EULER_TRACE), rr = find_op(c, HFAV_OP_EULER_RIEMANN);
+    int rf = find_op(c, HFAV_OP_EULER_FLUX), ru = find_op(c, HFAV_OP_EULER_UPDATE);
+    int rm = find_op(c, HFAV_OP_EULER_SMAX), rd = find_op(c, HFAV_OP_EULER_DT);
+    if (rp < 0 || rs < 0 || rt < 0 || rr < 0 || rf < 0 || ru < 0 || rm == -2 || rd == -2) return false;
+    size_t expect = 6 + (rm >= 0) + (rd >= 0);
+    if (c->topo.size() != expect) return false;
+    const HRule &P = c->rules[rp], &S = c->rules[rs], &T = c->rules[rt], &R = c->rules[rr];
+    const HRule &F = c->rules[rf], &U = c->rules[ru];
+    // direction from the slope stencil
+    int d = -1;
+    for (int ax = 0; ax < 2; ++ax)
+        if (S.in[2].off[ax] == 1) d = ax;
+    if (d < 0) return false;
+    int e[3] = {0, 0, 0};
+    e[d] = 1;
+    for (int q = 0; q < 4; ++q)
+        if (c->terms[P.in[q].term].kind != TK_AXIOM || c->terms[P.in[q].term].rank != 2 ||
+            !ref_is(c, P.in[q], P.in[q].term, 0, 0, 0))
+            return false;
+    for (int q = 0; q < 4; ++q) {
+        int w = P.out[q];
+        if (!(ref_is(c, S.in[3 * q], w, -e[0], -e[1], 0) && ref_is(c, S.in[3 * q + 1], w, 0, 0, 0) &&
+              ref_is(c, S.in[3 * q + 2], w, e[0], e[1], 0)))
+            return false;
+    }
+    for (int q = 0; q < 5; ++q)
+        if (!ref_is(c, T.in[q], P.out[q], 0, 0, 0)) return false;
+    for (int q = 0; q < 4; ++q)
+        if (!ref_is(c, T.in[5 + q], S.out[q], 0, 0, 0)) return false;
+    const int dt = T.in[9].term;
+    for (int q = 0; q < 4; ++q) {
+        if (!ref_is(c, R.in[q], T.out[q], 0, 0, 0)) return false;
+        if (!ref_is(c, R.in[4 + q], T.out[4 + q], e[0], e[1], 0)) return false;
+        if (!ref_is(c, F.in[q], R.out[q], 0, 0, 0)) return false;
+        if (!ref_is(c, U.in[q], P.in[q].term, 0, 0, 0)) return false;
+        if (!ref_is(c, U.in[4 + q], F.out[q], 0, 0, 0)) return false;
+        if (!ref_is(c, U.in[8 + q], F.out[q], -e[0], -e[1], 0)) return false;
+    }
+    if (U.in[12].term != dt) return false;
+    const double g = P.param[0];
+    if (R.param[0] != g || F.param[0] != g) return false;
+    if (R.param[1] < 0 || R.param[1] > 64 || R.param[1] != (double)(int)R.param[1]) return false;
+    // dt: an axiom, or a 0-D rule from an smax axiom
+    if (rd >= 0) {
+        const HRule &Dr = c->rules[rd];
+        if (Dr.out[0] != dt || c->terms[Dr.in[0].term].kind != TK_AXIOM) return false;
+        p.fam_dt_term = Dr.in[0].term;
+        p.fam_dt_mode = 1;
+        p.fam_cfl = Dr.param[0];
+    } else {
+        if (c->terms[dt].kind != TK_AXIOM) return false;
+        p.fam_dt_term = dt;
+        p.fam_dt_mode = 0;
+    }
+    // the intermediates stay intermediates; goals are the 4 updated fields
+    for (int r : {rp, rs, rt, rr, rf})
+        for (int t : c->rules[r].out)
+            if (!is_inter(c, t)) return false;
+    for (int q = 0; q < 4; ++q)
+        if (c->terms[U.out[q]].kind != TK_GOAL) return false;
+    p.fam_smax_goal = -1;
+    if (rm >= 0) {
+        const HRule &M = c->rules[rm];
+        if (M.param[0] != g) return false;
+        const bool ok0 = ref_is(c, M.in[0], U.out[0], 0, 0, 0) && ref_is(c, M.in[3], U.out[3], 0, 0, 0);
+        const bool ok12 = (ref_is(c, M.in[1], U.out[1], 0, 0, 0) && ref_is(c, M.in[2], U.out[2], 0, 0, 0)) ||
+                          (ref_is(c, M.in[1], U.out[2], 0, 0, 0) && ref_is(c, M.in[2], U.out[1], 0, 0, 0));
+        if (!ok0 || !ok12 || c->terms[M.out[0]].kind != TK_GOAL) return false;
+        p.fam_smax_goal = M.out[0];
+    }
+    if (c->goals.size() != 4u + (rm >= 0)) return false;
+    p.fam_in = {P.in[0].term, P.in[1].term, P.in[2].term, P.in[3].term};
+    p.fam_out = {U.out[0], U.out[1], U.out[2], U.out[3]};
+    p.fam_param = {g, R.param[1]};
+    dir = d;
+    return true;
+}
+
+bool match_smax(const hfav_chain *c, HPlan &p) {
+    if (c->topo.size() != 1) return false;
+    const HRule &M = c->rules[c->topo[0]];
+    if (M.op != HFAV_OP_EULER_SMAX || c->ndim != 2) return false;
+    for (int q = 0; q < 4; ++q)
+        if (c->terms[M.in[q].term].kind != TK_AXIOM || !ref_is(c, M.in[q], M.in[q].term, 0, 0, 0)) return false;
+    p.fam_in = {M.in[0].term, M.in[1].term, M.in[2].term, M.in[3].term};
+    p.fam_out = {M.out[0]};
+    p.fam_param = {M.param[0]};
+    return true;
+}
+
+bool match_lap7_chain(const hfav_chain *c, HPlan &p) {
+    if (c->ndim != 3 || c->topo.size() != 3) return false;
+    const HRule &A = c->rules[c->topo[0]], &B = c->rules[c->topo[1]], &X = c->rules[c->topo[2]];
+    if (A.op != HFAV_OP_LAP7 || B.op != HFAV_OP_LAP7 || X.op != HFAV_OP_AXPY) return false;
+    const int u = A.in[0].term, l1 = A.out[0], l2 = B.out[0];
+    if (c->terms[u].kind != TK_AXIOM || !is_inter(c, l1) || !is_inter(c, l2)) return false;
+    auto lap_ok = [&](const HRule &Rl, int src) {
+        return ref_is(c, Rl.in[0], src, 0, 0, 0) && ref_is(c, Rl.in[1], src, 1, 0, 0) &&
+               ref_is(c, Rl.in[2], src, -1, 0, 0) && ref_is(c, Rl.in[3], src, 0, 1, 0) &&
+               ref_is(c, Rl.in[4], src, 0, -1, 0) && ref_is(c, Rl.in[5], src, 0, 0, 1) &&
+               ref_is(c, Rl.in[6], src, 0, 0, -1);
+    };
+    if (!lap_ok(A, u) || !lap_ok(B, l1)) return false;
+    if (!ref_is(c, X.in[0], u, 0, 0, 0) || !ref_is(c, X.in[1], l2, 0, 0, 0)) return false;
+    if (c->goals.size() != 1 || c->goals[0] != X.out[0]) return false;
+    for (int ax = 0; ax < 3; ++ax)
+        if (p.opts.boundary[ax] != HFAV_BC_PERIODIC) return false;
+    p.fam_in = {u};
+    p.fam_out = {X.out[0]};
+    p.fam_param = {X.param[0]};
+    return true;
+}
+
+size_t esize(int dtype) { return dtype == HFAV_F64 ? 8 : 4; }
+
+void json_int3(std::ostringstream &o, const int *v) { o << "[" << v[0] << "," << v[1] << "," << v[2] << "]"; }
+
+}  // namespace
+
+int hfav_plan_impl(hfav_chain *c, const hfav_plan_opts *o, hfav_plan_info *info) {
+    if (!c || !o) return hfav_fail(HFAV_EINVAL, "null chain or options");
+    HPlan p;
+    p.opts = *o;
+    const int nd = c->ndim;
+    for (int ax = 0; ax < 3; ++ax) {
+        if (o->dims[ax] < 1) return hfav_fail(HFAV_EINVAL, "dims must be >= 1");
+        if (ax >= nd && o->dims[ax] != 1) return hfav_fail(HFAV_EINVAL, "dims beyond ndim must be 1");
+        if (o->boundary[ax] != HFAV_BC_PERIODIC && o->boundary[ax] != HFAV_BC_TRANSMISSIVE)
+            return hfav_fail(HFAV_EINVAL, "unknown boundary");
+    }
+    if ((int64_t)o->dims[0] * o->dims[1] * o->dims[2] > (int64_t)1 << 36)
+        return hfav_fail(HFAV_EINVAL, "grid too large");
+    if (o->mode < HFAV_MODE_AUTO || o->mode > HFAV_MODE_UNFUSED) return hfav_fail(HFAV_EINVAL, "unknown mode");
+    if (o->precision != HFAV_PREC_NATIVE && o->precision != HFAV_PREC_F32_F64ACC)
+        return hfav_fail(HFAV_EINVAL, "unknown precision");
+    if (o->precision == HFAV_PREC_F32_F64ACC && c->dtype != HFAV_F32)
+        return hfav_fail(HFAV_EUNSUP, "F32_F64ACC precision needs an F32 chain");
+    const int64_t ncell = (int64_t)o->dims[0] * o->dims[1] * o->dims[2];
+
+    // ---- nests and fusion
+    const Reach D = reachability(c);
+    std::vector<HNest> initial;
+    for (int r : c->topo) {
+        HNest n;
+        n.rank = c->rules[r].rank;
+        n.steady = {r};
+        initial.push_back(n);
+    }
+    if (!initial.empty()) {
+        HNest cur = initial[0];
+        for (size_t q = 1; q < initial.size(); ++q) {
+            HNest fused;
+            if (fuse_inest(D, cur, initial[q], fused)) cur = fused;
+            else {                      // split: close the fusing nest
+                p.nests.push_back(cur);
+                cur = initial[q];
+            }
+        }
+        p.nests.push_back(cur);
+    }
+    if ((int)p.nests.size() > HFAV_MAX_NESTS) return hfav_fail(HFAV_EUNSUP, "too many nests after fusion");
+
+    // ---- Minkowski extents, backward from the goals
+    const int nt = (int)c->terms.size();
+    p.terms.assign(nt, HTermPlan{});
+    for (HTermPlan &tp : p.terms) {
+        tp.has_ext = false;
+        tp.window_axis = -1;
+        tp.window = 0;
+        tp.storage = HFAV_STORE_FULL;
+        for (int ax = 0; ax < 3; ++ax) tp.lo[ax] = tp.hi[ax] = 0;
+    }
+    auto widen = [&](int t, const int *lo, const int *hi) {
+        HTermPlan &tp = p.terms[t];
+        if (!tp.has_ext) {
+            tp.has_ext = true;
+            for (int ax = 0; ax < 3; ++ax) { tp.lo[ax] = lo[ax]; tp.hi[ax] = hi[ax]; }
+        } else {
+            for (int ax = 0; ax < 3; ++ax) {
+                tp.lo[ax] = std::min(tp.lo[ax], lo[ax]);
+                tp.hi[ax] = std::max(tp.hi[ax], hi[ax]);
+            }
+        }
+    };
+    const int zero[3] = {0, 0, 0};
+    for (int t : c->goals)
+        if (c->terms[t].rank > 0) widen(t, zero, zero);
+    for (int pos = (int)c->topo.size() - 1; pos >= 0; --pos) {
+        const int r = c->topo[pos];
+        const HRule &R = c->rules[r];
+        if (R.rank == 0) continue;
+        int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+        bool any = false;
+        if (R.reduce == HFAV_REDUCE_NONE) {
+            for (int t : R.out) {
+                const HTermPlan &tp = p.terms[t];
+                if (!tp.has_ext) continue;
+                for (int ax = 0; ax < 3; ++ax) {
+                    lo[ax] = any ? std::min(lo[ax], tp.lo[ax]) : tp.lo[ax];
+                    hi[ax] = any ? std::max(hi[ax], tp.hi[ax]) : tp.hi[ax];
+                }
+                any = true;
+            }
+        }
+        if (!any) { for (int ax = 0; ax < 3; ++ax) lo[ax] = hi[ax] = 0; }
+        for (const HRef &ref : R.in) {
+            if (c->terms[ref.term].rank == 0) continue;
+            int l2[3], h2[3];
+            for (int ax = 0; ax < 3; ++ax) { l2[ax] = lo[ax] + ref.off[ax]; h2[ax] = hi[ax] + ref.off[ax]; }
+            widen(ref.term, l2, h2);
+        }
+    }
+
+    // ---- storage classes and windows
+    std::vector<int> nest_of(c->rules.size(), -1);
+    for (size_t n = 0; n < p.nests.size(); ++n)
+        for (int r : all_phases(p.nests[n])) nest_of[r] = (int)n;
+    int64_t fp_un = 0, fp_con = 0;
+    int maxw = 0;
+    for (int t = 0; t < nt; ++t) {
+        const HTerm &T = c->terms[t];
+        HTermPlan &tp = p.terms[t];
+        if (T.rank == 0) { tp.storage = HFAV_STORE_SCALAR; continue; }
+        if (T.kind != TK_INTER) { tp.storage = HFAV_STORE_FULL; continue; }
+        if (T.producer < 0 || !c->live[T.producer]) continue;
+        fp_un += ncell;
+        bool same_nest = true;
+        for (int r : c->topo)
+            for (const HRef &ref : c->rules[r].in)
+                if (ref.term == t && nest_of[r] != nest_of[T.producer]) same_nest = false;
+        if (!same_nest) {
+            tp.storage = HFAV_STORE_FULL;
+            fp_con += ncell;
+            continue;
+        }
+        // outermost axis (in loop order) along which the extent varies
+        int wax = -1;
+        for (int q = 0; q < nd; ++q) {
+            const int ax = c->order[q];
+            if (tp.hi[ax] != tp.lo[ax]) { wax = ax; break; }
+        }
+        if (wax < 0) {
+            tp.storage = HFAV_STORE_REGISTER;
+            tp.window = 1;
+            tp.window_axis = -1;
+            fp_con += 1;
+        } else {
+            tp.window_axis = wax;
+            tp.window = tp.hi[wax] - tp.lo[wax] + 1;
+            const int inner = c->order[nd - 1];
+            if (wax == inner) {
+                tp.storage = HFAV_STORE_INNER;
+                fp_con += tp.window;
+            } else {
+                tp.storage = HFAV_STORE_OUTER;
+                // a slab of axis wax spans the axes inside it in loop order
+                int64_t slab = 1;
+                bool inside = false;
+                for (int q = 0; q < nd; ++q) {
+                    if (inside) slab *= o->dims[c->order[q]];
+                    if (c->order[q] == wax) inside = true;
+                }
+                fp_con += tp.window * slab;
+            }
+        }
+        maxw = std::max(maxw, tp.window);
+    }
+
+    // ---- byte counts
+    const size_t es = esize(c->dtype);
+    double bf = 0.0, bu = 0.0;
+    for (int t : c->axioms)
+        if (c->terms[t].rank > 0) bf += es;
+    for (int t : c->goals)
+        if (c->terms[t].rank > 0) bf += es;
+    for (int r : c->topo) {
+        const HRule &R = c->rules[r];
+        if (R.rank == 0) continue;
+        std::vector<int> seen;
+        for (const HRef &ref : R.in)
+            if (c->terms[ref.term].rank > 0 && std::find(seen.begin(), seen.end(), ref.term) == seen.end())
+                seen.push_back(ref.term);
+        bu += es * seen.size();
+        for (int t : R.out)
+            if (c->terms[t].rank > 0) bu += es;
+    }
+
+    // ---- kernel family
+    int dir = -1;
+    if (match_hdiff(c, p)) p.family = HFAV_FAMILY_HDIFF;
+    else if (match_euler(c, p, dir)) {
+        p.family = dir == 0 ? HFAV_FAMILY_EULER_X : HFAV_FAMILY_EULER_Y;
+        if (o->boundary[dir] != HFAV_BC_PERIODIC && o->boundary[dir] != HFAV_BC_TRANSMISSIVE) p.family = 0;
+    } else if (match_lap7_chain(c, p)) p.family = HFAV_FAMILY_LAP7_CHAIN;
+    else if (match_smax(c, p)) p.family = HFAV_FAMILY_SMAX;
+    else p.family = HFAV_FAMILY_NONE;
+    if (o->precision == HFAV_PREC_F32_F64ACC && p.family != HFAV_FAMILY_EULER_X &&
+        p.family != HFAV_FAMILY_EULER_Y && o->mode == HFAV_MODE_FUSED)
+        return hfav_fail(HFAV_EUNSUP, "F32_F64ACC is implemented for the Euler sweeps only");
+
+    bool fused = false;
+    if (o->mode == HFAV_MODE_FUSED) {
+        if (p.family == HFAV_FAMILY_NONE)
+            return hfav_fail(HFAV_EUNSUP, "no fused kernel family matches this chain");
+        fused = true;
+    } else if (o->mode == HFAV_MODE_AUTO) {
+        fused = p.family != HFAV_FAMILY_NONE;
+    }
+    // the single-rule reduction has no separate unfused form: it is the same kernel
+    if (p.family == HFAV_FAMILY_SMAX && o->mode == HFAV_MODE_UNFUSED) fused = false;
+
+    // ---- configuration
+    hfav_config cfg = hfav_default_config(p.family, c->dtype, o->dims);
+    int src = HFAV_CONFIG_DEFAULT;
+    if (o->config_source == HFAV_CONFIG_FORCED) {
+        cfg = o->forced;
+        if (cfg.block <= 0 || cfg.block > 1024 || cfg.seg < 0 || cfg.seg > 4096 || cfg.variant < 0)
+            return hfav_fail(HFAV_EINVAL, "forced configuration out of range");
+        src = HFAV_CONFIG_FORCED;
+    } else if (o->config_source == HFAV_CONFIG_TUNED) {
+        if (hfav_tuned_config(p.family, c->dtype, o->dims, &cfg)) src = HFAV_CONFIG_TUNED;
+    } else if (o->config_source == HFAV_CONFIG_MODEL) {
+        if (hfav_model_config(c, p.family, o->dims, &cfg)) src = HFAV_CONFIG_MODEL;
+    }
+
+    // ---- unfused workspace layout
+    p.ws_off.assign(nt, -1);
+    p.ws_bytes = 0;
+    if (!fused) {
+        for (int t = 0; t < nt; ++t) {
+            const HTerm &T = c->terms[t];
+            if (T.kind != TK_INTER || T.producer < 0 || !c->live[T.producer]) continue;
+            p.ws_off[t] = (int64_t)p.ws_bytes;
+            size_t b = T.rank == 0 ? 8 : (size_t)ncell * es;
+            p.ws_bytes += (b + 255) / 256 * 256;
+        }
+    }
+    p.exec_order = c->topo;
+
+    // ---- info
+    hfav_plan_info &I = p.info;
+    memset(&I, 0, sizeof(I));
+    I.n_rules = (int)c->topo.size();
+    for (size_t q = 0; q < c->topo.size(); ++q) I.rule_order[q] = c->topo[q];
+    I.n_nests = (int)p.nests.size();
+    for (int r = 0; r < HFAV_MAX_RULES; ++r) { I.nest_of_rule[r] = -1; I.phase_of_rule[r] = -1; }
+    for (size_t n = 0; n < p.nests.size(); ++n)
+        for (int r : all_phases(p.nests[n])) {
+            I.nest_of_rule[r] = (int)n;
+            I.phase_of_rule[r] = phase_of(p.nests[n], r);
+        }
+    I.family = p.family;
+    I.fused = fused ? 1 : 0;
+    I.streamed_axis = p.family == HFAV_FAMILY_EULER_X ? 0 : p.family == HFAV_FAMILY_LAP7_CHAIN ? 2 : 1;
+    I.config = cfg;
+    I.config_source = src;
+    I.footprint_unfused = fp_un;
+    I.footprint_contracted = fp_con;
+    I.max_window = maxw;
+    I.bytes_per_cell_fused = bf;
+    I.bytes_per_cell_unfused = bu;
+    I.workspace_bytes = p.ws_bytes;
+
+    // ---- JSON
+    std::ostringstream js;
+    js << "{\"family\":" << p.family << ",\"fused\":" << I.fused << ",\"nests\":[";
+    for (size_t n = 0; n < p.nests.size(); ++n) {
+        const HNest &N = p.nests[n];
+        auto lst = [&](const std::vector<int> &v) {
+            js << "[";
+            for (size_t q = 0; q < v.size(); ++q) js << (q ? "," : "") << v[q];
+            js << "]";
+        };
+        js << (n ? "," : "") << "{\"rank\":" << N.rank << ",\"prologue\":";
+        lst(N.prologue);
+        js << ",\"steady\":";
+        lst(N.steady);
+        js << ",\"epilogue\":";
+        lst(N.epilogue);
+        js << "}";
+    }
+    js << "],\"terms\":[";
+    for (int t = 0; t < nt; ++t) {
+        const HTerm &T = c->terms[t];
+        const HTermPlan &tp = p.terms[t];
+        js << (t ? "," : "") << "{\"name\":\"" << T.name << "\",\"kind\":" << T.kind << ",\"rank\":" << T.rank
+           << ",\"lo\":";
+        json_int3(js, tp.lo);
+        js << ",\"hi\":";
+        json_int3(js, tp.hi);
+        js << ",\"storage\":\"" << storage_name(tp.storage) << "\",\"window_axis\":" << tp.window_axis
+           << ",\"window\":" << tp.window << "}";
+    }
+    js << "],\"footprint_unfused\":" << fp_un << ",\"footprint_contracted\":" << fp_con
+       << ",\"max_window\":" << maxw << ",\"bytes_per_cell_fused\":" << bf
+       << ",\"bytes_per_cell_unfused\":" << bu << ",\"config\":{\"block\":" << cfg.block
+       << ",\"tile_y\":" << cfg.tile_y << ",\"seg\":" << cfg.seg << ",\"variant\":" << cfg.variant
+       << "},\"config_source\":" << src << ",\"workspace_bytes\":" << p.ws_bytes << "}";
+    p.json = js.str();
+    p.valid = true;
+    c->plan = p;
+    if (info) *info = I;
+    return HFAV_OK;
+}
+
+extern "C" int hfav_plan(hfav_chain *chain, const hfav_plan_opts *opts, hfav_plan_info *info) {
+    if (chain) chain->plan.valid = false;
+    try {
+        return hfav_plan_impl(chain, opts, info);
+    } catch (...) {
+        return hfav_fail(HFAV_EINVAL, "host exception while planning");
+    }
+}
+
+extern "C" int hfav_plan_term(const hfav_chain *c, int index, hfav_term_info *info) {
+    if (!c || !info) return hfav_fail(HFAV_EINVAL, "null argument");
+    if (!c->plan.valid) return hfav_fail(HFAV_ENOPLAN, "chain has no plan");
+    if (index < 0 || index >= (int)c->terms.size()) return hfav_fail(HFAV_EINVAL, "term index out of range");
+    const HTerm &T = c->terms[index];
+    const HTermPlan &tp = c->plan.terms[index];
+    info->name = T.name.c_str();
+    info->kind = T.kind;
+    info->rank = T.rank;
+    info->producer = T.producer;
+    for (int ax = 0; ax < 3; ++ax) { info->ext_lo[ax] = tp.lo[ax]; info->ext_hi[ax] = tp.hi[ax]; }
+    info->storage = tp.storage;
+    info->window_axis = tp.window_axis;
+    info->window = tp.window;
+    return HFAV_OK;
+}
+
+extern "C" const char *hfav_plan_json(const hfav_chain *c) {
+    if (!c || !c->plan.valid) {
+        hfav_fail(HFAV_ENOPLAN, "chain has no plan");
+        return nullptr;
+    }
+    return c->plan.json.c_str();
+}

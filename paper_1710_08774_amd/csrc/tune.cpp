@@ -1,0 +1,76 @@
+// Tile configurations: built-in defaults per kernel family, a tuning table
+// filled from the autotuner's results, and the hook for the learned cost
+// model.
+#include <cmath>
+#include <mutex>
+#include <vector>
+
+#include "internal.h"
+#include "../../include/hfav_tune.h"
+
+namespace {
+struct Entry {
+    int family, dtype;
+    int dims[3];
+    hfav_config cfg;
+};
+std::mutex g_mu;
+std::vector<Entry> g_table;
+}  // namespace
+
+hfav_config hfav_default_config(int family, int dtype, const int dims[3]) {
+    hfav_config c{256, 1, 0, 0};
+    switch (family) {
+    case HFAV_FAMILY_HDIFF: c.block = 256; c.seg = 32; break;
+    case HFAV_FAMILY_EULER_X: c.block = 128; break;
+    case HFAV_FAMILY_EULER_Y: c.block = 64; c.seg = 16; break;
+    case HFAV_FAMILY_LAP7_CHAIN: c.block = 256; c.seg = 32; c.variant = 0; break;
+    default: break;
+    }
+    (void)dtype;
+    (void)dims;
+    return c;
+}
+
+// nearest entry of the same family and dtype, distance in log2 of the dims
+bool hfav_tuned_config(int family, int dtype, const int dims[3], hfav_config *cfg) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    double best = 1e30;
+    bool found = false;
+    for (const Entry &e : g_table) {
+        if (e.family != family || e.dtype != dtype) continue;
+        double dist = 0.0;
+        for (int ax = 0; ax < 3; ++ax) {
+            double a = std::log2((double)e.dims[ax]), b = std::log2((double)dims[ax]);
+            dist += (a - b) * (a - b);
+        }
+        if (dist < best) {
+            best = dist;
+            *cfg = e.cfg;
+            found = true;
+        }
+    }
+    return found;
+}
+
+extern "C" void hfav_tuning_clear(void) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_table.clear();
+}
+
+extern "C" int hfav_tuning_add(int family, int dtype, const int dims[3], const hfav_config *cfg) {
+    if (!dims || !cfg || cfg->block <= 0) return HFAV_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    Entry e;
+    e.family = family;
+    e.dtype = dtype;
+    for (int ax = 0; ax < 3; ++ax) e.dims[ax] = dims[ax] > 0 ? dims[ax] : 1;
+    e.cfg = *cfg;
+    g_table.push_back(e);
+    return HFAV_OK;
+}
+
+extern "C" int hfav_tuning_size(void) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    return (int)g_table.size();
+}

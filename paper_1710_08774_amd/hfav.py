@@ -1,0 +1,380 @@
+"""ctypes binding of libhfav.so: argument marshalling only.
+
+Every step of the fused and unfused paths runs in the library's HIP kernels;
+this module only converts Python chain descriptions into the C descriptor,
+and torch tensors (or raw device addresses) into pointers.  If libhfav.so is
+missing the import fails: there is no Python or CPU fallback.
+
+Names follow the C ABI (include/hfav.h): chain_create, plan, execute,
+chain_destroy, last_error, plan_term, plan_json.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import json
+import os
+from dataclasses import dataclass, field
+from typing import Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhfav.so")
+
+# ----------------------------------------------------------------- constants
+OK, EINVAL, EUNSAT, EDUP, ECYCLE, EUNSUP, EALIAS, ENOPLAN, EDEVICE = range(9)
+STATUS = {0: "OK", 1: "EINVAL", 2: "EUNSAT", 3: "EDUP", 4: "ECYCLE", 5: "EUNSUP", 6: "EALIAS",
+          7: "ENOPLAN", 8: "EDEVICE"}
+F64, F32 = 0, 1
+OP = {
+    "HDIFF_LAP": 1, "HDIFF_FLX": 2, "HDIFF_FLY": 3, "HDIFF_OUT": 4,
+    "EULER_PRIM": 10, "EULER_SLOPE": 11, "EULER_TRACE": 12, "EULER_RIEMANN": 13,
+    "EULER_FLUX": 14, "EULER_UPDATE": 15, "EULER_SMAX": 16, "EULER_DT": 17,
+    "LAP7": 20, "AXPY": 21, "STAR": 22,
+}
+REDUCE_NONE, REDUCE_MAX = 0, 1
+BC_PERIODIC, BC_TRANSMISSIVE = 0, 1
+MODE_AUTO, MODE_FUSED, MODE_UNFUSED = 0, 1, 2
+PREC_NATIVE, PREC_F32_F64ACC = 0, 1
+CONFIG_DEFAULT, CONFIG_TUNED, CONFIG_MODEL, CONFIG_FORCED = 0, 1, 2, 3
+FAMILY = {0: "none", 1: "hdiff", 2: "euler_x", 3: "euler_y", 4: "lap7_chain", 5: "star_chain", 6: "smax"}
+STORAGE = {0: "full", 1: "register", 2: "inner", 3: "outer", 4: "scalar"}
+MAX_RULES = 64
+
+
+class hfav_ref(C.Structure):
+    _fields_ = [("term", C.c_char_p), ("off", C.c_int * 3)]
+
+
+class hfav_rule(C.Structure):
+    _fields_ = [("op", C.c_int), ("n_in", C.c_int), ("in_", C.POINTER(hfav_ref)),
+                ("n_out", C.c_int), ("out", C.POINTER(C.c_char_p)),
+                ("n_param", C.c_int), ("param", C.POINTER(C.c_double)), ("reduce", C.c_int)]
+
+
+class hfav_term_decl(C.Structure):
+    _fields_ = [("name", C.c_char_p), ("rank", C.c_int)]
+
+
+class hfav_chain_desc(C.Structure):
+    _fields_ = [("ndim", C.c_int), ("loop_order", C.c_char_p), ("dtype", C.c_int),
+                ("n_axiom", C.c_int), ("axioms", C.POINTER(hfav_term_decl)),
+                ("n_goal", C.c_int), ("goals", C.POINTER(C.c_char_p)),
+                ("n_rule", C.c_int), ("rules", C.POINTER(hfav_rule))]
+
+
+class hfav_config(C.Structure):
+    _fields_ = [("block", C.c_int), ("tile_y", C.c_int), ("seg", C.c_int), ("variant", C.c_int)]
+
+
+class hfav_plan_opts(C.Structure):
+    _fields_ = [("dims", C.c_int * 3), ("boundary", C.c_int * 3), ("mode", C.c_int),
+                ("precision", C.c_int), ("config_source", C.c_int), ("forced", hfav_config)]
+
+
+class hfav_plan_info(C.Structure):
+    _fields_ = [("n_rules", C.c_int), ("rule_order", C.c_int * MAX_RULES), ("n_nests", C.c_int),
+                ("nest_of_rule", C.c_int * MAX_RULES), ("phase_of_rule", C.c_int * MAX_RULES),
+                ("family", C.c_int), ("fused", C.c_int), ("streamed_axis", C.c_int),
+                ("config", hfav_config), ("config_source", C.c_int),
+                ("footprint_unfused", C.c_int64), ("footprint_contracted", C.c_int64),
+                ("max_window", C.c_int), ("bytes_per_cell_fused", C.c_double),
+                ("bytes_per_cell_unfused", C.c_double), ("workspace_bytes", C.c_size_t)]
+
+
+class hfav_term_info(C.Structure):
+    _fields_ = [("name", C.c_char_p), ("kind", C.c_int), ("rank", C.c_int), ("producer", C.c_int),
+                ("ext_lo", C.c_int * 3), ("ext_hi", C.c_int * 3), ("storage", C.c_int),
+                ("window_axis", C.c_int), ("window", C.c_int)]
+
+
+# ----------------------------------------------------------------- library
+_lib = None
+EXPORTS = ["hfav_chain_create", "hfav_plan", "hfav_execute", "hfav_chain_destroy", "hfav_last_error",
+           "hfav_version", "hfav_num_terms", "hfav_plan_term", "hfav_plan_json",
+           "hfav_tuning_clear", "hfav_tuning_add", "hfav_tuning_size"]
+
+
+def lib():
+    """Load libhfav.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_1710_08774_amd/build.py "
+                          "(there is no fallback implementation)")
+    L = C.CDLL(LIB_PATH)
+    L.hfav_chain_create.argtypes = [C.POINTER(hfav_chain_desc), C.POINTER(C.c_void_p)]
+    L.hfav_plan.argtypes = [C.c_void_p, C.POINTER(hfav_plan_opts), C.POINTER(hfav_plan_info)]
+    L.hfav_execute.argtypes = [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_void_p,
+                               C.c_void_p]
+    L.hfav_chain_destroy.argtypes = [C.c_void_p]
+    L.hfav_chain_destroy.restype = None
+    L.hfav_last_error.restype = C.c_char_p
+    L.hfav_version.restype = C.c_char_p
+    L.hfav_num_terms.argtypes = [C.c_void_p]
+    L.hfav_plan_term.argtypes = [C.c_void_p, C.c_int, C.POINTER(hfav_term_info)]
+    L.hfav_plan_json.argtypes = [C.c_void_p]
+    L.hfav_plan_json.restype = C.c_char_p
+    L.hfav_tuning_clear.restype = None
+    L.hfav_tuning_add.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(hfav_config)]
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    return lib().hfav_last_error().decode()
+
+
+def version() -> str:
+    return lib().hfav_version().decode()
+
+
+class HfavError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _check(rc):
+    if rc != OK:
+        raise HfavError(rc, last_error())
+
+
+# ----------------------------------------------------------------- chain spec
+@dataclass
+class Rule:
+    op: str
+    inputs: Sequence           # (term, (di, dj, dk)) pairs
+    outputs: Sequence[str]
+    params: Sequence[float] = ()
+    reduce: int = REDUCE_NONE
+
+
+@dataclass
+class ChainSpec:
+    ndim: int
+    axioms: Sequence           # (name, rank) pairs
+    goals: Sequence[str]
+    rules: Sequence[Rule]
+    dtype: int = F64
+    loop_order: str | None = None
+    _keep: list = field(default_factory=list, repr=False)
+
+    def to_c(self):
+        keep = []
+        axs = (hfav_term_decl * len(self.axioms))(*[hfav_term_decl(n.encode(), r) for n, r in self.axioms])
+        goals = (C.c_char_p * len(self.goals))(*[g.encode() for g in self.goals])
+        crules = (hfav_rule * max(1, len(self.rules)))()
+        for q, r in enumerate(self.rules):
+            refs = (hfav_ref * len(r.inputs))()
+            for m, (t, off) in enumerate(r.inputs):
+                o = tuple(off) + (0,) * (3 - len(off))
+                refs[m] = hfav_ref(t.encode(), (C.c_int * 3)(*o))
+            outs = (C.c_char_p * len(r.outputs))(*[o.encode() for o in r.outputs])
+            params = (C.c_double * max(1, len(r.params)))(*[float(p) for p in r.params])
+            crules[q] = hfav_rule(OP[r.op] if isinstance(r.op, str) else int(r.op), len(r.inputs), refs,
+                                  len(r.outputs), outs, len(r.params), params, int(r.reduce))
+            keep += [refs, outs, params]
+        d = hfav_chain_desc(self.ndim, self.loop_order.encode() if self.loop_order else None, self.dtype,
+                            len(self.axioms), axs, len(self.goals), goals, len(self.rules), crules)
+        keep += [axs, goals, crules]
+        return d, keep
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+class Chain:
+    """A created chain handle (hfav_chain_create) with plan and execute."""
+
+    def __init__(self, spec: ChainSpec):
+        self.spec = spec
+        d, keep = spec.to_c()
+        h = C.c_void_p()
+        _check(lib().hfav_chain_create(C.byref(d), C.byref(h)))
+        self._h = h
+        self.info = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.hfav_chain_destroy(h)
+            self._h = None
+
+    def plan(self, dims, boundary=(BC_PERIODIC,) * 3, mode=MODE_AUTO, precision=PREC_NATIVE,
+             config_source=CONFIG_DEFAULT, forced=None) -> hfav_plan_info:
+        dims = tuple(int(x) for x in dims) + (1,) * (3 - len(dims))
+        bnd = tuple(boundary) + (BC_PERIODIC,) * (3 - len(boundary))
+        f = hfav_config(*(forced if forced is not None else (0, 0, 0, 0)))
+        o = hfav_plan_opts((C.c_int * 3)(*dims), (C.c_int * 3)(*bnd), mode, precision, config_source, f)
+        info = hfav_plan_info()
+        _check(lib().hfav_plan(self._h, C.byref(o), C.byref(info)))
+        self.info = info
+        self.dims = dims
+        return info
+
+    def execute(self, axioms, goals, workspace=None, stream=None):
+        """Enqueue on `stream` (torch.cuda.Stream, raw handle, or None = current)."""
+        ax = (C.c_void_p * len(axioms))(*[_ptr(a) for a in axioms])
+        go = (C.c_void_p * len(goals))(*[_ptr(g) for g in goals])
+        if stream is None:
+            import torch
+            s = torch.cuda.current_stream().cuda_stream
+        elif isinstance(stream, int):
+            s = stream
+        else:
+            s = stream.cuda_stream
+        _check(lib().hfav_execute(self._h, ax, go, _ptr(workspace), s))
+
+    def execute_status(self, axioms, goals, workspace=None, stream=0):
+        """Like execute but returns the status code instead of raising."""
+        ax = (C.c_void_p * len(axioms))(*[_ptr(a) for a in axioms])
+        go = (C.c_void_p * len(goals))(*[_ptr(g) for g in goals])
+        return lib().hfav_execute(self._h, ax, go, _ptr(workspace), stream)
+
+    def num_terms(self):
+        return lib().hfav_num_terms(self._h)
+
+    def term(self, index) -> dict:
+        ti = hfav_term_info()
+        _check(lib().hfav_plan_term(self._h, index, C.byref(ti)))
+        return {"name": ti.name.decode(), "kind": ti.kind, "rank": ti.rank, "producer": ti.producer,
+                "lo": tuple(ti.ext_lo), "hi": tuple(ti.ext_hi), "storage": STORAGE[ti.storage],
+                "window_axis": ti.window_axis, "window": ti.window}
+
+    def terms(self) -> dict:
+        return {t["name"]: t for t in (self.term(q) for q in range(self.num_terms()))}
+
+    def plan_json(self) -> dict:
+        s = lib().hfav_plan_json(self._h)
+        if s is None:
+            raise HfavError(ENOPLAN, last_error())
+        return json.loads(s.decode())
+
+
+def chain_create(spec: ChainSpec) -> Chain:
+    return Chain(spec)
+
+
+def tuning_clear():
+    lib().hfav_tuning_clear()
+
+
+def tuning_add(family, dtype, dims, cfg):
+    d = (C.c_int * 3)(*(tuple(dims) + (1,) * (3 - len(dims))))
+    c = hfav_config(*cfg)
+    _check(lib().hfav_tuning_add(int(family), int(dtype), d, C.byref(c)))
+
+
+def tuning_size():
+    return lib().hfav_tuning_size()
+
+
+# ----------------------------------------------------------------- workload chains
+def hdiff_spec(coeff=0.025, dtype=F64, loop_order=None) -> ChainSpec:
+    """COSMO horizontal diffusion (Performance, "COSMO Micro-Kernels")."""
+    z = (0, 0, 0)
+    return ChainSpec(
+        ndim=3, dtype=dtype, loop_order=loop_order, axioms=[("u", 3)], goals=["out"],
+        rules=[
+            Rule("HDIFF_LAP", [("u", z), ("u", (1, 0, 0)), ("u", (-1, 0, 0)), ("u", (0, 1, 0)),
+                               ("u", (0, -1, 0))], ["lap"]),
+            Rule("HDIFF_FLX", [("lap", z), ("lap", (1, 0, 0)), ("u", z), ("u", (1, 0, 0))], ["flx"]),
+            Rule("HDIFF_FLY", [("lap", z), ("lap", (0, 1, 0)), ("u", z), ("u", (0, 1, 0))], ["fly"]),
+            Rule("HDIFF_OUT", [("u", z), ("flx", z), ("flx", (-1, 0, 0)), ("fly", z), ("fly", (0, -1, 0))],
+                 ["out"], [coeff]),
+        ])
+
+
+EULER_AXIOMS = ("rho", "mx", "my", "E")
+EULER_GOALS = ("rho_n", "mx_n", "my_n", "E_n")
+
+
+def euler_sweep_spec(direction, gamma=1.4, niter=10, cfl=0.5, dt_source="smax", with_smax=False,
+                     dtype=F64) -> ChainSpec:
+    """One directional Godunov sweep (Performance, "Hydro2D").
+
+    direction 0 sweeps x (normal momentum mx), 1 sweeps y (normal momentum my).
+    dt_source "smax": a 0-D axiom `smax` and a 0-D rule dt = cfl/smax;
+    "dt": a 0-D axiom `dt`.  with_smax adds the CFL reduction of the updated
+    state as a 0-D goal `smax_n`.
+    """
+    e = (1, 0, 0) if direction == 0 else (0, 1, 0)
+    me = tuple(-x for x in e)
+    z = (0, 0, 0)
+    rho, mx, my, E = EULER_AXIOMS
+    mn, mt = (mx, my) if direction == 0 else (my, mx)
+    gmn, gmt = ("mx_n", "my_n") if direction == 0 else ("my_n", "mx_n")
+    prim = ["w_r", "w_un", "w_ut", "w_p", "w_c"]
+    slopes = ["d_r", "d_un", "d_ut", "d_p"]
+    plus = ["fp_r", "fp_un", "fp_ut", "fp_p"]
+    minus = ["fm_r", "fm_un", "fm_ut", "fm_p"]
+    gst = ["g_r", "g_un", "g_ut", "g_p"]
+    flx = ["F_r", "F_mn", "F_mt", "F_E"]
+    rules = []
+    axioms = [(rho, 2), (mx, 2), (my, 2), (E, 2)]
+    if dt_source == "smax":
+        axioms.append(("smax", 0))
+        rules.append(Rule("EULER_DT", [("smax", z)], ["dt"], [cfl]))
+    else:
+        axioms.append(("dt", 0))
+    rules += [
+        Rule("EULER_PRIM", [(rho, z), (mn, z), (mt, z), (E, z)], prim, [gamma]),
+        Rule("EULER_SLOPE", [(w, o) for w in prim[:4] for o in (me, z, e)], slopes),
+        Rule("EULER_TRACE", [(w, z) for w in prim] + [(d, z) for d in slopes] + [("dt", z)], plus + minus),
+        Rule("EULER_RIEMANN", [(w, z) for w in plus] + [(w, e) for w in minus], gst, [gamma, niter]),
+        Rule("EULER_FLUX", [(w, z) for w in gst], flx, [gamma]),
+        Rule("EULER_UPDATE", [(rho, z), (mn, z), (mt, z), (E, z)] + [(f, z) for f in flx] +
+             [(f, me) for f in flx] + [("dt", z)], ["rho_n", gmn, gmt, "E_n"]),
+    ]
+    goals = list(EULER_GOALS)
+    if with_smax:
+        rules.append(Rule("EULER_SMAX", [("rho_n", z), ("mx_n", z), ("my_n", z), ("E_n", z)], ["smax_n"],
+                          [gamma], REDUCE_MAX))
+        goals.append("smax_n")
+    return ChainSpec(ndim=2, dtype=dtype, axioms=axioms, goals=goals, rules=rules)
+
+
+def smax_spec(gamma=1.4, dtype=F64) -> ChainSpec:
+    """The CFL reduction alone (initial time step)."""
+    z = (0, 0, 0)
+    return ChainSpec(ndim=2, dtype=dtype, axioms=[(a, 2) for a in EULER_AXIOMS], goals=["smax"],
+                     rules=[Rule("EULER_SMAX", [(a, z) for a in EULER_AXIOMS], ["smax"], [gamma], REDUCE_MAX)])
+
+
+def lap7_refs(t):
+    return [(t, (0, 0, 0)), (t, (1, 0, 0)), (t, (-1, 0, 0)), (t, (0, 1, 0)), (t, (0, -1, 0)),
+            (t, (0, 0, 1)), (t, (0, 0, -1))]
+
+
+def biharm_spec(nu=1.0 / 128.0, dtype=F64) -> ChainSpec:
+    """lap1 = L7(u), lap2 = L7(lap1), out = u - nu*lap2 on a 3-D box."""
+    return ChainSpec(ndim=3, dtype=dtype, axioms=[("u", 3)], goals=["out"],
+                     rules=[Rule("LAP7", lap7_refs("u"), ["lap1"]),
+                            Rule("LAP7", lap7_refs("lap1"), ["lap2"]),
+                            Rule("AXPY", [("u", (0, 0, 0)), ("lap2", (0, 0, 0))], ["out"], [-nu])])
+
+
+def star_chain_spec(chain: dict, offsets_fn) -> ChainSpec:
+    """Random linear star chain (dict from inputs.random_chain) as STAR rules."""
+    nd = chain["ndim"]
+    dtype = F64 if chain["dtype"] == "f64" else F32
+    stages = chain["stages"]
+    names = [[f"x{f}" for f in range(chain["n_in"])]]
+    rules = []
+    for s, st in enumerate(stages):
+        offs = offsets_fn(nd, st["r"])
+        outs = [f"s{s}_{o}" if s + 1 < len(stages) else f"y{o}" for o in range(st["f_out"])]
+        for o in range(st["f_out"]):
+            refs, params = [], []
+            for f in range(st["f_in"]):
+                for q, off in enumerate(offs):
+                    refs.append((names[-1][f], off))
+                    params.append(float(st["coeff"][o, f, q]))
+            rules.append(Rule("STAR", refs, [outs[o]], params))
+        names.append(outs)
+    return ChainSpec(ndim=nd, dtype=dtype, axioms=[(n, nd) for n in names[0]], goals=names[-1], rules=rules)

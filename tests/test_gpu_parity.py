@@ -1,0 +1,234 @@
+"""GPU parity: the HIP fused and unfused paths against the FP64 CPU oracle.
+
+Every case calls the library through the C ABI (the ctypes binding) on
+seeded inputs shared with the oracle.  FP64 tolerance: 1e-12 normwise
+relative error per output field.  The bandwidth-bound chains evaluate each
+rule in the oracle's operation order without FMA contraction, so they are
+also required to match bit for bit.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import dev, field_errs, host, relerr
+from paper_1710_08774_amd import hfav as H
+from paper_1710_08774_amd import inputs
+from paper_1710_08774_amd.euler import EulerStepper
+
+pytestmark = pytest.mark.gpu
+TOL64 = 1e-12
+
+
+# ------------------------------------------------------------------ hdiff
+HDIFF_SHAPES = [(1, 8, 8), (3, 13, 7), (2, 65, 3), (1, 1, 40), (2, 100, 300), (8, 256, 256)]
+
+
+@pytest.mark.parametrize("shape", HDIFF_SHAPES)
+@pytest.mark.parametrize("mode", [H.MODE_FUSED, H.MODE_UNFUSED])
+def test_hdiff_parity(shape, mode):
+    nk, nj, ni = shape
+    a = inputs.hdiff_input(nk, nj, ni, seed=sum(shape) + 7)
+    ref = oracle.hdiff(a)
+    c = H.Chain(H.hdiff_spec())
+    info = c.plan((ni, nj, nk), mode=mode)
+    assert info.fused == (mode == H.MODE_FUSED)
+    u = dev(a)
+    out = torch.empty_like(u)
+    ws = torch.empty(info.workspace_bytes, dtype=torch.uint8, device="cuda") if info.workspace_bytes else None
+    c.execute([u], [out], ws)
+    got = host(out)
+    assert relerr(got, ref) <= TOL64
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("block,seg", [(64, 1), (64, 7), (128, 16), (512, 64)])
+def test_hdiff_tile_configs(block, seg):
+    a = inputs.hdiff_input(2, 70, 200, seed=3)
+    ref = oracle.hdiff(a)
+    c = H.Chain(H.hdiff_spec())
+    c.plan((200, 70, 2), mode=H.MODE_FUSED, config_source=H.CONFIG_FORCED, forced=(block, 1, seg, 0))
+    u = dev(a)
+    out = torch.empty_like(u)
+    c.execute([u], [out])
+    assert np.array_equal(host(out), ref)
+
+
+def test_hdiff_f32_error_bound():
+    a = inputs.hdiff_input(2, 64, 96, seed=4)
+    a32 = a.astype(np.float32).astype(np.float64)
+    ref = oracle.hdiff(a32)
+    c = H.Chain(H.hdiff_spec(dtype=H.F32))
+    c.plan((96, 64, 2))
+    u = dev(a, torch.float32)
+    out = torch.empty_like(u)
+    c.execute([u], [out])
+    assert relerr(host(out), ref) <= 4e-7
+
+
+# ------------------------------------------------------------------ euler, one sweep
+def _sweep_gpu(U, direction, dt, mode, bc=H.BC_PERIODIC, forced=None):
+    _, ny, nx = U.shape
+    c = H.Chain(H.euler_sweep_spec(direction, dt_source="dt"))
+    src = H.CONFIG_FORCED if forced else H.CONFIG_DEFAULT
+    info = c.plan((nx, ny), (bc, bc), mode=mode, config_source=src, forced=forced)
+    d = dev(U)
+    o = torch.empty_like(d)
+    dtt = torch.tensor([dt], dtype=torch.float64, device="cuda")
+    ws = torch.empty(info.workspace_bytes, dtype=torch.uint8, device="cuda") if info.workspace_bytes else None
+    c.execute([d[0], d[1], d[2], d[3], dtt], [o[0], o[1], o[2], o[3]], ws)
+    return host(o)
+
+
+@pytest.mark.parametrize("shape", [(8, 8), (48, 64), (37, 100), (5, 300), (130, 3)])
+@pytest.mark.parametrize("direction", [0, 1])
+@pytest.mark.parametrize("mode", [H.MODE_FUSED, H.MODE_UNFUSED])
+def test_euler_sweep_parity(shape, direction, mode):
+    ny, nx = shape
+    U = inputs.euler_ic(nx, ny, seed=nx * 31 + ny, amp=0.05)
+    dt = 0.5 / oracle.euler_smax(U)
+    ref = oracle.euler_sweep(U, direction, dt)
+    got = _sweep_gpu(U, direction, dt, mode)
+    assert max(field_errs(got, ref)) <= TOL64
+
+
+@pytest.mark.parametrize("direction,cfg", [(0, (64, 1, 0, 0)), (0, (256, 1, 0, 0)),
+                                           (1, (128, 1, 3, 0)), (1, (256, 1, 64, 0)), (1, (64, 1, 1, 0))])
+def test_euler_sweep_tile_configs(direction, cfg):
+    U = inputs.euler_ic(300, 70, seed=12, amp=0.05)
+    dt = 0.5 / oracle.euler_smax(U)
+    ref = oracle.euler_sweep(U, direction, dt)
+    got = _sweep_gpu(U, direction, dt, H.MODE_FUSED, forced=cfg)
+    assert max(field_errs(got, ref)) <= TOL64
+
+
+@pytest.mark.parametrize("direction", [0, 1])
+def test_euler_transmissive_sweep(direction):
+    n = 128
+    x = (np.arange(n) + 0.5) / n
+    rho = np.where(x < 0.5, 1.0, 0.125)
+    p = np.where(x < 0.5, 1.0, 0.1)
+    if direction == 0:
+        U = inputs.euler_state_from_prim(np.tile(rho, (3, 1)), 0.0, 0.0, np.tile(p, (3, 1)))
+    else:
+        U = inputs.euler_state_from_prim(np.tile(rho[:, None], (1, 3)), 0.0, 0.0, np.tile(p[:, None], (1, 3)))
+    for mode in (H.MODE_FUSED, H.MODE_UNFUSED):
+        V = U.copy()
+        W = U.copy()
+        for _ in range(10):
+            dt = 0.5 / oracle.euler_smax(V)
+            V = oracle.euler_sweep(V, direction, dt, bc=oracle.BC_TRANSMISSIVE)
+            W = _sweep_gpu(W, direction, dt, mode, bc=H.BC_TRANSMISSIVE)
+        assert max(field_errs(W, V)) <= TOL64
+
+
+def test_euler_constant_state_bitwise():
+    U = inputs.euler_state_from_prim(np.full((40, 70), 0.7), 0.3, -0.4, 1.9)
+    for d in (0, 1):
+        for mode in (H.MODE_FUSED, H.MODE_UNFUSED):
+            assert np.array_equal(_sweep_gpu(U, d, 0.1, mode), U)
+
+
+# ------------------------------------------------------------------ euler, time stepping
+@pytest.mark.parametrize("mode", [H.MODE_FUSED, H.MODE_UNFUSED])
+def test_euler_run_parity(mode):
+    nx, ny, steps = 96, 80, 30
+    U = inputs.euler_ic(nx, ny, seed=101)
+    ref, dts = oracle.euler_run(U, steps)
+    st = EulerStepper(nx, ny, mode=mode)
+    st.load(U)
+    st.step(steps)
+    got = host(st.state())
+    assert max(field_errs(got, ref)) <= TOL64
+
+
+def test_euler_config_workload_two_steps_full_size():
+    # the benchmark configuration (2048^2, FP64, periodic), compared in full
+    nx = ny = 2048
+    U = inputs.euler_ic(nx, ny)
+    ref, _ = oracle.euler_run(U, 2)
+    st = EulerStepper(nx, ny)
+    st.load(U)
+    st.step(2)
+    got = host(st.state())
+    assert max(field_errs(got, ref)) <= TOL64
+
+
+def test_euler_hundred_steps_parity():
+    nx, ny = 256, 192
+    U = inputs.euler_ic(nx, ny, seed=7)
+    ref, _ = oracle.euler_run(U, 100)
+    st = EulerStepper(nx, ny)
+    st.load(U)
+    st.step(100)
+    assert max(field_errs(host(st.state()), ref)) <= TOL64
+
+
+def test_fused_matches_unfused_stepper():
+    nx, ny = 150, 70
+    U = inputs.euler_ic(nx, ny, seed=9)
+    a = EulerStepper(nx, ny, mode=H.MODE_FUSED)
+    b = EulerStepper(nx, ny, mode=H.MODE_UNFUSED)
+    a.load(U)
+    b.load(U)
+    a.step(10)
+    b.step(10)
+    # identical rule bodies; the two paths differ only in where the compiler
+    # forms fused multiply-adds (about one rounding per rule evaluation),
+    # which ten steps grow to the 1e-14 level
+    assert max(field_errs(host(a.state()), host(b.state()))) <= 1e-13
+
+
+def test_smax_reduction_matches_oracle():
+    U = inputs.euler_ic(333, 77, seed=2, amp=0.05)
+    st = EulerStepper(333, 77)
+    st.load(U)
+    torch.cuda.synchronize()
+    assert abs(float(st.smax[0]) - oracle.euler_smax(U)) <= 1e-15 * oracle.euler_smax(U)
+
+
+# ------------------------------------------------------------------ biharmonic
+@pytest.mark.parametrize("shape", [(8, 8, 8), (5, 9, 70), (20, 33, 130), (64, 64, 64)])
+@pytest.mark.parametrize("mode", [H.MODE_FUSED, H.MODE_UNFUSED])
+def test_biharm_parity(shape, mode):
+    nz, ny, nx = shape
+    u = inputs.biharm_input(shape=shape, seed=nx + ny + nz)
+    ref = oracle.biharm(u)
+    c = H.Chain(H.biharm_spec())
+    info = c.plan((nx, ny, nz), mode=mode)
+    d = dev(u)
+    o = torch.empty_like(d)
+    ws = torch.empty(info.workspace_bytes, dtype=torch.uint8, device="cuda") if info.workspace_bytes else None
+    c.execute([d], [o], ws)
+    got = host(o)
+    assert relerr(got, ref) <= TOL64
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
+def test_biharm_tile_variants(variant):
+    shape = (17, 40, 150)
+    u = inputs.biharm_input(shape=shape, seed=5)
+    ref = oracle.biharm(u)
+    c = H.Chain(H.biharm_spec())
+    c.plan((150, 40, 17), mode=H.MODE_FUSED, config_source=H.CONFIG_FORCED, forced=(256, 1, 5, variant))
+    d = dev(u)
+    o = torch.empty_like(d)
+    c.execute([d], [o])
+    assert np.array_equal(host(o), ref)
+
+
+def test_biharm_f32_error_bound():
+    shape = (32, 32, 32)
+    u = inputs.biharm_input(shape=shape, seed=8)
+    u32 = u.astype(np.float32).astype(np.float64)
+    ref_a = oracle.biharm(u32)    # arithmetic error only
+    ref_b = oracle.biharm(u)      # end to end
+    c = H.Chain(H.biharm_spec(dtype=H.F32))
+    c.plan((32, 32, 32))
+    d = dev(u, torch.float32)
+    o = torch.empty_like(d)
+    c.execute([d], [o])
+    got = host(o)
+    assert relerr(got, ref_a) <= 1e-6
+    assert relerr(got, ref_b) <= 1e-6
