@@ -1,0 +1,187 @@
+"""Benchmark: fused vs unfused split Godunov hydro chain on one MI355X.
+
+Workload: 2-D compressible Euler, directionally split Godunov step (prim ->
+van Leer slopes -> characteristic trace -> exact Riemann solver with 10
+Newton iterations -> flux -> conservative update, x sweep then y sweep,
+fused CFL reduction), FP64, 2048 x 2048 cells, periodic, gamma 1.4, CFL 0.5,
+Sod-like seeded initial state (synthetic stand-in for the Hydro2D input).
+A step is one x sweep plus one y sweep.  The state is resident in HBM
+before the timed region; dt stays on the device.
+
+Prints ONE JSON line.  `value` is fused cell-updates/s (cells x steps / s).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell-updates/s + % of 8 TB/s HBM, fused vs unfused on one MI355X"
+HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+NX = NY = 2048
+# Algorithmic FP64 operations per cell per sweep of the chain (each add, sub,
+# mul, div, sqrt and pow counted once): prim 13, slopes 28, trace 70, exact
+# Riemann solver with 10 Newton steps 311, flux 16, update 12.
+FLOPS_PER_CELL_SWEEP = 450
+COMPULSORY_BYTES_PER_CELL_SWEEP = 64      # 4 FP64 fields read once, written once
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("k_euler.hip", "ops.h"):
+        with open(os.path.join(ROOT, "paper_1710_08774_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when the kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "euler_sweeps_2048_traffic.json")
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+    except OSError:
+        return None
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    k = d.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("hbm_bytes_per_launch")
+
+
+def run_gpu(mode, steps, warmup, U0, timing=True):
+    import torch
+    from paper_1710_08774_amd import hfav as H
+    from paper_1710_08774_amd.euler import EulerStepper
+
+    st = EulerStepper(NX, NY, mode=mode)
+    st.load(U0)
+    st.step(warmup)
+    st.load(U0)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)] if timing else None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        if timing:
+            evs[s][0].record(stream)
+        st.sweep_x()
+        if timing:
+            evs[s][1].record(stream)
+        st.sweep_y()
+        st.slot = 1 - st.slot
+        if timing:
+            evs[s][2].record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    out = {"ms_per_step": (t1 - t0) * 1e3 / steps, "seconds": t1 - t0}
+    if timing:
+        out["x_ms"] = sum(e[0].elapsed_time(e[1]) for e in evs) / steps
+        out["y_ms"] = sum(e[1].elapsed_time(e[2]) for e in evs) / steps
+    out["state_finite"] = bool(torch.isfinite(st.state()).all())
+    out["info_fused"] = int(st.ix.fused and st.iy.fused)
+    return out
+
+
+def cpu_baseline(U0, budget_s=12.0):
+    import oracle
+    cores = oracle.num_threads()
+    U = U0.copy()
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        U, _ = oracle.euler_run(U, 1)
+        steps += 1
+        if time.perf_counter() - t0 >= budget_s or steps >= 50:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": NX * NY * steps / dt, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"FP64 oracle, {NX}x{NY} hydro chain, {steps} full steps from the initial state "
+                      f"({dt:.1f} s on {cores} OpenMP threads)"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-unfused", action="store_true")
+    ap.add_argument("--no-timing-events", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (counter calibration)")
+    a = ap.parse_args(argv)
+    if a.gpus != 1:
+        print(f"bench.py: this build measures one GPU only; --gpus {a.gpus} is not supported "
+              "(the chains would shard along the slowest axis with one halo exchange per chain; "
+              "that path is not built)", file=sys.stderr)
+        return 2
+    import torch
+    from paper_1710_08774_amd import hfav as H
+    from paper_1710_08774_amd import inputs
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    H.lib()
+    if a.copy_probe_mib:
+        n = a.copy_probe_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n * 8, "launches": 3}), flush=True)
+        return 0
+    U0 = inputs.euler_ic(NX, NY)
+    timing = not a.no_timing_events
+    fused = run_gpu(H.MODE_FUSED, a.steps, a.warmup, U0, timing)
+    unf = None if a.no_unfused else run_gpu(H.MODE_UNFUSED, a.steps, a.warmup, U0, timing)
+    cells = NX * NY
+    value = cells / (fused["ms_per_step"] * 1e-3)
+    line = {
+        "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": fused["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "euler2d-split-godunov-exact-riemann-2048x2048-f64", "grid": [NX, NY],
+                   "gamma": 1.4, "cfl": 0.5, "newton_iters": 10, "boundary": "periodic",
+                   "initial_state": "Sod-like split on a seeded random-angle line + 1e-3 sinusoidal modes",
+                   "path": "fused (one kernel per sweep, CFL reduction fused into the y sweep)"},
+        "hbm_compulsory": {
+            "bytes_per_cell_step": 2 * COMPULSORY_BYTES_PER_CELL_SWEEP,
+            "achieved_GBs": 2 * COMPULSORY_BYTES_PER_CELL_SWEEP * cells / (fused["ms_per_step"] * 1e-3) / 1e9,
+            "frac_of_8TBs": 2 * COMPULSORY_BYTES_PER_CELL_SWEEP * cells / (fused["ms_per_step"] * 1e-3) / 1e9
+            / HBM_PEAK_GBS},
+    }
+    if unf is not None:
+        line["unfused"] = {"value": cells / (unf["ms_per_step"] * 1e-3), "ms_per_step": unf["ms_per_step"],
+                           "x_ms": unf.get("x_ms"), "y_ms": unf.get("y_ms")}
+        line["fused_over_unfused"] = unf["ms_per_step"] / fused["ms_per_step"]
+    if timing:
+        kx, ky = fused["x_ms"], fused["y_ms"]
+        dom, dur = ("euler_x_kernel", kx) if kx >= ky else ("euler_y_kernel", ky)
+        flops = FLOPS_PER_CELL_SWEEP * cells
+        achieved = flops / (dur * 1e-3) / 1e12
+        line["roofline"] = {"bound": "alu", "kernel": dom, "achieved": achieved,
+                            "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                            "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": load_traffic(dom),
+                            "avg_launch_ms": dur, "x_sweep_ms": kx, "y_sweep_ms": ky,
+                            "flops_per_launch": flops}
+    if not a.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(U0)
+    line["state_finite"] = fused["state_finite"]
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

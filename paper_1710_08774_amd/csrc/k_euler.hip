@@ -62,12 +62,16 @@ __device__ __forceinline__ void slope_trace(const Prim<T> &wm, const Prim<T> &w0
 }
 
 // ------------------------------------------------------------------ x pass
-template <class T, class A, bool G14, int B>
-__global__ __launch_bounds__(B) void euler_x_kernel(EArgs<T> a) {
-    constexpr int R = 2 * B, M = R - 1;
-    __shared__ T s_w[5][R];     // primitive window ring (r, un, ut, p, c)
-    __shared__ T s_f[4][R];     // plus-face ring
-    __shared__ T s_F[4][R];     // interface flux ring: slot p holds F(p-1/2)
+template <class T, class A, bool G14, int B, int WPE>
+__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(WPE))) void euler_x_kernel(EArgs<T> a) {
+    // Rings of R = B + 4 slots indexed by cell modulo R: a chunk touches
+    // cells c0-2 .. c0+B, and a barrier separates every write of a slot from
+    // the last read of the cell it held before.
+    constexpr int R = B + 4;
+    __shared__ T s_w[5][R];     // primitive window (r, un, ut, p, c)
+    __shared__ T s_u[4][R];     // conserved state, read back by the update
+    __shared__ T s_f[4][R];     // plus-face state
+    __shared__ T s_F[4][R];     // interface flux: slot of cell p holds F(p-1/2)
     __shared__ T s_F0[4];       // F(-1/2) for the periodic wrap
     __shared__ T s_Fn[4];       // F(nx-1/2) for a transmissive right end
 
@@ -78,60 +82,74 @@ __global__ __launch_bounds__(B) void euler_x_kernel(EArgs<T> a) {
     const double dt = read_dt(a.dt_src, a.dt_mode, a.cfl);
     const T nu = (T)dt;
     const A nuA = (A)dt;
-
-    auto put_prim = [&](int cell) {
-        const int q = bwrap(cell, nx, a.bc);
-        const size_t o = row + q;
-        Prim<T> w = euler_prim(a.rho[o], a.mn[o], a.mt[o], a.E[o], g);
-        const int sl = cell & M;
-        s_w[0][sl] = w.r; s_w[1][sl] = w.un; s_w[2][sl] = w.ut; s_w[3][sl] = w.p; s_w[4][sl] = w.c;
+    int ob = 0;                 // slot of cell c0 (c0 mod R)
+    // slot of cell c0 + d for d in [-2, B + 1]
+    auto slot = [&](int d) {
+        int sl = ob + d;
+        sl += sl < 0 ? R : 0;
+        return sl >= R ? sl - R : sl;
     };
-    auto get_prim = [&](int cell) {
-        const int sl = cell & M;
+    auto load_cell = [&](int cell, T *u) {
+        const size_t o = row + bwrap(cell, nx, a.bc);
+        u[0] = a.rho[o]; u[1] = a.mn[o]; u[2] = a.mt[o]; u[3] = a.E[o];
+    };
+    auto put = [&](int sl, const T *u) {
+        Prim<T> w = euler_prim(u[0], u[1], u[2], u[3], g);
+        s_w[0][sl] = w.r; s_w[1][sl] = w.un; s_w[2][sl] = w.ut; s_w[3][sl] = w.p; s_w[4][sl] = w.c;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s_u[q][sl] = u[q];
+    };
+    auto get_prim = [&](int sl) {
         Prim<T> w;
         w.r = s_w[0][sl]; w.un = s_w[1][sl]; w.ut = s_w[2][sl]; w.p = s_w[3][sl]; w.c = s_w[4][sl];
         return w;
     };
 
     // prologue: cells -2, -1, 0 and the plus face of cell -1
-    if (t < 3) put_prim(t - 2);
+    if (t < 3) {
+        T u[4];
+        load_cell(t - 2, u);
+        put(slot(t - 2), u);
+    }
     __syncthreads();
     if (t == 0) {
         T plus[4], minus[4];
-        slope_trace(get_prim(-2), get_prim(-1), get_prim(0), nu, plus, minus);
-        const int sl = (-1) & M;
+        slope_trace(get_prim(slot(-2)), get_prim(slot(-1)), get_prim(slot(0)), nu, plus, minus);
+        const int sl = slot(-1);
 #pragma unroll
         for (int q = 0; q < 4; ++q) s_f[q][sl] = plus[q];
     }
-    __syncthreads();
 
     for (int c0 = 0; c0 < nx; c0 += B) {
+        ob = c0 % R;
         const int p = c0 + t;
         const bool act = p < nx;
-        // stage 1: primitive state of the cell entering the window
-        if (act) put_prim(p + 1);
+        const int sm = slot(t - 1), s0 = slot(t), sp = slot(t + 1);
+        // stage 1: conserved state of the cell entering the window
+        T unew[4];
+        if (act) load_cell(p + 1, unew);
+        __syncthreads();      // previous chunk's reads of these slots are done
+        if (act) put(sp, unew);
         __syncthreads();
         // stage 2: slopes + trace of cell p; the plus face goes to its right
         // neighbour through LDS, the minus face stays in registers
         T minus[4];
         if (act) {
             T plus[4];
-            slope_trace(get_prim(p - 1), get_prim(p), get_prim(p + 1), nu, plus, minus);
-            const int sl = p & M;
+            slope_trace(get_prim(sm), get_prim(s0), get_prim(sp), nu, plus, minus);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) s_f[q][sl] = plus[q];
+            for (int q = 0; q < 4; ++q) s_f[q][s0] = plus[q];
         }
         __syncthreads();
         // stage 3: Riemann problem and flux at interface p-1/2
         if (act) {
             T L[4], G[4], F[4];
-            const int sl = (p - 1) & M;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) L[q] = s_f[q][sl];
+            for (int q = 0; q < 4; ++q) L[q] = s_f[q][sm];
             riemann_T<T, G14>(L, minus, g, a.niter, G);
             euler_flux(G, g, F);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) s_F[q][p & M] = F[q];
+            for (int q = 0; q < 4; ++q) s_F[q][s0] = F[q];
             if (p == 0) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) s_F0[q] = F[q];
@@ -140,10 +158,9 @@ __global__ __launch_bounds__(B) void euler_x_kernel(EArgs<T> a) {
                 // right ghost cell copies cell nx-1 and has zero slopes, so
                 // its minus face is the primitive state of cell nx-1
                 T Lr[4], Rr[4], Gr[4];
-                const int sp = p & M;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) Lr[q] = s_f[q][sp];
-                Rr[0] = s_w[0][sp]; Rr[1] = s_w[1][sp]; Rr[2] = s_w[2][sp]; Rr[3] = s_w[3][sp];
+                for (int q = 0; q < 4; ++q) Lr[q] = s_f[q][s0];
+                Rr[0] = s_w[0][s0]; Rr[1] = s_w[1][s0]; Rr[2] = s_w[2][s0]; Rr[3] = s_w[3][s0];
                 riemann_T<T, G14>(Lr, Rr, g, a.niter, Gr);
                 euler_flux(Gr, g, s_Fn);
             }
@@ -152,20 +169,18 @@ __global__ __launch_bounds__(B) void euler_x_kernel(EArgs<T> a) {
         // stage 4: conservative update of cell p-1 (and of cell nx-1 at the end)
         if (act && p >= 1) {
             const size_t o = row + (p - 1);
-            const int s1 = (p - 1) & M, s2 = p & M;
-            a.orho[o] = euler_update(a.rho[o], s_F[0][s2], s_F[0][s1], nuA);
-            a.omn[o] = euler_update(a.mn[o], s_F[1][s2], s_F[1][s1], nuA);
-            a.omt[o] = euler_update(a.mt[o], s_F[2][s2], s_F[2][s1], nuA);
-            a.oE[o] = euler_update(a.E[o], s_F[3][s2], s_F[3][s1], nuA);
+            a.orho[o] = euler_update(s_u[0][sm], s_F[0][s0], s_F[0][sm], nuA);
+            a.omn[o] = euler_update(s_u[1][sm], s_F[1][s0], s_F[1][sm], nuA);
+            a.omt[o] = euler_update(s_u[2][sm], s_F[2][s0], s_F[2][sm], nuA);
+            a.oE[o] = euler_update(s_u[3][sm], s_F[3][s0], s_F[3][sm], nuA);
         }
         if (act && p == nx - 1) {
             const size_t o = row + p;
-            const int s1 = p & M;
             const T *Fp = a.bc == HFAV_BC_PERIODIC ? s_F0 : s_Fn;
-            a.orho[o] = euler_update(a.rho[o], Fp[0], s_F[0][s1], nuA);
-            a.omn[o] = euler_update(a.mn[o], Fp[1], s_F[1][s1], nuA);
-            a.omt[o] = euler_update(a.mt[o], Fp[2], s_F[2][s1], nuA);
-            a.oE[o] = euler_update(a.E[o], Fp[3], s_F[3][s1], nuA);
+            a.orho[o] = euler_update(s_u[0][s0], Fp[0], s_F[0][s0], nuA);
+            a.omn[o] = euler_update(s_u[1][s0], Fp[1], s_F[1][s0], nuA);
+            a.omt[o] = euler_update(s_u[2][s0], Fp[2], s_F[2][s0], nuA);
+            a.oE[o] = euler_update(s_u[3][s0], Fp[3], s_F[3][s0], nuA);
         }
     }
 }
@@ -187,10 +202,14 @@ __device__ __forceinline__ void block_max_to(double v, double *out) {
     }
 }
 
-template <class T, class A, bool G14, int B>
-__global__ __launch_bounds__(B) void euler_y_kernel(EArgs<T> a) {
+template <class T, class A, bool G14, int B, int WPE>
+__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(WPE))) void euler_y_kernel(EArgs<T> a) {
+    // each lane keeps the conserved state of its last three cells in its own
+    // LDS slots (read back two rows later by the update)
+    __shared__ T s_u[3][4][B];
     const int nx = a.nx, ny = a.ny;
-    const int i = blockIdx.x * B + threadIdx.x;
+    const int t = threadIdx.x;
+    const int i = blockIdx.x * B + t;
     const int j0 = blockIdx.y * a.seg;
     const int j1 = min(j0 + a.seg, ny);
     const T g = (T)a.g;
@@ -199,29 +218,35 @@ __global__ __launch_bounds__(B) void euler_y_kernel(EArgs<T> a) {
     const A nuA = (A)dt;
     double smax = 0.0;
     if (i < nx) {
-        auto P = [&](int jj) {
+        auto P = [&](int jj, int slot) {
             const size_t o = (size_t)bwrap(jj, ny, a.bc) * nx + i;
-            return euler_prim(a.rho[o], a.mn[o], a.mt[o], a.E[o], g);
+            const T r = a.rho[o], mn = a.mn[o], mt = a.mt[o], e = a.E[o];
+            if (slot >= 0) {
+                s_u[slot][0][t] = r; s_u[slot][1][t] = mn; s_u[slot][2][t] = mt; s_u[slot][3][t] = e;
+            }
+            return euler_prim(r, mn, mt, e, g);
         };
-        Prim<T> w0 = P(j0 - 2), w1 = P(j0 - 1), w2 = P(j0);
+        Prim<T> w0 = P(j0 - 2, -1), w1 = P(j0 - 1, -1), w2 = P(j0, 0);
         T fp[4], Fm[4];
         {
             T minus[4];
             slope_trace(w0, w1, w2, nu, fp, minus);     // plus face of cell j0-1
         }
-        // window: w1 = cell j-1, w2 = cell j
+        // window: w1 = cell j-1, w2 = cell j; cell j0 + m sits in slot m % 3
+        int snew = 1;                                   // slot of cell j+1
         for (int j = j0; j <= j1; ++j) {
-            const Prim<T> w3 = P(j + 1);
+            const Prim<T> w3 = P(j + 1, snew);
             T plus[4], minus[4], G[4], F[4];
             slope_trace(w1, w2, w3, nu, plus, minus);
             riemann_T<T, G14>(fp, minus, g, a.niter, G);
             euler_flux(G, g, F);                         // flux at j-1/2
             if (j > j0) {
+                const int su = snew == 2 ? 0 : snew + 1; // slot of cell j-1
                 const size_t o = (size_t)(j - 1) * nx + i;
-                const T r = euler_update(a.rho[o], F[0], Fm[0], nuA);
-                const T mn = euler_update(a.mn[o], F[1], Fm[1], nuA);
-                const T mt = euler_update(a.mt[o], F[2], Fm[2], nuA);
-                const T e = euler_update(a.E[o], F[3], Fm[3], nuA);
+                const T r = euler_update(s_u[su][0][t], F[0], Fm[0], nuA);
+                const T mn = euler_update(s_u[su][1][t], F[1], Fm[1], nuA);
+                const T mt = euler_update(s_u[su][2][t], F[2], Fm[2], nuA);
+                const T e = euler_update(s_u[su][3][t], F[3], Fm[3], nuA);
                 a.orho[o] = r; a.omn[o] = mn; a.omt[o] = mt; a.oE[o] = e;
                 if (a.smax_out) smax = fmax(smax, (double)euler_speed(r, mt, mn, e, g));
             }
@@ -229,6 +254,7 @@ __global__ __launch_bounds__(B) void euler_y_kernel(EArgs<T> a) {
             for (int q = 0; q < 4; ++q) { Fm[q] = F[q]; fp[q] = plus[q]; }
             w1 = w2;
             w2 = w3;
+            snew = snew == 2 ? 0 : snew + 1;
         }
     }
     if (a.smax_out) block_max_to<B>(smax, a.smax_out);
@@ -261,14 +287,20 @@ static EArgs<T> make_args(const EulerLaunch &L) {
     return a;
 }
 
+// variant 1 asks the compiler for at least 4 waves per SIMD (the register
+// budget drops to 128 and the Riemann solver's state partly spills)
+#define EX_LAUNCH(BB, W) hipLaunchKernelGGL((euler_x_kernel<T, A, G14, BB, W>), grid, dim3(BB), 0, s, a)
+#define EY_LAUNCH(BB, W) hipLaunchKernelGGL((euler_y_kernel<T, A, G14, BB, W>), grid, dim3(BB), 0, s, a)
+
 template <class T, class A, bool G14>
 static hipError_t euler_x_dispatch(const EulerLaunch &L, hipStream_t s) {
     EArgs<T> a = make_args<T>(L);
     dim3 grid(L.ny);
+    const bool w4 = L.cfg.variant == 1;
     switch (L.cfg.block) {
-    case 64: hipLaunchKernelGGL((euler_x_kernel<T, A, G14, 64>), grid, dim3(64), 0, s, a); break;
-    case 128: hipLaunchKernelGGL((euler_x_kernel<T, A, G14, 128>), grid, dim3(128), 0, s, a); break;
-    default: hipLaunchKernelGGL((euler_x_kernel<T, A, G14, 256>), grid, dim3(256), 0, s, a); break;
+    case 64: if (w4) EX_LAUNCH(64, 4); else EX_LAUNCH(64, 1); break;
+    case 128: if (w4) EX_LAUNCH(128, 4); else EX_LAUNCH(128, 1); break;
+    default: if (w4) EX_LAUNCH(256, 4); else EX_LAUNCH(256, 1); break;
     }
     return hipGetLastError();
 }
@@ -278,13 +310,16 @@ static hipError_t euler_y_dispatch(const EulerLaunch &L, hipStream_t s) {
     EArgs<T> a = make_args<T>(L);
     const int B = (L.cfg.block == 64 || L.cfg.block == 128 || L.cfg.block == 256) ? L.cfg.block : 64;
     dim3 grid((L.nx + B - 1) / B, (L.ny + a.seg - 1) / a.seg);
+    const bool w4 = L.cfg.variant == 1;
     switch (B) {
-    case 128: hipLaunchKernelGGL((euler_y_kernel<T, A, G14, 128>), grid, dim3(128), 0, s, a); break;
-    case 256: hipLaunchKernelGGL((euler_y_kernel<T, A, G14, 256>), grid, dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL((euler_y_kernel<T, A, G14, 64>), grid, dim3(64), 0, s, a); break;
+    case 128: if (w4) EY_LAUNCH(128, 4); else EY_LAUNCH(128, 1); break;
+    case 256: if (w4) EY_LAUNCH(256, 4); else EY_LAUNCH(256, 1); break;
+    default: if (w4) EY_LAUNCH(64, 4); else EY_LAUNCH(64, 1); break;
     }
     return hipGetLastError();
 }
+#undef EX_LAUNCH
+#undef EY_LAUNCH
 
 template <bool X>
 static hipError_t euler_dispatch(const EulerLaunch &L, hipStream_t s) {

@@ -9,7 +9,9 @@
 // rotation of rows); the Laplacian window (rows j and j+1, columns i-1..i+1)
 // and the y-flux window (rows j-1 and j) live in registers, and the x flux at
 // i-1 is recomputed by the lane from the same registers instead of being
-// exchanged.  One barrier per row.
+// exchanged.  One barrier per row.  Row loads are software-pipelined P rows
+// ahead through registers so that enough bytes are in flight per CU to cover
+// HBM latency.
 #include <hip/hip_runtime.h>
 #include "kernels.h"
 #include "ops.h"
@@ -29,7 +31,7 @@ __device__ __forceinline__ int pwrap(int i, int n) {
     return i < 0 ? i + n : i;
 }
 
-template <class T, int B>
+template <class T, int B, int P>
 __global__ __launch_bounds__(B) void hdiff_kernel(HArgs<T> a) {
     constexpr int W = B + 4;              // row slot: columns i0-2 .. i0+B+1
     __shared__ T ring[4][W];
@@ -46,45 +48,65 @@ __global__ __launch_bounds__(B) void hdiff_kernel(HArgs<T> a) {
     const int col = pwrap(i0 + t, ni);
     const int hs = t < 2 ? t : t + B;     // halo slot for lanes 0..3
     const int hcol = pwrap(i0 - 2 + hs, ni);
+    const bool halo = t < 4;
 
-    auto load_row = [&](int j) {
+    auto fetch = [&](int j, T &v, T &h) {
         const T *r = plane + (size_t)pwrap(j, nj) * ni;
+        v = r[col];
+        if (halo) h = r[hcol];
+    };
+    auto commit = [&](int j, T v, T h) {
         T *s = ring[j & 3];
-        s[t + 2] = r[col];
-        if (t < 4) s[hs] = r[hcol];
+        s[t + 2] = v;
+        if (halo) s[hs] = h;
     };
     auto L = [&](int j, int d) { return ring[j & 3][t + 2 + d]; };
     auto lap_at = [&](int j, int d) {
         return hdiff_lap(L(j, d), L(j, d + 1), L(j, d - 1), L(j + 1, d), L(j - 1, d));
     };
 
+    // software pipeline: rows j+2 .. j+1+P are in flight in registers while
+    // row j is computed, so each workgroup keeps P row loads outstanding
+    T pv[P], ph[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        ph[q] = T(0);
+        if (j0 + 2 + q <= j1 + 1) fetch(j0 + 2 + q, pv[q], ph[q]);
+    }
     // prologue: rows j0-2 .. j0+1, the Laplacian of rows j0-1 (centre) and
     // j0 (three columns), and the y flux of row j0-1
-    load_row(j0 - 2);
-    load_row(j0 - 1);
-    load_row(j0);
-    load_row(j0 + 1);
+    for (int r = -2; r <= 1; ++r) {
+        T v, h = T(0);
+        fetch(j0 + r, v, h);
+        commit(j0 + r, v, h);
+    }
     __syncthreads();
     T lm1 = lap_at(j0 - 1, 0);
     T la = lap_at(j0, -1), lb = lap_at(j0, 0), lc = lap_at(j0, 1);
     T fym = hdiff_flux(lm1, lb, L(j0 - 1, 0), L(j0, 0));
     __syncthreads();
 
-    for (int j = j0; j < j1; ++j) {
-        load_row(j + 2);                    // overwrites row j-2's slot
-        __syncthreads();
-        // Laplacian of row j+1 at columns i-1, i, i+1
-        const T na = lap_at(j + 1, -1), nb = lap_at(j + 1, 0), nc = lap_at(j + 1, 1);
-        const T u = L(j, 0);
-        const T fx0 = hdiff_flux(lb, lc, u, L(j, 1));
-        const T fxm = hdiff_flux(la, lb, L(j, -1), u);
-        const T fy0 = hdiff_flux(lb, nb, u, L(j + 1, 0));
-        if (i0 + t < ni) oplane[(size_t)j * ni + i0 + t] = hdiff_out(u, fx0, fxm, fy0, fym, a.coeff);
-        fym = fy0;
-        la = na; lb = nb; lc = nc;
-        // no second barrier: the next write goes to row j-1's slot, which no
-        // lane still in this step reads, and a lane cannot run two rows ahead
-        // of the post-load barrier
+    for (int jb = j0; jb < j1; jb += P) {
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            const int j = jb + q;
+            if (j >= j1) break;
+            commit(j + 2, pv[q], ph[q]);        // overwrites row j-2's slot
+            if (j + 2 + P <= j1 + 1) fetch(j + 2 + P, pv[q], ph[q]);
+            __syncthreads();
+            // Laplacian of row j+1 at columns i-1, i, i+1
+            const T na = lap_at(j + 1, -1), nb = lap_at(j + 1, 0), nc = lap_at(j + 1, 1);
+            const T u = L(j, 0);
+            const T fx0 = hdiff_flux(lb, lc, u, L(j, 1));
+            const T fxm = hdiff_flux(la, lb, L(j, -1), u);
+            const T fy0 = hdiff_flux(lb, nb, u, L(j + 1, 0));
+            if (i0 + t < ni) oplane[(size_t)j * ni + i0 + t] = hdiff_out(u, fx0, fxm, fy0, fym, a.coeff);
+            fym = fy0;
+            la = na; lb = nb; lc = nc;
+            // no second barrier: the next write goes to row j-1's slot, which
+            // no lane still in this step reads, and a lane cannot run two rows
+            // ahead of the post-commit barrier
+        }
     }
 }
 
@@ -98,13 +120,25 @@ static hipError_t hdiff_dispatch(const HdiffLaunch &L, hipStream_t s) {
     a.coeff = (T)L.coeff;
     int B = L.cfg.block;
     if (B != 64 && B != 128 && B != 256 && B != 512) B = 256;
+    // variant: prefetch depth (rows in flight per workgroup) 1, 2, 4 or 8
+    const int P = L.cfg.variant == 1 ? 1 : L.cfg.variant == 2 ? 2 : L.cfg.variant == 4 ? 8 : 4;
     dim3 grid((L.ni + B - 1) / B, (L.nj + a.seg - 1) / a.seg, L.nk);
-    switch (B) {
-    case 64: hipLaunchKernelGGL((hdiff_kernel<T, 64>), grid, dim3(64), 0, s, a); break;
-    case 128: hipLaunchKernelGGL((hdiff_kernel<T, 128>), grid, dim3(128), 0, s, a); break;
-    case 512: hipLaunchKernelGGL((hdiff_kernel<T, 512>), grid, dim3(512), 0, s, a); break;
-    default: hipLaunchKernelGGL((hdiff_kernel<T, 256>), grid, dim3(256), 0, s, a); break;
+#define HD_LAUNCH(BB, PP) hipLaunchKernelGGL((hdiff_kernel<T, BB, PP>), grid, dim3(BB), 0, s, a)
+#define HD_P(BB)                               \
+    switch (P) {                               \
+    case 1: HD_LAUNCH(BB, 1); break;           \
+    case 2: HD_LAUNCH(BB, 2); break;           \
+    case 8: HD_LAUNCH(BB, 8); break;           \
+    default: HD_LAUNCH(BB, 4); break;          \
     }
+    switch (B) {
+    case 64: HD_P(64); break;
+    case 128: HD_P(128); break;
+    case 512: HD_P(512); break;
+    default: HD_P(256); break;
+    }
+#undef HD_P
+#undef HD_LAUNCH
     return hipGetLastError();
 }
 

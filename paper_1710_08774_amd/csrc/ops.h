@@ -103,28 +103,27 @@ __device__ __forceinline__ void euler_trace(const Prim<T>& w, T dr, T du, T dv, 
     minus[3] = w.p - cc * (cm0 + cm3);
 }
 
+// Reciprocal from the hardware estimate refined by one Newton step
+// (relative error about one unit in the last place).
+__device__ __forceinline__ double frcp(double d) {
+    const double r = __builtin_amdgcn_rcp(d);
+    return fma(r, fma(-d, r, 1.0), r);
+}
+
 // x^(-1/7) for x > 0: a single-precision hardware log2/exp2 estimate
-// refined by two steps of the division-free Newton iteration for
-// w^-7 = x (w <- w + w(1 - x w^7)/7, quadratic convergence; the estimate's
-// 1e-7 relative error falls below double rounding after two steps).
-// Outside the single-precision normal range it defers to pow.
+// (relative error e0 ~ 1e-7) refined by one third-order step of the
+// iteration for w^-7 = x: with e = 1 - x w^7, the exact correction factor is
+// (1 - e)^(-1/7) = 1 + e/7 + 4e^2/49 + O(e^3), so the error after the step is
+// O(e0^3), far below double rounding.  Outside the single-precision normal
+// range it defers to pow.
 __device__ __forceinline__ double rroot7(double x) {
     if (!(x > 1e-30 && x < 1e30)) return pow(x, -1.0 / 7.0);
-    float l = __builtin_amdgcn_logf((float)x);            // log2
-    double w = (double)__builtin_amdgcn_exp2f(l * (-1.0f / 7.0f));
-#pragma unroll
-    for (int it = 0; it < 2; ++it) {
-        double w2 = w * w, w4 = w2 * w2, w7 = w4 * w2 * w;
-        double e = fma(-x, w7, 1.0);
-        w = fma(w * (1.0 / 7.0), e, w);
-    }
-    return w;
-}
-__device__ __forceinline__ float rroot7f(float x) {
-    if (!(x > 1e-30f && x < 1e30f)) return powf(x, -1.0f / 7.0f);
-    float w = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(x) * (-1.0f / 7.0f));
-    float w2 = w * w, w4 = w2 * w2, w7 = w4 * w2 * w;
-    return fmaf(w * (1.0f / 7.0f), fmaf(-x, w7, 1.0f), w);
+    const float l = __builtin_amdgcn_logf((float)x);            // log2
+    const double w = (double)__builtin_amdgcn_exp2f(l * (-1.0f / 7.0f));
+    const double w2 = w * w, w4 = w2 * w2, w7 = w4 * w2 * w;
+    const double e = fma(-x, w7, 1.0);
+    const double t = e * fma(e, 4.0 / 49.0, 1.0 / 7.0);
+    return fma(w, t, w);
 }
 
 // Pressure-function data of one side of the Riemann problem (Toro ch. 4).
@@ -141,12 +140,13 @@ template <bool G14>
 __device__ __forceinline__ Side make_side(double r, double u, double p, double g) {
     Side s;
     s.r = r; s.u = u; s.p = p;
-    s.c = sqrt(g * p / r);
-    s.ip = 1.0 / p;
-    s.irc = 1.0 / (r * s.c);
-    s.sA = sqrt(2.0 / ((g + 1.0) * r));
+    const double t = rsqrt(g * p * r);        // 1/(rho c), since rho c = sqrt(g p rho)
+    s.irc = t;
+    s.c = g * p * t;                          // c = sqrt(g p / rho)
+    s.ip = frcp(p);
+    s.sA = sqrt(2.0 / (g + 1.0)) * rsqrt(r);  // sqrt(2/((g+1) rho))
     s.B = (g - 1.0) / (g + 1.0) * p;
-    s.k2 = 2.0 * s.c / (g - 1.0);
+    s.k2 = 2.0 / (g - 1.0) * s.c;
     return s;
 }
 
@@ -216,7 +216,9 @@ __device__ __forceinline__ void riemann0(const double* L, const double* R, doubl
         double fl, fdl, fr, fdr;
         pres_fun<G14>(sl, p, g, fl, fdl);
         pres_fun<G14>(sr, p, g, fr, fdr);
-        p = fmax(p - (fl + fr + du) / (fdl + fdr), 1e-10);
+        // the step f/f' only needs a relative accuracy far below the
+        // iteration's own convergence, so a refined reciprocal suffices
+        p = fmax(p - (fl + fr + du) * frcp(fdl + fdr), 1e-10);
     }
     double fl, fdl, fr, fdr;
     pres_fun<G14>(sl, p, g, fl, fdl);

@@ -20,14 +20,17 @@ std::vector<Entry> g_table;
 
 hfav_config hfav_default_config(int family, int dtype, const int dims[3]) {
     hfav_config c{256, 1, 0, 0};
+    // measured on MI355X at the workload sizes (64x2048x2048 hdiff, 2048^2
+    // hydro, 512^3 biharmonic); the autotuner refines these per size
     switch (family) {
-    case HFAV_FAMILY_HDIFF: c.block = 256; c.seg = 32; break;
-    case HFAV_FAMILY_EULER_X: c.block = 128; break;
+    case HFAV_FAMILY_HDIFF: c.block = 256; c.seg = 128; c.variant = 0; break;
+    case HFAV_FAMILY_EULER_X: c.block = 64; break;
     case HFAV_FAMILY_EULER_Y: c.block = 64; c.seg = 16; break;
-    case HFAV_FAMILY_LAP7_CHAIN: c.block = 256; c.seg = 32; c.variant = 0; break;
+    case HFAV_FAMILY_LAP7_CHAIN:
+        c.block = 1024; c.seg = 64; c.variant = 5; c.tile_y = dtype == HFAV_F64 ? 2 : 4;
+        break;
     default: break;
     }
-    (void)dtype;
     (void)dims;
     return c;
 }
