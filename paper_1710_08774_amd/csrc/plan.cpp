@@ -568,7 +568,28 @@ int hfav_plan_impl(hfav_chain *c, const hfav_plan_opts *o, hfav_plan_info *info)
         js << ",\"hi\":";
         json_int3(js, tp.hi);
         js << ",\"storage\":\"" << storage_name(tp.storage) << "\",\"window_axis\":" << tp.window_axis
-           << ",\"window\":" << tp.window << "}";
+           << ",\"window\":" << tp.window << ",\"reuse\":[";
+        // reuse order: the distinct references to the term, in the order a
+        // value is visited under the loop order (first visit at the largest
+        // offset along the outermost axis); this total order is the longest
+        // path of the per-term reuse graph (Design, "Grouping")
+        std::vector<std::array<int, 3>> refs;
+        for (int r : c->topo)
+            for (const HRef &ref : c->rules[r].in)
+                if (ref.term == t) {
+                    std::array<int, 3> o = {ref.off[0], ref.off[1], ref.off[2]};
+                    if (std::find(refs.begin(), refs.end(), o) == refs.end()) refs.push_back(o);
+                }
+        std::sort(refs.begin(), refs.end(), [&](const std::array<int, 3> &a, const std::array<int, 3> &b) {
+            for (int q = 0; q < nd; ++q) {
+                const int ax = c->order[q];
+                if (a[ax] != b[ax]) return a[ax] > b[ax];
+            }
+            return false;
+        });
+        for (size_t q = 0; q < refs.size(); ++q)
+            js << (q ? "," : "") << "[" << refs[q][0] << "," << refs[q][1] << "," << refs[q][2] << "]";
+        js << "]}";
     }
     js << "],\"footprint_unfused\":" << fp_un << ",\"footprint_contracted\":" << fp_con
        << ",\"max_window\":" << maxw << ",\"bytes_per_cell_fused\":" << bf

@@ -12,3 +12,10 @@ if HERE not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: long-running CPU test")
+    # build the libraries only when nothing is built (a fresh checkout)
+    if not os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so")):
+        from oracle import build as ob
+        ob.build()
+    if not os.path.exists(os.path.join(ROOT, "paper_1710_08774_amd", "libhfav.so")):
+        from paper_1710_08774_amd import build as hb
+        hb.build()

@@ -1,0 +1,266 @@
+"""Host-side planner tests (no GPU): chain validation, fusion, extents,
+windows and footprints against the structural figures the paper states
+(tests/golden/plan_pins.json), error codes, determinism."""
+import json
+import os
+
+import pytest
+
+from paper_1710_08774_amd import hfav as H
+from paper_1710_08774_amd import inputs
+
+PINS = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "plan_pins.json")))
+Z = (0, 0, 0)
+
+
+def star(refs, out, coeffs=None):
+    return H.Rule("STAR", refs, [out], coeffs or [1.0] * len(refs))
+
+
+def test_laplace3_window_is_three_values():
+    spec = H.ChainSpec(ndim=2, axioms=[("a", 2)], goals=["out"], rules=[
+        star([("a", Z)], "v"),
+        star([("v", (-1, 0, 0)), ("v", Z), ("v", (1, 0, 0))], "out", [1.0, -2.0, 1.0])])
+    c = H.Chain(spec)
+    c.plan((64, 8))
+    v = c.terms()["v"]
+    assert v["storage"] == PINS["laplace3_1d"]["storage"]
+    assert v["window"] == PINS["laplace3_1d"]["window"] and v["window_axis"] == 0
+
+
+def test_laplace5_window_and_reuse_order():
+    refs = [("v", (0, -1, 0)), ("v", (1, 0, 0)), ("v", Z), ("v", (0, 1, 0)), ("v", (-1, 0, 0))]
+    spec = H.ChainSpec(ndim=2, axioms=[("a", 2)], goals=["out"], rules=[
+        star([("a", Z)], "v"), star(refs, "out", [0.25, 0.25, -1.0, 0.25, 0.25])])
+    c = H.Chain(spec)
+    info = c.plan((32, 32))
+    v = c.terms()["v"]
+    pin = PINS["laplace5_2d"]
+    assert v["storage"] == pin["storage"] and v["window_axis"] == 1 and v["window"] == pin["window_rows"]
+    reuse = [t for t in c.plan_json()["terms"] if t["name"] == "v"][0]["reuse"]
+    assert [r[:2] for r in reuse] == pin["reuse_order_ij"]
+    assert info.footprint_contracted == 3 * 32
+
+
+def test_grouping_and_minkowski_extents():
+    # cell read at five displacements forms one group; aux is separate
+    refs = [("cell", (1, 0, 0)), ("cell", (-1, 0, 0)), ("cell", (0, 1, 0)), ("cell", (0, -1, 0)),
+            ("cell", Z), ("aux", (1, 0, 0))]
+    spec = H.ChainSpec(ndim=2, axioms=[("cell", 2), ("aux", 2)], goals=["out"], rules=[
+        star(refs, "w"), star([("w", (2, 0, 0)), ("w", (0, -1, 0))], "out")])
+    c = H.Chain(spec)
+    c.plan((16, 16))
+    t = c.terms()
+    # extent of cell = extent of w (i in [0,2], j in [-1,0]) + the 5-point star
+    assert t["w"]["lo"] == (0, -1, 0) and t["w"]["hi"] == (2, 0, 0)
+    assert t["cell"]["lo"] == (-1, -2, 0) and t["cell"]["hi"] == (3, 1, 0)
+    assert t["aux"]["lo"] == (1, -1, 0) and t["aux"]["hi"] == (3, 0, 0)
+
+
+def test_cosmo_chain_contraction():
+    pin = PINS["cosmo_hdiff"]
+    c = H.Chain(H.hdiff_spec())
+    ni, nj, nk = 256, 256, 8
+    info = c.plan((ni, nj, nk))
+    t = c.terms()
+    assert info.n_nests == pin["nests"]
+    assert (t["lap"]["storage"], t["lap"]["window_axis"], t["lap"]["window"]) == ("outer", 1, pin["lap_rows"])
+    assert (t["fly"]["storage"], t["fly"]["window_axis"], t["fly"]["window"]) == ("outer", 1, pin["fly_rows"])
+    assert (t["flx"]["storage"], t["flx"]["window_axis"], t["flx"]["window"]) == ("inner", 0, pin["flx_elems"])
+    assert t["u"]["storage"] == "full" and t["out"]["storage"] == "full"
+    assert info.footprint_contracted == 5 * ni + 2
+    assert info.footprint_unfused == 3 * ni * nj * nk
+    assert t["u"]["lo"] == (-2, -2, 0) and t["u"]["hi"] == (2, 2, 0)      # halo 2
+    assert info.family == 1 and info.fused == 1
+    assert info.bytes_per_cell_fused == 16.0
+
+
+@pytest.mark.parametrize("direction", [0, 1])
+def test_hydro_pass_one_nest_windows_at_most_five(direction):
+    pin = PINS["hydro2d_pass"]
+    c = H.Chain(H.euler_sweep_spec(direction, with_smax=direction == 1))
+    info = c.plan((128, 96))
+    assert info.n_nests == pin["nests"]
+    assert info.max_window == pin["max_window"]
+    terms = c.terms()
+    for name, t in terms.items():
+        if t["kind"] == 1:
+            assert t["storage"] in ("inner", "outer", "register", "scalar"), name
+            assert t["window"] <= 5
+        if t["kind"] in (0, 2) and t["rank"] == 2:
+            assert t["storage"] == "full"
+    ax = 0 if direction == 0 else 1
+    assert terms["w_r"]["window_axis"] == ax and terms["w_r"]["window"] == 5
+    assert terms["F_r"]["window"] == 2
+    js = c.plan_json()
+    assert len(js["nests"]) == 1 and js["nests"][0]["prologue"] == [0]     # dt broadcast
+    assert info.family == (2 if direction == 0 else 3)
+    assert info.bytes_per_cell_fused == 64.0
+    assert info.bytes_per_cell_unfused == (528.0 if direction == 0 else 560.0)
+
+
+def test_concave_dataflow_splits_into_two_nests():
+    # CFL reduction of the state feeding (through dt) a sweep of the same state
+    spec = H.euler_sweep_spec(0, dt_source="smax")
+    rules = list(spec.rules)
+    axioms = [a for a in spec.axioms if a[0] != "smax"]
+    rules.insert(0, H.Rule("EULER_SMAX", [(a, Z) for a in H.EULER_AXIOMS], ["smax"], [1.4], H.REDUCE_MAX))
+    c = H.Chain(H.ChainSpec(ndim=2, axioms=axioms, goals=spec.goals, rules=rules))
+    info = c.plan((64, 64))
+    assert info.n_nests == PINS["normalization_split"]["nests"]
+    js = c.plan_json()
+    # nest 0: the reduction (rule 0) with the rules that do not need dt
+    # (prim 2, slope 3) in its steady state and dt (rule 1) in its epilogue;
+    # the trace needs dt, so it starts nest 1
+    assert js["nests"][0]["steady"] == [0, 2, 3] and js["nests"][0]["epilogue"] == [1]
+    assert js["nests"][1]["steady"][0] == 4
+    t = c.terms()
+    assert t["smax"]["storage"] == "scalar"
+    # terms crossing the split stay full arrays; those inside a nest contract
+    assert t["w_r"]["storage"] == "full" and t["d_p"]["storage"] == "full"
+    assert t["F_r"]["storage"] == "inner"
+    assert info.family == 0 and info.fused == 0          # falls back to the unfused path
+
+
+def test_independent_chains_fuse():
+    spec = H.ChainSpec(ndim=2, axioms=[("a", 2), ("b", 2)], goals=["x", "y"], rules=[
+        star([("a", (1, 0, 0)), ("a", Z)], "x"), star([("b", (0, 1, 0))], "y")])
+    info = H.Chain(spec).plan((8, 8))
+    assert info.n_nests == 1
+
+
+def test_loop_order_changes_windows():
+    c = H.Chain(H.hdiff_spec(loop_order="jik"))   # i is the middle axis, k innermost
+    c.plan((32, 32, 4))
+    t = c.terms()
+    assert t["lap"]["window_axis"] == 1 and t["lap"]["window"] == 3   # j outermost varying
+    assert t["flx"]["storage"] == "outer" and t["flx"]["window_axis"] == 0
+
+
+def test_dead_rules_are_pruned_and_plan_is_deterministic():
+    spec = H.ChainSpec(ndim=2, axioms=[("a", 2)], goals=["x"], rules=[
+        star([("a", Z)], "x"), star([("a", (1, 0, 0))], "dead")])
+    c = H.Chain(spec)
+    i1 = c.plan((16, 16))
+    j1 = c.plan_json()
+    i2 = c.plan((16, 16))
+    assert j1 == c.plan_json()
+    assert i1.n_rules == 1 and i1.nest_of_rule[1] == -1
+    assert list(i1.rule_order[:1]) == [0]
+
+
+def test_unfused_workspace_layout():
+    c = H.Chain(H.euler_sweep_spec(0))
+    info = c.plan((100, 10), mode=H.MODE_UNFUSED)
+    # 25 grid intermediates (prim 5, slopes 4, faces 8, Godunov state 4,
+    # fluxes 4) of 1000 doubles, 256-byte aligned, plus the 0-D dt
+    assert info.fused == 0
+    assert info.workspace_bytes == 25 * ((8000 + 255) // 256 * 256) + 256
+
+
+# ----------------------------------------------------------------- errors
+def code(fn):
+    try:
+        fn()
+    except H.HfavError as e:
+        return e.code
+    return H.OK
+
+
+def test_error_duplicate_producer():
+    spec = H.ChainSpec(ndim=2, axioms=[("a", 2)], goals=["x"], rules=[
+        star([("a", Z)], "x"), star([("a", (1, 0, 0))], "x")])
+    assert code(lambda: H.Chain(spec)) == H.EDUP
+    spec2 = H.ChainSpec(ndim=2, axioms=[("a", 2)], goals=["x"], rules=[
+        star([("a", Z)], "x"), star([("x", Z)], "a")])
+    assert code(lambda: H.Chain(spec2)) == H.EDUP
+    spec3 = H.ChainSpec(ndim=2, axioms=[("a", 2), ("a", 2)], goals=["x"], rules=[star([("a", Z)], "x")])
+    assert code(lambda: H.Chain(spec3)) == H.EDUP
+
+
+def test_error_cycle():
+    spec = H.ChainSpec(ndim=2, axioms=[("a", 2)], goals=["x"], rules=[
+        star([("a", Z), ("y", Z)], "x"), star([("x", (1, 0, 0))], "y")])
+    assert code(lambda: H.Chain(spec)) == H.ECYCLE
+
+
+def test_error_unsatisfiable():
+    spec = H.ChainSpec(ndim=2, axioms=[("a", 2)], goals=["nope"], rules=[star([("a", Z)], "x")])
+    assert code(lambda: H.Chain(spec)) == H.EUNSAT
+    spec2 = H.ChainSpec(ndim=2, axioms=[("a", 2)], goals=["x"], rules=[star([("ghost", Z)], "x")])
+    assert code(lambda: H.Chain(spec2)) == H.EUNSAT
+
+
+def test_error_invalid():
+    bad_arity = H.ChainSpec(ndim=2, axioms=[("a", 2)], goals=["x"],
+                            rules=[H.Rule("HDIFF_LAP", [("a", Z)], ["x"])])
+    assert code(lambda: H.Chain(bad_arity)) == H.EINVAL
+    bad_op = H.ChainSpec(ndim=2, axioms=[("a", 2)], goals=["x"], rules=[H.Rule(999, [("a", Z)], ["x"])])
+    assert code(lambda: H.Chain(bad_op)) == H.EINVAL
+    bad_nd = H.ChainSpec(ndim=4, axioms=[("a", 4)], goals=["x"], rules=[star([("a", Z)], "x")])
+    assert code(lambda: H.Chain(bad_nd)) == H.EINVAL
+    bad_off = H.ChainSpec(ndim=2, axioms=[("a", 2)], goals=["x"], rules=[star([("a", (0, 0, 1))], "x")])
+    assert code(lambda: H.Chain(bad_off)) == H.EINVAL
+    scalar_as_grid = H.ChainSpec(ndim=2, axioms=[("a", 0)], goals=["x"], rules=[star([("a", Z)], "x")])
+    assert code(lambda: H.Chain(scalar_as_grid)) == H.EINVAL
+    c = H.Chain(H.hdiff_spec())
+    assert code(lambda: c.plan((0, 4, 4))) == H.EINVAL
+    assert code(lambda: c.plan((4, 4, 4), boundary=(7, 0, 0))) == H.EINVAL
+    c2 = H.Chain(H.euler_sweep_spec(0))
+    assert code(lambda: c2.plan((8, 8, 2))) == H.EINVAL       # nz must be 1 for a 2-D chain
+
+
+def test_error_unsupported_fused_mode():
+    spec = H.ChainSpec(ndim=2, axioms=[("a", 2)], goals=["x"], rules=[star([("a", Z)], "x")])
+    c = H.Chain(spec)
+    assert code(lambda: c.plan((8, 8), mode=H.MODE_FUSED)) == H.EUNSUP
+    assert c.plan((8, 8), mode=H.MODE_AUTO).fused == 0
+    c64 = H.Chain(H.hdiff_spec())
+    assert code(lambda: c64.plan((8, 8, 1), precision=H.PREC_F32_F64ACC)) == H.EUNSUP
+
+
+def test_execute_errors_before_any_device_call():
+    c = H.Chain(H.hdiff_spec())
+    assert c.execute_status([0x10000], [0x20000]) == H.ENOPLAN      # no plan yet
+    c.plan((16, 16, 2))
+    # output overlapping the input
+    assert c.execute_status([0x10000], [0x10000 + 64]) == H.EALIAS
+    assert c.execute_status([0], [0x20000]) == H.EINVAL               # null pointer
+    cu = H.Chain(H.hdiff_spec())
+    cu.plan((16, 16, 2), mode=H.MODE_UNFUSED)
+    assert cu.execute_status([0x10000], [0x900000], None) == H.ENOPLAN  # workspace missing
+    assert "workspace" in H.last_error()
+
+
+def test_forced_config_validation():
+    c = H.Chain(H.hdiff_spec())
+    assert code(lambda: c.plan((8, 8, 1), config_source=H.CONFIG_FORCED, forced=(0, 1, 1, 0))) == H.EINVAL
+    info = c.plan((8, 8, 1), config_source=H.CONFIG_FORCED, forced=(128, 1, 7, 2))
+    assert (info.config.block, info.config.seg, info.config.variant) == (128, 7, 2)
+    assert info.config_source == H.CONFIG_FORCED
+
+
+def test_tuning_table_nearest_entry():
+    H.tuning_clear()
+    H.tuning_add(1, H.F64, (256, 256, 8), (64, 1, 16, 1))
+    H.tuning_add(1, H.F64, (2048, 2048, 64), (512, 1, 128, 4))
+    c = H.Chain(H.hdiff_spec())
+    small = c.plan((300, 200, 4), config_source=H.CONFIG_TUNED)
+    big = c.plan((1800, 2100, 32), config_source=H.CONFIG_TUNED)
+    assert small.config.block == 64 and big.config.block == 512
+    assert small.config_source == H.CONFIG_TUNED
+    H.tuning_clear()
+    assert c.plan((300, 200, 4), config_source=H.CONFIG_TUNED).config_source == H.CONFIG_DEFAULT
+
+
+def test_random_star_chain_plans():
+    rng = inputs.rng_for(5)
+    for _ in range(10):
+        ch = inputs.random_chain(rng)
+        c = H.Chain(H.star_chain_spec(ch, inputs.star_offsets))
+        nx, ny, nz = ch["dims"]
+        info = c.plan((nx, ny, nz) if ch["ndim"] == 3 else (nx, ny))
+        assert info.n_nests == 1
+        halo = sum(s["r"] for s in ch["stages"])
+        t = c.terms()
+        assert t["x0"]["lo"][0] == -halo and t["x0"]["hi"][0] == halo
