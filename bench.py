@@ -56,12 +56,12 @@ def load_traffic(kernel):
     return None if k is None else k.get("hbm_bytes_per_launch")
 
 
-def run_gpu(mode, steps, warmup, U0, timing=True):
+def run_gpu(mode, steps, warmup, U0, timing=True, dtype=None):
     import torch
     from paper_1710_08774_amd import hfav as H
     from paper_1710_08774_amd.euler import EulerStepper
 
-    st = EulerStepper(NX, NY, mode=mode)
+    st = EulerStepper(NX, NY, mode=mode, dtype=dtype or torch.float64)
     st.load(U0)
     st.step(warmup)
     st.load(U0)
@@ -88,6 +88,66 @@ def run_gpu(mode, steps, warmup, U0, timing=True):
         out["y_ms"] = sum(e[1].elapsed_time(e[2]) for e in evs) / steps
     out["state_finite"] = bool(torch.isfinite(st.state()).all())
     out["info_fused"] = int(st.ix.fused and st.iy.fused)
+    return out
+
+
+def time_chain(spec, dims, mode, reps, inputs_fn):
+    """Average ms per hfav_execute of a single-axiom, single-goal chain, timed
+    with HIP events on the stream the chain is launched on."""
+    import torch
+    from paper_1710_08774_amd import hfav as H
+
+    c = H.Chain(spec)
+    info = c.plan(dims, mode=mode)
+    u = inputs_fn()
+    o = torch.empty_like(u)
+    ws = torch.empty(info.workspace_bytes, dtype=torch.uint8, device="cuda") if info.workspace_bytes else None
+    c.execute([u], [o], ws)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        c.execute([u], [o], ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del u, o, ws
+    return ms, info
+
+
+def bandwidth_chains(reps=10, which=("hdiff", "biharm64", "biharm32"), unfused=True):
+    """Fused vs unfused throughput of the bandwidth-bound chains at sizes whose
+    working sets are far larger than the caches."""
+    import torch
+    from paper_1710_08774_amd import hfav as H
+
+    out = {}
+    g = torch.Generator(device="cuda")
+    for name in which:
+        if name == "hdiff":
+            dims, spec, es = (2048, 2048, 64), H.hdiff_spec(), 8
+            mk = lambda: torch.rand((64, 2048, 2048), dtype=torch.float64, device="cuda", generator=g.manual_seed(1))
+        elif name == "biharm64":
+            dims, spec, es = (512, 512, 512), H.biharm_spec(), 8
+            mk = lambda: torch.rand((512, 512, 512), dtype=torch.float64, device="cuda", generator=g.manual_seed(2))
+        else:
+            dims, spec, es = (512, 512, 512), H.biharm_spec(dtype=H.F32), 4
+            mk = lambda: torch.rand((512, 512, 512), dtype=torch.float32, device="cuda", generator=g.manual_seed(3))
+        cells = dims[0] * dims[1] * dims[2]
+        ms, info = time_chain(spec, dims, H.MODE_FUSED, reps, mk)
+        gbs = 2 * es * cells / (ms * 1e-3) / 1e9
+        r = {"dims": list(dims), "dtype": "f64" if es == 8 else "f32", "fused_ms": ms,
+             "fused_cell_updates_per_s": cells / (ms * 1e-3), "fused_GBs": gbs,
+             "fused_frac_of_8TBs": gbs / HBM_PEAK_GBS,
+             "bytes_per_cell_fused": info.bytes_per_cell_fused,
+             "config": [info.config.block, info.config.tile_y, info.config.seg, info.config.variant]}
+        if unfused:
+            ums, uinfo = time_chain(spec, dims, H.MODE_UNFUSED, max(2, reps // 3), mk)
+            r.update({"unfused_ms": ums, "unfused_cell_updates_per_s": cells / (ums * 1e-3),
+                      "fused_over_unfused": ums / ms, "bytes_per_cell_unfused": uinfo.bytes_per_cell_unfused})
+        out[name] = r
+        torch.cuda.empty_cache()
     return out
 
 
@@ -118,6 +178,10 @@ def main(argv=None):
     ap.add_argument("--no-timing-events", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--no-aux", action="store_true",
+                    help="skip the bandwidth-bound chains and the FP32 hydro variant")
+    ap.add_argument("--only", choices=["hdiff", "biharm64", "biharm32"], default=None,
+                    help="only time one bandwidth-bound chain (for profiling)")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(f"bench.py: this build measures one GPU only; --gpus {a.gpus} is not supported "
@@ -140,6 +204,10 @@ def main(argv=None):
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": n * 8, "launches": 3}), flush=True)
+        return 0
+    if a.only:
+        res = bandwidth_chains(reps=a.steps, which=(a.only,), unfused=not a.no_unfused)
+        print(json.dumps({"workload": a.only, **res[a.only]}), flush=True)
         return 0
     U0 = inputs.euler_ic(NX, NY)
     timing = not a.no_timing_events
@@ -176,6 +244,13 @@ def main(argv=None):
                             "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": load_traffic(dom),
                             "avg_launch_ms": dur, "x_sweep_ms": kx, "y_sweep_ms": ky,
                             "flops_per_launch": flops}
+    if not a.no_aux:
+        aux = bandwidth_chains()
+        f32 = run_gpu(H.MODE_FUSED, a.steps, a.warmup, U0, False, dtype=torch.float32)
+        aux["euler_f32_state_f64_riemann"] = {
+            "ms_per_step": f32["ms_per_step"], "cell_updates_per_s": cells / (f32["ms_per_step"] * 1e-3),
+            "compulsory_GBs": 64 * cells / (f32["ms_per_step"] * 1e-3) / 1e9}
+        line["aux"] = aux
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(U0)
     line["state_finite"] = fused["state_finite"]

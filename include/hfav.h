@@ -189,10 +189,14 @@ typedef struct hfav_chain hfav_chain;   /* opaque */
 
 /* Fused-kernel tile configuration (autotuner / cost-model search space). */
 typedef struct {
-    int block;      /* threads per workgroup (64, 128, 256, 512) */
-    int tile_y;     /* rows of the tile across lanes (2-D tiles), or 1 */
+    int block;      /* threads per workgroup (64, 128, 256, 512, 1024) */
+    int tile_y;     /* family-specific second tile parameter (prefetch depth
+                       of the 7-point chain), or 1 */
     int seg;        /* cells streamed per thread along the streamed axis */
     int variant;    /* family-specific kernel variant, 0 = default */
+    int xcd;        /* workgroup order over the 8 XCDs: 0 = hardware order,
+                       G > 0 = runs of G consecutive tiles per XCD,
+                       -1 = one contiguous range of tiles per XCD */
 } hfav_config;
 
 typedef struct {
@@ -271,6 +275,26 @@ const char *hfav_last_error(void);
 
 /* Library version string. */
 const char *hfav_version(void);
+
+/* ------------------------------------------------------------- batches */
+#define HFAV_MAX_BATCH 640
+
+/* Plan a 2-D Euler sweep chain (or its CFL reduction) for a batch of
+ * independent grids of different sizes, advanced together by persistent
+ * kernels (one launch per sweep for all grids).  dims: host array
+ * (n_grids, 2) of (nx, ny), each in [1, 65535]; opts.dims is ignored.  Every
+ * grid term is then ONE packed device buffer holding grid g at element
+ * offset hfav_batch_offset(chain, g), and every 0-D term is a device array of
+ * n_grids doubles (one dt / CFL slot per grid).  The y-sweep segment length
+ * of each grid comes from the configuration source (the tuning table is
+ * consulted with that grid's own size).  Host only; allocates nothing.
+ * Errors: EINVAL (bad sizes, n_grids not in [1, HFAV_MAX_BATCH]), EUNSUP
+ * (chain not an Euler sweep or CFL reduction, or unfused mode). */
+int hfav_plan_batch(hfav_chain *chain, const hfav_plan_opts *opts, int n_grids, const int *dims,
+                    hfav_plan_info *info);
+
+/* Element offset of grid g in the packed buffers of a batched plan, or -1. */
+int64_t hfav_batch_offset(const hfav_chain *chain, int grid);
 
 /* Per-term plan details (extent, storage class, window), term index in
  * [0, hfav_num_terms).  Errors: ENOPLAN, EINVAL. */

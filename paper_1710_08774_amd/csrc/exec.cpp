@@ -33,6 +33,10 @@ int dev_err(hipError_t e, const char *what) {
 }
 
 size_t term_bytes(const hfav_chain *c, int t) {
+    if (c->plan.batch) {
+        if (c->terms[t].rank == 0) return 8 * c->plan.bnx.size();
+        return (size_t)c->plan.btotal * (c->dtype == HFAV_F64 ? 8 : 4);
+    }
     if (c->terms[t].rank == 0) return 8;
     const int *d = c->plan.opts.dims;
     return (size_t)d[0] * d[1] * d[2] * (c->dtype == HFAV_F64 ? 8 : 4);
@@ -43,9 +47,47 @@ bool overlap(const void *a, size_t na, const void *b, size_t nb) {
     return pa < pb + nb && pb < pa + na;
 }
 
+int run_batch(const hfav_chain *c, const Bind &B, hipStream_t s) {
+    const HPlan &p = c->plan;
+    hfav::EulerBatch Bt;
+    Bt.n = (int)p.bnx.size();
+    Bt.nx = p.bnx.data();
+    Bt.ny = p.bny.data();
+    Bt.seg = p.bseg.data();
+    Bt.workgroups = 0;
+    if (p.family == HFAV_FAMILY_SMAX) {
+        const void *U[4];
+        for (int q = 0; q < 4; ++q) U[q] = B.ptr(p.fam_in[q]);
+        double *out = (double *)B.wptr(p.fam_out[0]);
+        int rc = dev_err(hfav::launch_fill_batch(out, Bt.n, 0.0, s), "reduction init");
+        if (rc) return rc;
+        return dev_err(hfav::launch_euler_smax_batch(U, Bt, p.fam_param[0], out, c->dtype, s), "batched smax launch");
+    }
+    hfav::EulerLaunch L;
+    for (int q = 0; q < 4; ++q) { L.in[q] = B.ptr(p.fam_in[q]); L.out[q] = B.wptr(p.fam_out[q]); }
+    L.nx = L.ny = 0;
+    const int dir = p.family == HFAV_FAMILY_EULER_X ? 0 : 1;
+    L.bc = p.opts.boundary[dir];
+    L.gamma = p.fam_param[0];
+    L.niter = (int)p.fam_param[1];
+    L.dt_src = (const double *)B.ptr(p.fam_dt_term);
+    L.dt_mode = p.fam_dt_mode == 1 ? hfav::DT_FROM_SMAX : hfav::DT_VALUE;
+    L.cfl = p.fam_cfl;
+    L.smax_out = p.fam_smax_goal >= 0 ? (double *)B.wptr(p.fam_smax_goal) : nullptr;
+    L.dtype = c->dtype;
+    L.precision = p.opts.precision;
+    L.cfg = p.info.config;
+    if (L.smax_out) {
+        int rc = dev_err(hfav::launch_fill_batch(L.smax_out, Bt.n, 0.0, s), "reduction init");
+        if (rc) return rc;
+    }
+    return dev_err(hfav::launch_euler_batch(L, Bt, dir == 0, s), "batched sweep launch");
+}
+
 int run_fused(const hfav_chain *c, const Bind &B, hipStream_t s) {
     const HPlan &p = c->plan;
     const int *d = p.opts.dims;
+    if (p.batch) return run_batch(c, B, s);
     switch (p.family) {
     case HFAV_FAMILY_HDIFF: {
         hfav::HdiffLaunch L;

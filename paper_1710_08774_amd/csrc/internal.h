@@ -67,6 +67,11 @@ struct HPlan {
     size_t ws_bytes = 0;
     std::vector<int> exec_order; // rule order for the unfused path
     std::string json;
+    // batched plans: per-grid sizes, y-pass segment lengths and offsets
+    bool batch = false;
+    std::vector<int> bnx, bny, bseg;
+    std::vector<int64_t> boff;
+    int64_t btotal = 0;
 };
 
 struct hfav_chain {

@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 #include "kernels.h"
 #include "ops.h"
+#include "xcd.h"
 
 namespace hfav {
 
@@ -35,6 +36,7 @@ struct EArgs {
     double cfl;
     double *smax_out;
     int seg;
+    int xcd;
 };
 
 __device__ __forceinline__ int bwrap(int i, int n, int bc) {
@@ -61,25 +63,42 @@ __device__ __forceinline__ void slope_trace(const Prim<T> &wm, const Prim<T> &w0
     euler_trace(w0, dr, du, dv, dp, nu, plus, minus);
 }
 
-// ------------------------------------------------------------------ x pass
-template <class T, class A, bool G14, int B, int WPE>
-__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(WPE))) void euler_x_kernel(EArgs<T> a) {
-    // Rings of R = B + 4 slots indexed by cell modulo R: a chunk touches
-    // cells c0-2 .. c0+B, and a barrier separates every write of a slot from
-    // the last read of the cell it held before.
-    constexpr int R = B + 4;
-    __shared__ T s_w[5][R];     // primitive window (r, un, ut, p, c)
-    __shared__ T s_u[4][R];     // conserved state, read back by the update
-    __shared__ T s_f[4][R];     // plus-face state
-    __shared__ T s_F[4][R];     // interface flux: slot of cell p holds F(p-1/2)
-    __shared__ T s_F0[4];       // F(-1/2) for the periodic wrap
-    __shared__ T s_Fn[4];       // F(nx-1/2) for a transmissive right end
+// One grid (or one grid of a batch) as seen by a sweep body.
+template <class T>
+struct EView {
+    const T *rho, *mn, *mt, *E;
+    T *orho, *omn, *omt, *oE;
+    int nx, ny;
+};
 
-    const int nx = a.nx;
+template <class T>
+__device__ __forceinline__ EView<T> full_view(const EArgs<T> &a) {
+    return EView<T>{a.rho, a.mn, a.mt, a.E, a.orho, a.omn, a.omt, a.oE, a.nx, a.ny};
+}
+
+// ------------------------------------------------------------------ x pass
+// LDS of the x pass.  Rings of R = B + 4 slots indexed by cell modulo R: a
+// chunk touches cells c0-2 .. c0+B, and a barrier separates every write of a
+// slot from the last read of the cell it held before.
+template <class T, int B>
+struct XLds {
+    static constexpr int R = B + 4;
+    T w[5][R];      // primitive window (r, un, ut, p, c)
+    T u[4][R];      // conserved state, read back by the update
+    T f[4][R];      // plus-face state
+    T F[4][R];      // interface flux: slot of cell p holds F(p-1/2)
+    T F0[4];        // F(-1/2) for the periodic wrap
+    T Fn[4];        // F(nx-1/2) for a transmissive right end
+};
+
+// Sweep one row (row index j of view v) with the whole workgroup.
+template <class T, class A, bool G14, int B>
+__device__ __forceinline__ void x_row(const EArgs<T> &a, const EView<T> &v, int j, double dt, XLds<T, B> &S) {
+    constexpr int R = XLds<T, B>::R;
+    const int nx = v.nx;
     const int t = threadIdx.x;
-    const size_t row = (size_t)blockIdx.x * nx;
+    const size_t row = (size_t)j * nx;
     const T g = (T)a.g;
-    const double dt = read_dt(a.dt_src, a.dt_mode, a.cfl);
     const T nu = (T)dt;
     const A nuA = (A)dt;
     int ob = 0;                 // slot of cell c0 (c0 mod R)
@@ -91,20 +110,21 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(WPE))) void e
     };
     auto load_cell = [&](int cell, T *u) {
         const size_t o = row + bwrap(cell, nx, a.bc);
-        u[0] = a.rho[o]; u[1] = a.mn[o]; u[2] = a.mt[o]; u[3] = a.E[o];
+        u[0] = v.rho[o]; u[1] = v.mn[o]; u[2] = v.mt[o]; u[3] = v.E[o];
     };
     auto put = [&](int sl, const T *u) {
         Prim<T> w = euler_prim(u[0], u[1], u[2], u[3], g);
-        s_w[0][sl] = w.r; s_w[1][sl] = w.un; s_w[2][sl] = w.ut; s_w[3][sl] = w.p; s_w[4][sl] = w.c;
+        S.w[0][sl] = w.r; S.w[1][sl] = w.un; S.w[2][sl] = w.ut; S.w[3][sl] = w.p; S.w[4][sl] = w.c;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) s_u[q][sl] = u[q];
+        for (int q = 0; q < 4; ++q) S.u[q][sl] = u[q];
     };
     auto get_prim = [&](int sl) {
         Prim<T> w;
-        w.r = s_w[0][sl]; w.un = s_w[1][sl]; w.ut = s_w[2][sl]; w.p = s_w[3][sl]; w.c = s_w[4][sl];
+        w.r = S.w[0][sl]; w.un = S.w[1][sl]; w.ut = S.w[2][sl]; w.p = S.w[3][sl]; w.c = S.w[4][sl];
         return w;
     };
 
+    __syncthreads();            // the previous row of a persistent loop is done with the rings
     // prologue: cells -2, -1, 0 and the plus face of cell -1
     if (t < 3) {
         T u[4];
@@ -117,7 +137,7 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(WPE))) void e
         slope_trace(get_prim(slot(-2)), get_prim(slot(-1)), get_prim(slot(0)), nu, plus, minus);
         const int sl = slot(-1);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) s_f[q][sl] = plus[q];
+        for (int q = 0; q < 4; ++q) S.f[q][sl] = plus[q];
     }
 
     for (int c0 = 0; c0 < nx; c0 += B) {
@@ -138,51 +158,57 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(WPE))) void e
             T plus[4];
             slope_trace(get_prim(sm), get_prim(s0), get_prim(sp), nu, plus, minus);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) s_f[q][s0] = plus[q];
+            for (int q = 0; q < 4; ++q) S.f[q][s0] = plus[q];
         }
         __syncthreads();
         // stage 3: Riemann problem and flux at interface p-1/2
         if (act) {
             T L[4], G[4], F[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) L[q] = s_f[q][sm];
+            for (int q = 0; q < 4; ++q) L[q] = S.f[q][sm];
             riemann_T<T, G14>(L, minus, g, a.niter, G);
             euler_flux(G, g, F);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) s_F[q][s0] = F[q];
+            for (int q = 0; q < 4; ++q) S.F[q][s0] = F[q];
             if (p == 0) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) s_F0[q] = F[q];
+                for (int q = 0; q < 4; ++q) S.F0[q] = F[q];
             }
             if (a.bc != HFAV_BC_PERIODIC && p == nx - 1) {
                 // right ghost cell copies cell nx-1 and has zero slopes, so
                 // its minus face is the primitive state of cell nx-1
                 T Lr[4], Rr[4], Gr[4];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) Lr[q] = s_f[q][s0];
-                Rr[0] = s_w[0][s0]; Rr[1] = s_w[1][s0]; Rr[2] = s_w[2][s0]; Rr[3] = s_w[3][s0];
+                for (int q = 0; q < 4; ++q) Lr[q] = S.f[q][s0];
+                Rr[0] = S.w[0][s0]; Rr[1] = S.w[1][s0]; Rr[2] = S.w[2][s0]; Rr[3] = S.w[3][s0];
                 riemann_T<T, G14>(Lr, Rr, g, a.niter, Gr);
-                euler_flux(Gr, g, s_Fn);
+                euler_flux(Gr, g, S.Fn);
             }
         }
         __syncthreads();
         // stage 4: conservative update of cell p-1 (and of cell nx-1 at the end)
         if (act && p >= 1) {
             const size_t o = row + (p - 1);
-            a.orho[o] = euler_update(s_u[0][sm], s_F[0][s0], s_F[0][sm], nuA);
-            a.omn[o] = euler_update(s_u[1][sm], s_F[1][s0], s_F[1][sm], nuA);
-            a.omt[o] = euler_update(s_u[2][sm], s_F[2][s0], s_F[2][sm], nuA);
-            a.oE[o] = euler_update(s_u[3][sm], s_F[3][s0], s_F[3][sm], nuA);
+            v.orho[o] = euler_update(S.u[0][sm], S.F[0][s0], S.F[0][sm], nuA);
+            v.omn[o] = euler_update(S.u[1][sm], S.F[1][s0], S.F[1][sm], nuA);
+            v.omt[o] = euler_update(S.u[2][sm], S.F[2][s0], S.F[2][sm], nuA);
+            v.oE[o] = euler_update(S.u[3][sm], S.F[3][s0], S.F[3][sm], nuA);
         }
         if (act && p == nx - 1) {
             const size_t o = row + p;
-            const T *Fp = a.bc == HFAV_BC_PERIODIC ? s_F0 : s_Fn;
-            a.orho[o] = euler_update(s_u[0][s0], Fp[0], s_F[0][s0], nuA);
-            a.omn[o] = euler_update(s_u[1][s0], Fp[1], s_F[1][s0], nuA);
-            a.omt[o] = euler_update(s_u[2][s0], Fp[2], s_F[2][s0], nuA);
-            a.oE[o] = euler_update(s_u[3][s0], Fp[3], s_F[3][s0], nuA);
+            const T *Fp = a.bc == HFAV_BC_PERIODIC ? S.F0 : S.Fn;
+            v.orho[o] = euler_update(S.u[0][s0], Fp[0], S.F[0][s0], nuA);
+            v.omn[o] = euler_update(S.u[1][s0], Fp[1], S.F[1][s0], nuA);
+            v.omt[o] = euler_update(S.u[2][s0], Fp[2], S.F[2][s0], nuA);
+            v.oE[o] = euler_update(S.u[3][s0], Fp[3], S.F[3][s0], nuA);
         }
     }
+}
+
+template <class T, class A, bool G14, int B, int WPE>
+__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(WPE))) void euler_x_kernel(EArgs<T> a) {
+    __shared__ XLds<T, B> S;
+    x_row<T, A, G14, B>(a, full_view(a), blockIdx.x, read_dt(a.dt_src, a.dt_mode, a.cfl), S);
 }
 
 // ------------------------------------------------------------------ y pass
@@ -192,6 +218,7 @@ __device__ __forceinline__ void block_max_to(double v, double *out) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();            // red[] may still be read by a previous call
     if (lane == 0) red[w] = v;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -202,25 +229,24 @@ __device__ __forceinline__ void block_max_to(double v, double *out) {
     }
 }
 
-template <class T, class A, bool G14, int B, int WPE>
-__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(WPE))) void euler_y_kernel(EArgs<T> a) {
-    // each lane keeps the conserved state of its last three cells in its own
-    // LDS slots (read back two rows later by the update)
-    __shared__ T s_u[3][4][B];
-    const int nx = a.nx, ny = a.ny;
+// Sweep one tile (columns i0 .. i0+B-1, rows j0 .. j1-1) along y.  Each lane
+// keeps the conserved state of its last three cells in its own LDS slots
+// (read back two rows later by the update).  Returns the lane's largest
+// signal speed of the updated cells (0 when want_smax is false).
+template <class T, class A, bool G14, int B>
+__device__ __forceinline__ double y_tile(const EArgs<T> &a, const EView<T> &v, int i0, int j0, int j1, double dt,
+                                         bool want_smax, T (*s_u)[4][B]) {
+    const int nx = v.nx, ny = v.ny;
     const int t = threadIdx.x;
-    const int i = blockIdx.x * B + t;
-    const int j0 = blockIdx.y * a.seg;
-    const int j1 = min(j0 + a.seg, ny);
+    const int i = i0 + t;
     const T g = (T)a.g;
-    const double dt = read_dt(a.dt_src, a.dt_mode, a.cfl);
     const T nu = (T)dt;
     const A nuA = (A)dt;
     double smax = 0.0;
     if (i < nx) {
         auto P = [&](int jj, int slot) {
             const size_t o = (size_t)bwrap(jj, ny, a.bc) * nx + i;
-            const T r = a.rho[o], mn = a.mn[o], mt = a.mt[o], e = a.E[o];
+            const T r = v.rho[o], mn = v.mn[o], mt = v.mt[o], e = v.E[o];
             if (slot >= 0) {
                 s_u[slot][0][t] = r; s_u[slot][1][t] = mn; s_u[slot][2][t] = mt; s_u[slot][3][t] = e;
             }
@@ -247,8 +273,8 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(WPE))) void e
                 const T mn = euler_update(s_u[su][1][t], F[1], Fm[1], nuA);
                 const T mt = euler_update(s_u[su][2][t], F[2], Fm[2], nuA);
                 const T e = euler_update(s_u[su][3][t], F[3], Fm[3], nuA);
-                a.orho[o] = r; a.omn[o] = mn; a.omt[o] = mt; a.oE[o] = e;
-                if (a.smax_out) smax = fmax(smax, (double)euler_speed(r, mt, mn, e, g));
+                v.orho[o] = r; v.omn[o] = mn; v.omt[o] = mt; v.oE[o] = e;
+                if (want_smax) smax = fmax(smax, (double)euler_speed(r, mt, mn, e, g));
             }
 #pragma unroll
             for (int q = 0; q < 4; ++q) { Fm[q] = F[q]; fp[q] = plus[q]; }
@@ -257,7 +283,108 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(WPE))) void e
             snew = snew == 2 ? 0 : snew + 1;
         }
     }
+    return smax;
+}
+
+template <class T, class A, bool G14, int B, int WPE>
+__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(WPE))) void euler_y_kernel(EArgs<T> a) {
+    __shared__ T s_u[3][4][B];
+    const int nx = a.nx, ny = a.ny;
+    // logical tile: column tile fastest, then row segment
+    const int ntx = (nx + B - 1) / B, nsg = (ny + a.seg - 1) / a.seg;
+    const int tile = xcd_tile(blockIdx.x, ntx * nsg, a.xcd);
+    const int i0 = (tile % ntx) * B;
+    const int j0 = (tile / ntx) * a.seg;
+    const int j1 = min(j0 + a.seg, ny);
+    const double smax = y_tile<T, A, G14, B>(a, full_view(a), i0, j0, j1, read_dt(a.dt_src, a.dt_mode, a.cfl),
+                                             a.smax_out != nullptr, s_u);
     if (a.smax_out) block_max_to<B>(smax, a.smax_out);
+}
+
+// ------------------------------------------------------------------ batches
+// Many independent grids in packed buffers: grid g's plane q starts at
+// base + off_g with off_g the sum of nx*ny over the grids before it.  A
+// persistent pool of workgroups walks the work items of all grids in
+// grid-stride order; items of one grid are contiguous, so each workgroup
+// finds the grid of its next item by advancing a monotone cursor over the
+// per-grid sizes held in the kernel arguments (no device table).  Every grid
+// has its own dt (from its own smax slot) and its own CFL reduction slot.
+struct BatchDims {
+    int n;
+    unsigned short nx[HFAV_MAX_BATCH], ny[HFAV_MAX_BATCH];
+    unsigned char seg[HFAV_MAX_BATCH];   // y-pass segment length per grid
+};
+
+struct Cursor {
+    int g;          // current grid
+    long long base; // first item of grid g
+    long long off;  // element offset of grid g in the packed buffers
+};
+
+template <class F>
+__device__ __forceinline__ void advance(Cursor &c, long long item, const BatchDims &d, F count) {
+    while (c.g < d.n && item >= c.base + count(c.g)) {
+        c.base += count(c.g);
+        c.off += (long long)d.nx[c.g] * d.ny[c.g];
+        ++c.g;
+    }
+}
+
+template <class T>
+__device__ __forceinline__ EView<T> grid_view(const EArgs<T> &a, const BatchDims &d, const Cursor &c) {
+    return EView<T>{a.rho + c.off, a.mn + c.off, a.mt + c.off, a.E + c.off,
+                    a.orho + c.off, a.omn + c.off, a.omt + c.off, a.oE + c.off, d.nx[c.g], d.ny[c.g]};
+}
+
+template <class T, class A, bool G14, int B>
+__global__ __launch_bounds__(B) void euler_x_batch_kernel(EArgs<T> a, BatchDims d, long long items) {
+    __shared__ XLds<T, B> S;
+    Cursor c{0, 0, 0};
+    auto rows = [&](int g) { return (long long)d.ny[g]; };
+    for (long long it = blockIdx.x; it < items; it += gridDim.x) {
+        advance(c, it, d, rows);
+        const EView<T> v = grid_view(a, d, c);
+        const double dt = read_dt(a.dt_src + c.g, a.dt_mode, a.cfl);
+        x_row<T, A, G14, B>(a, v, (int)(it - c.base), dt, S);
+    }
+}
+
+template <class T, class A, bool G14, int B>
+__global__ __launch_bounds__(B) void euler_y_batch_kernel(EArgs<T> a, BatchDims d, long long items) {
+    __shared__ T s_u[3][4][B];
+    Cursor c{0, 0, 0};
+    auto tiles = [&](int g) {
+        return (long long)((d.nx[g] + B - 1) / B) * ((d.ny[g] + d.seg[g] - 1) / d.seg[g]);
+    };
+    for (long long it = blockIdx.x; it < items; it += gridDim.x) {
+        advance(c, it, d, tiles);
+        const EView<T> v = grid_view(a, d, c);
+        const int ntx = (v.nx + B - 1) / B;
+        const int tile = (int)(it - c.base);
+        const int i0 = (tile % ntx) * B, j0 = (tile / ntx) * d.seg[c.g];
+        const int j1 = min(j0 + (int)d.seg[c.g], v.ny);
+        const double dt = read_dt(a.dt_src + c.g, a.dt_mode, a.cfl);
+        const double smax = y_tile<T, A, G14, B>(a, v, i0, j0, j1, dt, a.smax_out != nullptr, s_u);
+        if (a.smax_out) block_max_to<B>(smax, a.smax_out + c.g);
+    }
+}
+
+template <class T, int B>
+__global__ __launch_bounds__(B) void euler_smax_batch_kernel(const T *rho, const T *mx, const T *my, const T *E,
+                                                             BatchDims d, double g, double *out) {
+    // one workgroup per grid
+    long long off = 0;
+    for (int h = 0; h < (int)blockIdx.x; ++h) off += (long long)d.nx[h] * d.ny[h];
+    const long long n = (long long)d.nx[blockIdx.x] * d.ny[blockIdx.x];
+    double m = 0.0;
+    for (long long q = threadIdx.x; q < n; q += B)
+        m = fmax(m, (double)euler_speed(rho[off + q], mx[off + q], my[off + q], E[off + q], (T)g));
+    block_max_to<B>(m, out + blockIdx.x);
+}
+
+__global__ void fill_batch_kernel(double *p, int n, double v) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) p[q] = v;
 }
 
 // ------------------------------------------------------------------ smax
@@ -284,6 +411,7 @@ static EArgs<T> make_args(const EulerLaunch &L) {
     a.dt_src = L.dt_src; a.dt_mode = L.dt_mode; a.cfl = L.cfl;
     a.smax_out = L.smax_out;
     a.seg = L.cfg.seg > 0 ? L.cfg.seg : 16;
+    a.xcd = L.cfg.xcd;
     return a;
 }
 
@@ -309,7 +437,7 @@ template <class T, class A, bool G14>
 static hipError_t euler_y_dispatch(const EulerLaunch &L, hipStream_t s) {
     EArgs<T> a = make_args<T>(L);
     const int B = (L.cfg.block == 64 || L.cfg.block == 128 || L.cfg.block == 256) ? L.cfg.block : 64;
-    dim3 grid((L.nx + B - 1) / B, (L.ny + a.seg - 1) / a.seg);
+    dim3 grid(((L.nx + B - 1) / B) * ((L.ny + a.seg - 1) / a.seg));
     const bool w4 = L.cfg.variant == 1;
     switch (B) {
     case 128: if (w4) EY_LAUNCH(128, 4); else EY_LAUNCH(128, 1); break;
@@ -363,6 +491,64 @@ hipError_t launch_fill_scalar(double *p, double v, hipStream_t s) {
 
 hipError_t launch_dt_from_smax(const double *smax, double cfl, double *out, hipStream_t s) {
     hipLaunchKernelGGL(dt_from_smax_kernel, dim3(1), dim3(1), 0, s, smax, cfl, out);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ batch launchers
+static BatchDims make_dims(const EulerBatch &Bt) {
+    BatchDims d;
+    d.n = Bt.n;
+    for (int g = 0; g < Bt.n; ++g) {
+        d.nx[g] = (unsigned short)Bt.nx[g];
+        d.ny[g] = (unsigned short)Bt.ny[g];
+        d.seg[g] = (unsigned char)Bt.seg[g];
+    }
+    return d;
+}
+
+template <class T, class A, bool G14>
+static hipError_t batch_dispatch(const EulerLaunch &L, const EulerBatch &Bt, bool x, hipStream_t s) {
+    EArgs<T> a = make_args<T>(L);
+    const BatchDims d = make_dims(Bt);
+    long long items = 0;
+    const int B = 64;
+    for (int g = 0; g < Bt.n; ++g)
+        items += x ? Bt.ny[g] : (long long)((Bt.nx[g] + B - 1) / B) * ((Bt.ny[g] + Bt.seg[g] - 1) / Bt.seg[g]);
+    const long long cap = (long long)(Bt.workgroups > 0 ? Bt.workgroups : 256 * 12);
+    const unsigned nwg = (unsigned)(items < cap ? items : cap);
+    if (nwg == 0) return hipSuccess;
+    if (x) hipLaunchKernelGGL((euler_x_batch_kernel<T, A, G14, 64>), dim3(nwg), dim3(64), 0, s, a, d, items);
+    else hipLaunchKernelGGL((euler_y_batch_kernel<T, A, G14, 64>), dim3(nwg), dim3(64), 0, s, a, d, items);
+    return hipGetLastError();
+}
+
+hipError_t launch_euler_batch(const EulerLaunch &L, const EulerBatch &Bt, bool x, hipStream_t s) {
+    if (Bt.n < 1 || Bt.n > HFAV_MAX_BATCH) return hipErrorInvalidValue;
+    const bool g14 = L.gamma == 1.4;
+    if (L.dtype == HFAV_F64)
+        return g14 ? batch_dispatch<double, double, true>(L, Bt, x, s) : batch_dispatch<double, double, false>(L, Bt, x, s);
+    if (L.precision == HFAV_PREC_F32_F64ACC)
+        return g14 ? batch_dispatch<float, double, true>(L, Bt, x, s) : batch_dispatch<float, double, false>(L, Bt, x, s);
+    return g14 ? batch_dispatch<float, float, true>(L, Bt, x, s) : batch_dispatch<float, float, false>(L, Bt, x, s);
+}
+
+hipError_t launch_euler_smax_batch(const void *const *U, const EulerBatch &Bt, double gamma, double *out, int dtype,
+                                   hipStream_t s) {
+    if (Bt.n < 1 || Bt.n > HFAV_MAX_BATCH) return hipErrorInvalidValue;
+    const BatchDims d = make_dims(Bt);
+    if (dtype == HFAV_F64)
+        hipLaunchKernelGGL((euler_smax_batch_kernel<double, 256>), dim3(Bt.n), dim3(256), 0, s,
+                           (const double *)U[0], (const double *)U[1], (const double *)U[2], (const double *)U[3],
+                           d, gamma, out);
+    else
+        hipLaunchKernelGGL((euler_smax_batch_kernel<float, 256>), dim3(Bt.n), dim3(256), 0, s,
+                           (const float *)U[0], (const float *)U[1], (const float *)U[2], (const float *)U[3],
+                           d, gamma, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_batch(double *p, int n, double v, hipStream_t s) {
+    hipLaunchKernelGGL(fill_batch_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
     return hipGetLastError();
 }
 

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 #include "kernels.h"
 #include "ops.h"
+#include "xcd.h"
 
 namespace hfav {
 
@@ -22,7 +23,7 @@ template <class T>
 struct HArgs {
     const T *in;
     T *out;
-    int ni, nj, nk, seg;
+    int ni, nj, nk, seg, xcd;
     T coeff;
 };
 
@@ -36,11 +37,14 @@ __global__ __launch_bounds__(B) void hdiff_kernel(HArgs<T> a) {
     constexpr int W = B + 4;              // row slot: columns i0-2 .. i0+B+1
     __shared__ T ring[4][W];
     const int t = threadIdx.x;
-    const int i0 = blockIdx.x * B;
-    const int j0 = blockIdx.y * a.seg;
-    const int j1 = min(j0 + a.seg, a.nj);
-    const int k = blockIdx.z;
     const int ni = a.ni, nj = a.nj;
+    // logical tile: x tile fastest, then row segment, then plane
+    const int ntx = (ni + B - 1) / B, nsg = (nj + a.seg - 1) / a.seg;
+    const int tile = xcd_tile(blockIdx.x, ntx * nsg * a.nk, a.xcd);
+    const int i0 = (tile % ntx) * B;
+    const int j0 = ((tile / ntx) % nsg) * a.seg;
+    const int j1 = min(j0 + a.seg, a.nj);
+    const int k = tile / (ntx * nsg);
     const T *plane = a.in + (size_t)k * nj * ni;
     T *oplane = a.out + (size_t)k * nj * ni;
     // lane t keeps its own column (slot t+2); lanes 0..3 also fetch the
@@ -118,11 +122,12 @@ static hipError_t hdiff_dispatch(const HdiffLaunch &L, hipStream_t s) {
     a.ni = L.ni; a.nj = L.nj; a.nk = L.nk;
     a.seg = L.cfg.seg > 0 ? L.cfg.seg : 32;
     a.coeff = (T)L.coeff;
+    a.xcd = L.cfg.xcd;
     int B = L.cfg.block;
     if (B != 64 && B != 128 && B != 256 && B != 512) B = 256;
     // variant: prefetch depth (rows in flight per workgroup) 1, 2, 4 or 8
     const int P = L.cfg.variant == 1 ? 1 : L.cfg.variant == 2 ? 2 : L.cfg.variant == 4 ? 8 : 4;
-    dim3 grid((L.ni + B - 1) / B, (L.nj + a.seg - 1) / a.seg, L.nk);
+    dim3 grid(((L.ni + B - 1) / B) * ((L.nj + a.seg - 1) / a.seg) * L.nk);
 #define HD_LAUNCH(BB, PP) hipLaunchKernelGGL((hdiff_kernel<T, BB, PP>), grid, dim3(BB), 0, s, a)
 #define HD_P(BB)                               \
     switch (P) {                               \

@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 #include "kernels.h"
 #include "ops.h"
+#include "xcd.h"
 
 namespace hfav {
 
@@ -21,7 +22,7 @@ template <class T>
 struct BArgs {
     const T *in;
     T *out;
-    int nx, ny, nz, seg;
+    int nx, ny, nz, seg, xcd;
     T alpha;
 };
 
@@ -40,10 +41,13 @@ __global__ __launch_bounds__(TX * TY) void lap7_chain_kernel(BArgs<T> a) {
     __shared__ T sl[2][LY][LX];
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
-    const int k0 = blockIdx.z * a.seg;
-    const int k1 = min(k0 + a.seg, a.nz);
     const int nx = a.nx, ny = a.ny, nz = a.nz;
+    // logical tile: x tile fastest, then y tile, then z segment
+    const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY, nsg = (nz + a.seg - 1) / a.seg;
+    const int tile = xcd_tile(blockIdx.x, ntx * nty * nsg, a.xcd);
+    const int x0 = (tile % ntx) * TX, y0 = ((tile / ntx) % nty) * TY;
+    const int k0 = (tile / (ntx * nty)) * a.seg;
+    const int k1 = min(k0 + a.seg, a.nz);
     const size_t plane = (size_t)nx * ny;
     // per-lane offsets of its u points inside a plane (wrapped), fixed for
     // the whole segment
@@ -131,6 +135,7 @@ static hipError_t lap7_dispatch(const Lap7ChainLaunch &L, hipStream_t s) {
     a.nx = L.nx; a.ny = L.ny; a.nz = L.nz;
     a.seg = L.cfg.seg > 0 ? L.cfg.seg : 32;
     a.alpha = (T)L.alpha;
+    a.xcd = L.cfg.xcd;
     int tx = 64, ty = 4;
     switch (L.cfg.variant) {
     case 1: tx = 32; ty = 8; break;
@@ -142,7 +147,7 @@ static hipError_t lap7_dispatch(const Lap7ChainLaunch &L, hipStream_t s) {
     }
     // tile_y selects the prefetch depth (planes in flight): 1, 2 or 4
     const int P = L.cfg.tile_y == 1 ? 1 : L.cfg.tile_y == 4 ? 4 : 2;
-    dim3 grid((L.nx + tx - 1) / tx, (L.ny + ty - 1) / ty, (L.nz + a.seg - 1) / a.seg);
+    dim3 grid(((L.nx + tx - 1) / tx) * ((L.ny + ty - 1) / ty) * ((L.nz + a.seg - 1) / a.seg));
 #define B7(TX_, TY_, PP) hipLaunchKernelGGL((lap7_chain_kernel<T, TX_, TY_, PP>), grid, dim3(TX_ * TY_), 0, s, a)
 #define B7P(TX_, TY_)                 \
     switch (P) {                      \

@@ -30,6 +30,20 @@ struct EulerLaunch {
 hipError_t launch_euler_x(const EulerLaunch &L, hipStream_t s);
 hipError_t launch_euler_y(const EulerLaunch &L, hipStream_t s);
 
+// Batched sweeps over many grids in packed buffers (grid g at element offset
+// sum_{h<g} nx_h*ny_h of every plane); dt_src and smax_out point to arrays
+// of one value per grid.
+struct EulerBatch {
+    int n;
+    const int *nx, *ny;   // host arrays, n entries each
+    const int *seg;       // y-pass segment length per grid
+    int workgroups;       // persistent pool size, 0 = default
+};
+hipError_t launch_euler_batch(const EulerLaunch &L, const EulerBatch &B, bool x_pass, hipStream_t s);
+hipError_t launch_euler_smax_batch(const void *const *U, const EulerBatch &B, double gamma, double *out,
+                                   int dtype, hipStream_t s);
+hipError_t launch_fill_batch(double *p, int n, double v, hipStream_t s);
+
 // smax = max over cells of max(|u|+c, |v|+c); *out must hold 0 beforehand.
 hipError_t launch_euler_smax(const void *const *U, int n, double gamma, double *out,
                              int dtype, hipStream_t s);

@@ -493,7 +493,8 @@ int hfav_plan_impl(hfav_chain *c, const hfav_plan_opts *o, hfav_plan_info *info)
     int src = HFAV_CONFIG_DEFAULT;
     if (o->config_source == HFAV_CONFIG_FORCED) {
         cfg = o->forced;
-        if (cfg.block <= 0 || cfg.block > 1024 || cfg.seg < 0 || cfg.seg > 4096 || cfg.variant < 0)
+        if (cfg.block <= 0 || cfg.block > 1024 || cfg.seg < 0 || cfg.seg > 4096 || cfg.variant < 0 ||
+            cfg.xcd < -1 || cfg.xcd > 4096)
             return hfav_fail(HFAV_EINVAL, "forced configuration out of range");
         src = HFAV_CONFIG_FORCED;
     } else if (o->config_source == HFAV_CONFIG_TUNED) {
@@ -595,6 +596,7 @@ int hfav_plan_impl(hfav_chain *c, const hfav_plan_opts *o, hfav_plan_info *info)
        << ",\"max_window\":" << maxw << ",\"bytes_per_cell_fused\":" << bf
        << ",\"bytes_per_cell_unfused\":" << bu << ",\"config\":{\"block\":" << cfg.block
        << ",\"tile_y\":" << cfg.tile_y << ",\"seg\":" << cfg.seg << ",\"variant\":" << cfg.variant
+       << ",\"xcd\":" << cfg.xcd
        << "},\"config_source\":" << src << ",\"workspace_bytes\":" << p.ws_bytes << "}";
     p.json = js.str();
     p.valid = true;
@@ -610,6 +612,60 @@ extern "C" int hfav_plan(hfav_chain *chain, const hfav_plan_opts *opts, hfav_pla
     } catch (...) {
         return hfav_fail(HFAV_EINVAL, "host exception while planning");
     }
+}
+
+extern "C" int hfav_plan_batch(hfav_chain *chain, const hfav_plan_opts *opts, int n_grids, const int *dims,
+                               hfav_plan_info *info) {
+    if (chain) chain->plan.valid = false;
+    if (!chain || !opts || !dims) return hfav_fail(HFAV_EINVAL, "null argument");
+    if (n_grids < 1 || n_grids > HFAV_MAX_BATCH) return hfav_fail(HFAV_EINVAL, "n_grids out of range");
+    if (chain->ndim != 2) return hfav_fail(HFAV_EUNSUP, "batches are implemented for 2-D chains");
+    for (int g = 0; g < n_grids; ++g)
+        if (dims[2 * g] < 1 || dims[2 * g] > 65535 || dims[2 * g + 1] < 1 || dims[2 * g + 1] > 65535)
+            return hfav_fail(HFAV_EINVAL, "batch grid size out of range");
+    if (opts->mode == HFAV_MODE_UNFUSED) return hfav_fail(HFAV_EUNSUP, "batches run the fused kernels only");
+    hfav_plan_opts o = *opts;
+    o.dims[0] = dims[0];
+    o.dims[1] = dims[1];
+    o.dims[2] = 1;
+    o.mode = HFAV_MODE_FUSED;
+    int rc;
+    try {
+        rc = hfav_plan_impl(chain, &o, info);
+    } catch (...) {
+        rc = hfav_fail(HFAV_EINVAL, "host exception while planning");
+    }
+    if (rc != HFAV_OK) return rc;
+    HPlan &p = chain->plan;
+    if (p.family != HFAV_FAMILY_EULER_X && p.family != HFAV_FAMILY_EULER_Y && p.family != HFAV_FAMILY_SMAX) {
+        p.valid = false;
+        return hfav_fail(HFAV_EUNSUP, "batches are implemented for the Euler sweeps and their CFL reduction");
+    }
+    p.batch = true;
+    p.bnx.resize(n_grids);
+    p.bny.resize(n_grids);
+    p.bseg.resize(n_grids);
+    p.boff.resize(n_grids);
+    int64_t off = 0;
+    for (int g = 0; g < n_grids; ++g) {
+        p.bnx[g] = dims[2 * g];
+        p.bny[g] = dims[2 * g + 1];
+        p.boff[g] = off;
+        off += (int64_t)p.bnx[g] * p.bny[g];
+        const int gd[3] = {p.bnx[g], p.bny[g], 1};
+        hfav_config cg = hfav_default_config(HFAV_FAMILY_EULER_Y, chain->dtype, gd);
+        if (o.config_source == HFAV_CONFIG_FORCED) cg = o.forced;
+        else if (o.config_source == HFAV_CONFIG_TUNED) hfav_tuned_config(HFAV_FAMILY_EULER_Y, chain->dtype, gd, &cg);
+        int seg = cg.seg > 0 ? cg.seg : 16;
+        p.bseg[g] = seg > 255 ? 255 : seg;
+    }
+    p.btotal = off;
+    return HFAV_OK;
+}
+
+extern "C" int64_t hfav_batch_offset(const hfav_chain *c, int grid) {
+    if (!c || !c->plan.valid || !c->plan.batch || grid < 0 || grid >= (int)c->plan.boff.size()) return -1;
+    return c->plan.boff[grid];
 }
 
 extern "C" int hfav_plan_term(const hfav_chain *c, int index, hfav_term_info *info) {

@@ -19,7 +19,7 @@ std::vector<Entry> g_table;
 }  // namespace
 
 hfav_config hfav_default_config(int family, int dtype, const int dims[3]) {
-    hfav_config c{256, 1, 0, 0};
+    hfav_config c{256, 1, 0, 0, 0};
     // measured on MI355X at the workload sizes (64x2048x2048 hdiff, 2048^2
     // hydro, 512^3 biharmonic); the autotuner refines these per size
     switch (family) {

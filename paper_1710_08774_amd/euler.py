@@ -69,3 +69,74 @@ class EulerStepper:
 
     def dt(self, cfl=0.5):
         return cfl / float(self.smax[self.slot])
+
+
+class EulerBatchStepper:
+    """Many independent grids advanced together by the persistent batched
+    sweeps.  Fields are packed: plane q of grid g is U[q, off_g : off_g +
+    nx_g*ny_g] (row-major (ny_g, nx_g)).  Each grid has its own dt and CFL
+    slot.  `capture(steps)` records `steps` (even) steps into a HIP graph."""
+
+    def __init__(self, sizes, dtype=torch.float64, gamma=1.4, cfl=0.5, niter=10, bc=H.BC_PERIODIC,
+                 precision=H.PREC_NATIVE, config_source=H.CONFIG_DEFAULT, forced_y=None, device="cuda"):
+        self.sizes = [(int(a), int(b)) for a, b in sizes]
+        self.dtype = dtype
+        cd = H.F64 if dtype == torch.float64 else H.F32
+        if cd == H.F32 and precision == H.PREC_NATIVE:
+            precision = H.PREC_F32_F64ACC
+        self.n = len(self.sizes)
+        self.smax_chain = H.Chain(H.smax_spec(gamma, cd))
+        self.smax_chain.plan_batch(self.sizes, (bc, bc))
+        self.cx = H.Chain(H.euler_sweep_spec(0, gamma, niter, cfl, "smax", False, cd))
+        self.cy = H.Chain(H.euler_sweep_spec(1, gamma, niter, cfl, "smax", True, cd))
+        self.ix = self.cx.plan_batch(self.sizes, (bc, bc), precision=precision, config_source=config_source)
+        src_y = H.CONFIG_FORCED if forced_y is not None else config_source
+        self.iy = self.cy.plan_batch(self.sizes, (bc, bc), precision=precision, config_source=src_y,
+                                     forced=forced_y)
+        self.off = [self.cx.batch_offset(g) for g in range(self.n)]
+        self.total = self.off[-1] + self.sizes[-1][0] * self.sizes[-1][1]
+        self.U = [torch.empty((4, self.total), dtype=dtype, device=device) for _ in range(2)]
+        self.smax = torch.zeros((2, self.n), dtype=torch.float64, device=device)
+        self.slot = 0
+        self.graph = None
+
+    def cells(self):
+        return sum(a * b for a, b in self.sizes)
+
+    def load(self, states):
+        host = torch.empty((4, self.total), dtype=self.dtype)
+        for g, U in enumerate(states):
+            nx, ny = self.sizes[g]
+            host[:, self.off[g]:self.off[g] + nx * ny] = torch.as_tensor(U, dtype=self.dtype).reshape(4, -1)
+        self.U[0].copy_(host)
+        self.slot = 0
+        self.smax_chain.execute(list(self.U[0]), [self.smax[0]])
+
+    def step(self, n=1):
+        a, b = self.U
+        for _ in range(n):
+            s0, s1 = self.smax[self.slot], self.smax[1 - self.slot]
+            self.cx.execute([a[0], a[1], a[2], a[3], s0], [b[0], b[1], b[2], b[3]])
+            self.cy.execute([b[0], b[1], b[2], b[3], s0], [a[0], a[1], a[2], a[3], s1])
+            self.slot = 1 - self.slot
+
+    def capture(self, steps):
+        """Record `steps` steps (an even number, so the dt slots line up on
+        every replay) into a HIP graph."""
+        assert steps % 2 == 0
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        slot0 = self.slot
+        with torch.cuda.graph(g, stream=side):
+            self.step(steps)
+        self.slot = slot0
+        self.graph = g
+        return g
+
+    def replay(self):
+        self.graph.replay()
+
+    def grid(self, g):
+        nx, ny = self.sizes[g]
+        return self.U[0][:, self.off[g]:self.off[g] + nx * ny].reshape(4, ny, nx)

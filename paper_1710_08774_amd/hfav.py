@@ -62,7 +62,8 @@ class hfav_chain_desc(C.Structure):
 
 
 class hfav_config(C.Structure):
-    _fields_ = [("block", C.c_int), ("tile_y", C.c_int), ("seg", C.c_int), ("variant", C.c_int)]
+    _fields_ = [("block", C.c_int), ("tile_y", C.c_int), ("seg", C.c_int), ("variant", C.c_int),
+                ("xcd", C.c_int)]
 
 
 class hfav_plan_opts(C.Structure):
@@ -114,6 +115,10 @@ def lib():
     L.hfav_plan_term.argtypes = [C.c_void_p, C.c_int, C.POINTER(hfav_term_info)]
     L.hfav_plan_json.argtypes = [C.c_void_p]
     L.hfav_plan_json.restype = C.c_char_p
+    L.hfav_plan_batch.argtypes = [C.c_void_p, C.POINTER(hfav_plan_opts), C.c_int, C.POINTER(C.c_int),
+                                  C.POINTER(hfav_plan_info)]
+    L.hfav_batch_offset.argtypes = [C.c_void_p, C.c_int]
+    L.hfav_batch_offset.restype = C.c_int64
     L.hfav_tuning_clear.restype = None
     L.hfav_tuning_add.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(hfav_config)]
     _lib = L
@@ -209,13 +214,29 @@ class Chain:
              config_source=CONFIG_DEFAULT, forced=None) -> hfav_plan_info:
         dims = tuple(int(x) for x in dims) + (1,) * (3 - len(dims))
         bnd = tuple(boundary) + (BC_PERIODIC,) * (3 - len(boundary))
-        f = hfav_config(*(forced if forced is not None else (0, 0, 0, 0)))
+        f = hfav_config(*(tuple(forced) + (0,) * (5 - len(forced)) if forced is not None else (0,) * 5))
         o = hfav_plan_opts((C.c_int * 3)(*dims), (C.c_int * 3)(*bnd), mode, precision, config_source, f)
         info = hfav_plan_info()
         _check(lib().hfav_plan(self._h, C.byref(o), C.byref(info)))
         self.info = info
         self.dims = dims
         return info
+
+    def plan_batch(self, sizes, boundary=(BC_PERIODIC,) * 3, precision=PREC_NATIVE,
+                   config_source=CONFIG_DEFAULT, forced=None) -> hfav_plan_info:
+        """Plan for a batch of grids; sizes is a list of (nx, ny)."""
+        flat = (C.c_int * (2 * len(sizes)))(*[int(v) for s in sizes for v in s])
+        bnd = tuple(boundary) + (BC_PERIODIC,) * (3 - len(boundary))
+        f = hfav_config(*(tuple(forced) + (0,) * (5 - len(forced)) if forced is not None else (0,) * 5))
+        o = hfav_plan_opts((C.c_int * 3)(1, 1, 1), (C.c_int * 3)(*bnd), MODE_FUSED, precision, config_source, f)
+        info = hfav_plan_info()
+        _check(lib().hfav_plan_batch(self._h, C.byref(o), len(sizes), flat, C.byref(info)))
+        self.info = info
+        self.sizes = list(sizes)
+        return info
+
+    def batch_offset(self, g) -> int:
+        return int(lib().hfav_batch_offset(self._h, g))
 
     def execute(self, axioms, goals, workspace=None, stream=None):
         """Enqueue on `stream` (torch.cuda.Stream, raw handle, or None = current)."""
@@ -266,7 +287,7 @@ def tuning_clear():
 
 def tuning_add(family, dtype, dims, cfg):
     d = (C.c_int * 3)(*(tuple(dims) + (1,) * (3 - len(dims))))
-    c = hfav_config(*cfg)
+    c = hfav_config(*(tuple(cfg) + (0,) * (5 - len(cfg))))
     _check(lib().hfav_tuning_add(int(family), int(dtype), d, C.byref(c)))
 
 
