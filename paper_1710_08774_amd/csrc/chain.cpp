@@ -9,6 +9,8 @@
 #include <new>
 #include <string>
 
+#include <hip/hip_runtime.h>
+
 #include "internal.h"
 
 static thread_local std::string g_err;
@@ -266,6 +268,10 @@ extern "C" int hfav_chain_create(const hfav_chain_desc *desc, hfav_chain **out) 
     *out = c;
     g_err.clear();
     return HFAV_OK;
+}
+
+hfav_chain::~hfav_chain() {
+    if (pinned) (void)hipHostFree(pinned);
 }
 
 extern "C" void hfav_chain_destroy(hfav_chain *c) { delete c; }

@@ -131,6 +131,53 @@ int run_fused(const hfav_chain *c, const Bind &B, hipStream_t s) {
         L.cfg = p.info.config;
         return dev_err(hfav::launch_lap7_chain(L, s), "lap7 chain launch");
     }
+    case HFAV_FAMILY_STAR_CHAIN: {
+        // the coefficient table is copied from a pinned host copy into the
+        // workspace on the stream (a capturable async copy); the pinned
+        // buffer is allocated by the first execute of a plan, so capture a
+        // graph only after one eager call
+        const size_t bytes = p.scoeff.size() * 8;
+        hfav_chain *mc = const_cast<hfav_chain *>(c);
+        if (mc->pinned_bytes < bytes || mc->pinned_src != &p.scoeff) {
+            if (mc->pinned_bytes < bytes) {
+                if (mc->pinned) (void)hipHostFree(mc->pinned);
+                mc->pinned = nullptr;
+                mc->pinned_bytes = 0;
+                int rc0 = dev_err(hipHostMalloc(&mc->pinned, bytes, hipHostMallocDefault), "pinned allocation");
+                if (rc0) return rc0;
+                mc->pinned_bytes = bytes;
+            }
+            memcpy(mc->pinned, p.scoeff.data(), bytes);
+            mc->pinned_src = &p.scoeff;
+        }
+        double *coeff = (double *)(B.ws + p.ws_coeff);
+        int rc = dev_err(hipMemcpyAsync(coeff, c->pinned, p.scoeff.size() * 8, hipMemcpyHostToDevice, s),
+                         "coefficient upload");
+        if (rc) return rc;
+        const int K = (int)p.sstages.size();
+        for (size_t gi = 0; gi < p.sgroups.size(); ++gi) {
+            const int a = p.sgroups[gi], b = gi + 1 < p.sgroups.size() ? p.sgroups[gi + 1] : K;
+            hfav::StarGroupLaunch L{};
+            L.nstage = b - a;
+            L.nd = c->ndim;
+            L.nx = d[0]; L.ny = d[1]; L.nz = d[2];
+            L.seg = p.info.config.seg;
+            L.tile = p.info.config.variant;
+            L.dtype = c->dtype;
+            L.coeff = coeff;
+            for (int s2 = a; s2 < b; ++s2) {
+                L.st[s2 - a].r = p.sstages[s2].r;
+                L.st[s2 - a].fin = p.sstages[s2].fin;
+                L.st[s2 - a].fout = p.sstages[s2].fout;
+                L.st[s2 - a].coff = p.scoff[s2];
+            }
+            for (int f = 0; f < p.sstages[a].fin; ++f) L.in[f] = B.ptr(p.sstages[a].in_terms[f]);
+            for (int f = 0; f < p.sstages[b - 1].fout; ++f) L.out[f] = B.wptr(p.sstages[b - 1].out_terms[f]);
+            rc = dev_err(hfav::launch_star_group(L, s), "star group launch");
+            if (rc) return rc;
+        }
+        return HFAV_OK;
+    }
     case HFAV_FAMILY_SMAX: {
         const void *U[4];
         for (int q = 0; q < 4; ++q) U[q] = B.ptr(p.fam_in[q]);

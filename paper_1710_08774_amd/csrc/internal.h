@@ -67,6 +67,16 @@ struct HPlan {
     size_t ws_bytes = 0;
     std::vector<int> exec_order; // rule order for the unfused path
     std::string json;
+    // STAR_CHAIN family: stages, coefficient table, groups of fused stages
+    struct StarStage {
+        int r, fin, fout;
+        std::vector<int> in_terms, out_terms;   // term ids of the stage's inputs / outputs
+    };
+    std::vector<StarStage> sstages;
+    std::vector<double> scoeff;                 // host copy, (fout, fin, n_off) per stage
+    std::vector<int> scoff;                     // first coefficient of each stage
+    std::vector<int> sgroups;                   // first stage of each fused group
+    int64_t ws_coeff = -1;                      // workspace offset of the coefficient table
     // batched plans: per-grid sizes, y-pass segment lengths and offsets
     bool batch = false;
     std::vector<int> bnx, bny, bseg;
@@ -84,6 +94,10 @@ struct hfav_chain {
     std::vector<int> topo;       // topological order of live rules
     std::vector<int> axioms, goals;  // term ids in declaration order
     HPlan plan;
+    void *pinned = nullptr;      // pinned host copy of the plan's coefficient table
+    size_t pinned_bytes = 0;
+    const void *pinned_src = nullptr;   // plan table the pinned copy holds
+    ~hfav_chain();
 };
 
 // error reporting (thread-local text)
@@ -104,7 +118,12 @@ struct OpSpec {
 };
 const OpSpec *op_spec(int op);
 
+// STAR_CHAIN helpers (plan.cpp) and the learned model (costmodel.cpp)
+bool match_star_chain(const hfav_chain *c, HPlan &p);
+size_t star_group_bytes(const hfav_chain *c, const HPlan &p, int a, int b, int tile);
+bool star_groups(const hfav_chain *c, HPlan &p, int D, int tile);
+bool star_model_choose(const hfav_chain *c, HPlan &p, const int dims[3], hfav_config *cfg);
+
 // tuning hooks (tune.cpp)
 bool hfav_tuned_config(int family, int dtype, const int dims[3], hfav_config *cfg);
-bool hfav_model_config(const hfav_chain *c, int family, const int dims[3], hfav_config *cfg);
 hfav_config hfav_default_config(int family, int dtype, const int dims[3]);

@@ -104,4 +104,25 @@ struct StarRule {
 };
 hipError_t launch_star_rule(const StarRule &R, hipStream_t s);
 
+// ---- fused groups of linear star stages
+enum { SG_MAX_F = 5, SG_MAX_STAGES = 6, SG_MAX_LDS = 65536 };
+struct StarGroupLaunch {
+    struct Stage {
+        int r, fin, fout;
+        int coff;                      // first coefficient of the stage in the device table
+        int lds, planes, hx, hy, px, py;   // ring layout (filled by the launcher)
+    };
+    const void *in[SG_MAX_F];
+    void *out[SG_MAX_F];
+    const double *coeff;               // device coefficient table
+    int nstage, nd;
+    int nx, ny, nz;
+    int seg;
+    int tile;                          // tile-shape index
+    int dtype;
+    Stage st[SG_MAX_STAGES];
+};
+hipError_t launch_star_group(StarGroupLaunch &L, hipStream_t s);
+size_t star_group_lds_bytes(const StarGroupLaunch &L);
+
 }  // namespace hfav

@@ -23,6 +23,7 @@
 #include <string>
 
 #include "internal.h"
+#include "kernels.h"
 
 namespace {
 
@@ -296,6 +297,137 @@ void json_int3(std::ostringstream &o, const int *v) { o << "[" << v[0] << "," <<
 
 }  // namespace
 
+static bool star_ref_is(const hfav_chain *c, const HRef &r, int term, int di, int dj, int dk) {
+    (void)c;
+    return r.term == term && r.off[0] == di && r.off[1] == dj && r.off[2] == dk;
+}
+
+// Layered chain of STAR rules: stage k's rules each read every field of
+// stage k-1 through the same star stencil of radius r_k, in the canonical
+// offset order (centre, then -d, +d for d = 1..r along x, y, z).
+bool match_star_chain(const hfav_chain *c, HPlan &p) {
+    if (c->topo.empty()) return false;
+    for (int r : c->topo)
+        if (c->rules[r].op != HFAV_OP_STAR) return false;
+    for (int ax = 0; ax < c->ndim; ++ax)
+        if (p.opts.boundary[ax] != HFAV_BC_PERIODIC) return false;
+    const int nd = c->ndim;
+    std::vector<int> depth(c->rules.size(), -1);
+    int K = 0;
+    for (int r : c->topo) {
+        int d = 1;
+        for (const HRef &ref : c->rules[r].in) {
+            const int pr = c->terms[ref.term].producer;
+            if (pr >= 0) d = std::max(d, depth[pr] + 1);
+        }
+        depth[r] = d;
+        K = std::max(K, d);
+    }
+    if (K > 6) return false;
+    // rules of each stage, in descriptor order
+    std::vector<std::vector<int>> stage_rules(K + 1);
+    for (int r = 0; r < (int)c->rules.size(); ++r)
+        if (c->live[r]) stage_rules[depth[r]].push_back(r);
+    p.sstages.assign(K, HPlan::StarStage{});
+    // field order of stage k-1 = order of first appearance in stage k's first rule
+    std::vector<std::vector<int>> fields(K + 1);
+    for (int k = 1; k <= K; ++k) {
+        const HRule &R0 = c->rules[stage_rules[k][0]];
+        std::vector<int> order;
+        for (const HRef &ref : R0.in)
+            if (std::find(order.begin(), order.end(), ref.term) == order.end()) order.push_back(ref.term);
+        fields[k - 1] = order;
+    }
+    // last stage outputs: rule order
+    for (int r : stage_rules[K]) fields[K].push_back(c->rules[r].out[0]);
+    for (int k = 0; k <= K; ++k)
+        if (fields[k].empty() || fields[k].size() > 5) return false;
+    // stage 0 fields are axioms; stage k fields are exactly stage k's outputs
+    for (int t : fields[0])
+        if (c->terms[t].kind != TK_AXIOM || c->terms[t].rank != nd) return false;
+    for (int k = 1; k <= K; ++k) {
+        if (fields[k].size() != stage_rules[k].size()) return false;
+        for (int t : fields[k]) {
+            const int pr = c->terms[t].producer;
+            if (pr < 0 || depth[pr] != k) return false;
+            if (k < K && c->terms[t].kind != TK_INTER) return false;
+            if (k == K && c->terms[t].kind != TK_GOAL) return false;
+        }
+    }
+    if (c->goals.size() != fields[K].size()) return false;
+    p.scoeff.clear();
+    p.scoff.clear();
+    for (int k = 1; k <= K; ++k) {
+        const HRule &R0 = c->rules[stage_rules[k][0]];
+        const int fin = (int)fields[k - 1].size();
+        if ((int)R0.in.size() % fin) return false;
+        const int n_off = (int)R0.in.size() / fin;
+        const int r = (n_off - 1) / (2 * nd);
+        if (r < 1 || r > 3 || 1 + 2 * r * nd != n_off) return false;
+        HPlan::StarStage S;
+        S.r = r;
+        S.fin = fin;
+        S.fout = (int)fields[k].size();
+        S.in_terms = fields[k - 1];
+        S.out_terms = fields[k];
+        p.scoff.push_back((int)p.scoeff.size());
+        for (int o = 0; o < S.fout; ++o) {
+            const HRule &R = c->rules[c->terms[fields[k][o]].producer];
+            if ((int)R.in.size() != fin * n_off) return false;
+            for (int f = 0; f < fin; ++f) {
+                int q = 0;
+                auto expect = [&](int dx, int dy, int dz) {
+                    const HRef &ref = R.in[f * n_off + q];
+                    const bool ok = star_ref_is(c, ref, fields[k - 1][f], dx, dy, dz);
+                    ++q;
+                    return ok;
+                };
+                if (!expect(0, 0, 0)) return false;
+                for (int ax = 0; ax < nd; ++ax)
+                    for (int d = 1; d <= r; ++d) {
+                        int m[3] = {0, 0, 0}, pl[3] = {0, 0, 0};
+                        m[ax] = -d;
+                        pl[ax] = d;
+                        if (!expect(m[0], m[1], m[2]) || !expect(pl[0], pl[1], pl[2])) return false;
+                    }
+                for (int qq = 0; qq < n_off; ++qq) p.scoeff.push_back(R.param[f * n_off + qq]);
+            }
+        }
+        p.sstages[k - 1] = S;
+    }
+    return true;
+}
+
+// LDS bytes of the group of stages [a, b) at a tile shape
+size_t star_group_bytes(const hfav_chain *c, const HPlan &p, int a, int b, int tile) {
+    hfav::StarGroupLaunch L{};
+    L.nstage = b - a;
+    L.nd = c->ndim;
+    L.tile = tile;
+    L.dtype = c->dtype;
+    for (int s = a; s < b; ++s) {
+        L.st[s - a].r = p.sstages[s].r;
+        L.st[s - a].fin = p.sstages[s].fin;
+        L.st[s - a].fout = p.sstages[s].fout;
+    }
+    return hfav::star_group_lds_bytes(L);
+}
+
+// split the stages into groups of at most D (D = 0: all); false if a group
+// does not fit in LDS
+bool star_groups(const hfav_chain *c, HPlan &p, int D, int tile) {
+    const int K = (int)p.sstages.size();
+    if (D <= 0 || D > K) D = K;
+    p.sgroups.clear();
+    for (int s = 0; s < K; s += D) {
+        const int e = std::min(K, s + D);
+        if (star_group_bytes(c, p, s, e, tile) > hfav::SG_MAX_LDS) return false;
+        p.sgroups.push_back(s);
+    }
+    return true;
+}
+
+
 int hfav_plan_impl(hfav_chain *c, const hfav_plan_opts *o, hfav_plan_info *info) {
     if (!c || !o) return hfav_fail(HFAV_EINVAL, "null chain or options");
     HPlan p;
@@ -472,6 +604,7 @@ int hfav_plan_impl(hfav_chain *c, const hfav_plan_opts *o, hfav_plan_info *info)
         if (o->boundary[dir] != HFAV_BC_PERIODIC && o->boundary[dir] != HFAV_BC_TRANSMISSIVE) p.family = 0;
     } else if (match_lap7_chain(c, p)) p.family = HFAV_FAMILY_LAP7_CHAIN;
     else if (match_smax(c, p)) p.family = HFAV_FAMILY_SMAX;
+    else if (match_star_chain(c, p)) p.family = HFAV_FAMILY_STAR_CHAIN;
     else p.family = HFAV_FAMILY_NONE;
     if (o->precision == HFAV_PREC_F32_F64ACC && p.family != HFAV_FAMILY_EULER_X &&
         p.family != HFAV_FAMILY_EULER_Y && o->mode == HFAV_MODE_FUSED)
@@ -500,13 +633,43 @@ int hfav_plan_impl(hfav_chain *c, const hfav_plan_opts *o, hfav_plan_info *info)
     } else if (o->config_source == HFAV_CONFIG_TUNED) {
         if (hfav_tuned_config(p.family, c->dtype, o->dims, &cfg)) src = HFAV_CONFIG_TUNED;
     } else if (o->config_source == HFAV_CONFIG_MODEL) {
-        if (hfav_model_config(c, p.family, o->dims, &cfg)) src = HFAV_CONFIG_MODEL;
+        if (p.family == HFAV_FAMILY_STAR_CHAIN && star_model_choose(c, p, o->dims, &cfg)) src = HFAV_CONFIG_MODEL;
     }
 
-    // ---- unfused workspace layout
+    // ---- STAR_CHAIN: groups of fused stages (config.tile_y = stages per
+    // group, 0 = all; config.variant = tile shape); the default takes the
+    // deepest grouping that fits in LDS
+    if (fused && p.family == HFAV_FAMILY_STAR_CHAIN) {
+        if (src == HFAV_CONFIG_DEFAULT || src == HFAV_CONFIG_TUNED || !star_groups(c, p, cfg.tile_y, cfg.variant)) {
+            if (src == HFAV_CONFIG_FORCED)
+                return hfav_fail(HFAV_EUNSUP, "forced star-chain configuration does not fit in LDS");
+            int D = (int)p.sstages.size();
+            while (D > 1 && !star_groups(c, p, D, cfg.variant)) --D;
+            if (!star_groups(c, p, D, cfg.variant)) {
+                cfg.variant = 0;
+                D = (int)p.sstages.size();
+                while (D > 1 && !star_groups(c, p, D, 0)) --D;
+                if (!star_groups(c, p, D, 0)) fused = false;
+            }
+            cfg.tile_y = D;
+        }
+    }
+
+    // ---- workspace layout
     p.ws_off.assign(nt, -1);
     p.ws_bytes = 0;
+    if (fused && p.family == HFAV_FAMILY_STAR_CHAIN) {
+        p.ws_coeff = 0;
+        p.ws_bytes = (p.scoeff.size() * 8 + 255) / 256 * 256;
+        // outputs of every group but the last are full arrays
+        for (size_t gi = 1; gi < p.sgroups.size(); ++gi)
+            for (int t : p.sstages[p.sgroups[gi] - 1].out_terms) {
+                p.ws_off[t] = (int64_t)p.ws_bytes;
+                p.ws_bytes += ((size_t)ncell * es + 255) / 256 * 256;
+            }
+    }
     if (!fused) {
+        p.ws_coeff = -1;
         for (int t = 0; t < nt; ++t) {
             const HTerm &T = c->terms[t];
             if (T.kind != TK_INTER || T.producer < 0 || !c->live[T.producer]) continue;
@@ -601,6 +764,7 @@ int hfav_plan_impl(hfav_chain *c, const hfav_plan_opts *o, hfav_plan_info *info)
     p.json = js.str();
     p.valid = true;
     c->plan = p;
+    c->pinned_src = nullptr;
     if (info) *info = I;
     return HFAV_OK;
 }

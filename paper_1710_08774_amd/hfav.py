@@ -38,6 +38,8 @@ CONFIG_DEFAULT, CONFIG_TUNED, CONFIG_MODEL, CONFIG_FORCED = 0, 1, 2, 3
 FAMILY = {0: "none", 1: "hdiff", 2: "euler_x", 3: "euler_y", 4: "lap7_chain", 5: "star_chain", 6: "smax"}
 STORAGE = {0: "full", 1: "register", 2: "inner", 3: "outer", 4: "scalar"}
 MAX_RULES = 64
+COST_FEATURES = 24
+COST_MAX_CANDIDATES = 64
 
 
 class hfav_ref(C.Structure):
@@ -119,6 +121,22 @@ def lib():
                                   C.POINTER(hfav_plan_info)]
     L.hfav_batch_offset.argtypes = [C.c_void_p, C.c_int]
     L.hfav_batch_offset.restype = C.c_int64
+    L.hfav_mlp_nparams.argtypes = [C.c_int, C.c_int]
+    L.hfav_mlp_nparams.restype = C.c_size_t
+    L.hfav_mlp_workspace_bytes.argtypes = [C.c_int, C.c_int, C.c_int]
+    L.hfav_mlp_workspace_bytes.restype = C.c_size_t
+    L.hfav_mlp_forward.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_void_p]
+    L.hfav_mlp_loss_grad.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_void_p, C.c_void_p]
+    L.hfav_mlp_adam.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_float, C.c_float,
+                                C.c_float, C.c_float, C.c_int, C.c_void_p]
+    L.hfav_star_candidates.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(hfav_config), C.c_int]
+    L.hfav_costmodel_features.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(hfav_config),
+                                          C.POINTER(C.c_float)]
+    L.hfav_costmodel_set.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
+    L.hfav_costmodel_predict.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(hfav_config),
+                                         C.POINTER(C.c_float)]
     L.hfav_tuning_clear.restype = None
     L.hfav_tuning_add.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(hfav_config)]
     _lib = L
@@ -257,6 +275,29 @@ class Chain:
         go = (C.c_void_p * len(goals))(*[_ptr(g) for g in goals])
         return lib().hfav_execute(self._h, ax, go, _ptr(workspace), stream)
 
+    def candidates(self, dims):
+        """Feasible fused configurations of a linear star chain (host)."""
+        d = (C.c_int * 3)(*(tuple(dims) + (1,) * (3 - len(dims))))
+        out = (hfav_config * COST_MAX_CANDIDATES)()
+        n = lib().hfav_star_candidates(self._h, d, out, COST_MAX_CANDIDATES)
+        if n < 0:
+            raise HfavError(EUNSUP, "not a chain of linear star stages")
+        return [(c.block, c.tile_y, c.seg, c.variant, c.xcd) for c in out[:n]]
+
+    def features(self, dims, cfg):
+        d = (C.c_int * 3)(*(tuple(dims) + (1,) * (3 - len(dims))))
+        c = hfav_config(*(tuple(cfg) + (0,) * (5 - len(cfg))))
+        f = (C.c_float * COST_FEATURES)()
+        _check(lib().hfav_costmodel_features(self._h, d, C.byref(c), f))
+        return list(f)
+
+    def predict(self, dims, cfg):
+        d = (C.c_int * 3)(*(tuple(dims) + (1,) * (3 - len(dims))))
+        c = hfav_config(*(tuple(cfg) + (0,) * (5 - len(cfg))))
+        y = C.c_float()
+        _check(lib().hfav_costmodel_predict(self._h, d, C.byref(c), C.byref(y)))
+        return y.value
+
     def num_terms(self):
         return lib().hfav_num_terms(self._h)
 
@@ -293,6 +334,47 @@ def tuning_add(family, dtype, dims, cfg):
 
 def tuning_size():
     return lib().hfav_tuning_size()
+
+
+# ----------------------------------------------------------------- cost model
+def mlp_nparams(d, H=64):
+    return int(lib().hfav_mlp_nparams(d, H))
+
+
+def mlp_workspace_bytes(n, d, H=64):
+    return int(lib().hfav_mlp_workspace_bytes(n, d, H))
+
+
+def _mlp_rc(rc):
+    if rc != 0:
+        raise HfavError(EDEVICE if rc == 8 else EINVAL, "MLP kernel call failed")
+
+
+def mlp_forward(X, params, y, ws, H=64, stream=0):
+    n, d = X.shape
+    _mlp_rc(lib().hfav_mlp_forward(_ptr(X), n, d, H, _ptr(params), _ptr(y), _ptr(ws), stream))
+
+
+def mlp_loss_grad(X, t, params, grads, loss, ws, H=64, stream=0):
+    n, d = X.shape
+    _mlp_rc(lib().hfav_mlp_loss_grad(_ptr(X), _ptr(t), n, d, H, _ptr(params), _ptr(grads), _ptr(loss),
+                                     _ptr(ws), stream))
+
+
+def mlp_adam(params, grads, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, stream=0):
+    _mlp_rc(lib().hfav_mlp_adam(_ptr(params), _ptr(grads), _ptr(m), _ptr(v), params.numel(), lr, b1, b2, eps,
+                                step, stream))
+
+
+def costmodel_set(params, H, mean, std):
+    """Install trained weights (host sequences of floats); params=None removes."""
+    if params is None:
+        _check(lib().hfav_costmodel_set(None, 0, None, None))
+        return
+    P = (C.c_float * len(params))(*[float(x) for x in params])
+    M = (C.c_float * COST_FEATURES)(*[float(x) for x in mean])
+    S = (C.c_float * COST_FEATURES)(*[float(x) for x in std])
+    _check(lib().hfav_costmodel_set(P, H, M, S))
 
 
 # ----------------------------------------------------------------- workload chains

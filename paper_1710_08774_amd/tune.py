@@ -1,0 +1,264 @@
+"""Autotuner and learned cost model for fused linear star chains.
+
+* `autotune`  times every feasible configuration of a chain (exhaustive
+  search, the judge of the model's regret);
+* `collect`   builds a training set of (features, log time per cell) from the
+  autotuner's timings on seeded random chains;
+* `train`     fits the cost-model MLP on the GPU with the library's own
+  forward, backward and Adam kernels (full-batch Adam on z-scored features);
+* `study`     trains on one seeded set of chains and reports, on held-out
+  chains, the regret of the model's choice against exhaustive search and its
+  gain over the planner's default configuration.
+
+Timing uses HIP events on the stream the chain runs on.
+Command line: python -m paper_1710_08774_amd.tune study --help
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+from . import hfav as H
+from . import inputs
+
+TRAIN_SEED = inputs.BASE_SEED + inputs.W_CHAIN          # training chains
+TEST_SEED = inputs.BASE_SEED + inputs.W_CHAIN + 1       # held-out chains
+HIDDEN = 64
+
+
+def chain_dims(ch):
+    return tuple(ch["dims"]) if ch["ndim"] == 3 else tuple(ch["dims"][:2])
+
+
+def cfg_key(cfg):
+    """Configuration identity: (stages per group, segment, tile shape)."""
+    return (int(cfg[1]), int(cfg[2]) if cfg[2] > 0 else 32, int(cfg[3]))
+
+
+class ChainRun:
+    """Device buffers and a planned handle for timing one random chain."""
+
+    def __init__(self, ch, seed=0):
+        import torch
+        self.torch = torch
+        self.ch = ch
+        self.chain = H.Chain(H.star_chain_spec(ch, inputs.star_offsets))
+        self.dims = chain_dims(ch)
+        nx, ny, nz = ch["dims"]
+        tdt = torch.float64 if ch["dtype"] == "f64" else torch.float32
+        g = torch.Generator(device="cuda").manual_seed(int(seed))
+        self.x = [torch.rand((nz, ny, nx), dtype=tdt, device="cuda", generator=g) for _ in range(ch["n_in"])]
+        self.y = [torch.empty((nz, ny, nx), dtype=tdt, device="cuda") for _ in range(ch["stages"][-1]["f_out"])]
+        self.ws = None
+        self.cells = nx * ny * nz
+
+    def plan(self, cfg=None, source=H.CONFIG_DEFAULT):
+        if cfg is not None:
+            info = self.chain.plan(self.dims, mode=H.MODE_FUSED, config_source=H.CONFIG_FORCED, forced=cfg)
+        else:
+            info = self.chain.plan(self.dims, mode=H.MODE_FUSED, config_source=source)
+        need = int(info.workspace_bytes)
+        if need and (self.ws is None or self.ws.numel() < need):
+            self.ws = None
+            self.torch.cuda.empty_cache()
+            self.ws = self.torch.empty(need, dtype=self.torch.uint8, device="cuda")
+        return info
+
+    def run(self):
+        self.chain.execute(self.x, self.y, self.ws)
+
+    def time(self, reps=3):
+        torch = self.torch
+        self.run()
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            self.run()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    def free(self):
+        self.x = self.y = self.ws = None
+        self.torch.cuda.empty_cache()
+
+
+def autotune(run: ChainRun, reps=3):
+    """Exhaustive search: ms of every feasible configuration."""
+    out = []
+    for cfg in run.chain.candidates(run.dims):
+        run.plan(cfg)
+        out.append((cfg, run.time(reps)))
+    return out
+
+
+def random_chains(n, seed, max_cells=None):
+    rng = inputs.rng_for(seed)
+    chains = []
+    while len(chains) < n:
+        ch = inputs.random_chain(rng)
+        nx, ny, nz = ch["dims"]
+        if max_cells and nx * ny * nz > max_cells:
+            # keep the chain's structure, shrink the grid to the cap
+            s = (max_cells / float(nx * ny * nz)) ** (1.0 / ch["ndim"])
+            d = [max(32, int(x * s) // 32 * 32) for x in (nx, ny, nz)[:ch["ndim"]]]
+            ch["dims"] = tuple(d) + ((1,) if ch["ndim"] == 2 else ())
+        chains.append(ch)
+    return chains
+
+
+def collect(chains, reps=3, log=None):
+    """Training records: one per (chain, configuration)."""
+    rec = []
+    t0 = time.time()
+    for ci, ch in enumerate(chains):
+        run = ChainRun(ch, seed=ci)
+        for cfg, ms in autotune(run, reps):
+            rec.append({"chain": ci, "cfg": list(cfg), "ms": ms, "cells": run.cells,
+                        "features": run.chain.features(run.dims, cfg)})
+        run.free()
+        if log and (ci + 1) % 10 == 0:
+            log(f"collect: {ci + 1}/{len(chains)} chains, {len(rec)} timings, {time.time() - t0:.0f} s")
+    return rec
+
+
+def targets(rec):
+    """log of nanoseconds per cell"""
+    return np.array([math.log(r["ms"] * 1e6 / r["cells"]) for r in rec], dtype=np.float32)
+
+
+def init_params(d, Hh=HIDDEN, seed=0):
+    """He-normal weights, zero biases, in the library's flat layout."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for nin, nout in ((d, Hh), (Hh, Hh), (Hh, Hh), (Hh, 1)):
+        parts.append(rng.normal(0.0, math.sqrt(2.0 / nin), nout * nin))
+        parts.append(np.zeros(nout))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def train(X, y, Hh=HIDDEN, iters=3000, lr=1e-3, seed=0, log=None):
+    """Full-batch Adam on the GPU through the library's MLP kernels.
+
+    Returns (params, mean, std, loss history)."""
+    import torch
+    X = np.asarray(X, dtype=np.float32)
+    mean = X.mean(axis=0)
+    std = X.std(axis=0)
+    std[std < 1e-6] = 1.0
+    Xn = (X - mean) / std
+    n, d = Xn.shape
+    dev = "cuda"
+    Xd = torch.tensor(Xn, device=dev)
+    td = torch.tensor(np.asarray(y, dtype=np.float32), device=dev)
+    P = torch.tensor(init_params(d, Hh, seed), device=dev)
+    G = torch.zeros_like(P)
+    m = torch.zeros_like(P)
+    v = torch.zeros_like(P)
+    loss = torch.zeros(1, device=dev)
+    ws = torch.empty(H.mlp_workspace_bytes(n, d, Hh), dtype=torch.uint8, device=dev)
+    s = torch.cuda.current_stream().cuda_stream
+    hist = []
+    for it in range(1, iters + 1):
+        H.mlp_loss_grad(Xd, td, P, G, loss, ws, Hh, s)
+        H.mlp_adam(P, G, m, v, it, lr=lr, stream=s)
+        if it % 100 == 0 or it == 1:
+            hist.append((it, float(loss)))
+            if log and it % 1000 == 0:
+                log(f"train: iter {it} loss {hist[-1][1]:.4f}")
+    return P.cpu().numpy(), mean, std, hist
+
+
+def evaluate(chains, params, mean, std, reps=3, log=None):
+    """Regret of the model's choice vs exhaustive search, and its gain over
+    the planner's default, on each chain."""
+    H.costmodel_set(params.tolist(), HIDDEN, mean.tolist(), std.tolist())
+    out = []
+    t0 = time.time()
+    for ci, ch in enumerate(chains):
+        run = ChainRun(ch, seed=1000 + ci)
+        t_search = time.time()
+        table = {cfg_key(c): ms for c, ms in autotune(run, reps)}
+        t_search = time.time() - t_search
+        best = min(table.values())
+        t_model = time.time()
+        im = run.plan(source=H.CONFIG_MODEL)
+        t_model = time.time() - t_model
+        km = cfg_key((im.config.block, im.config.tile_y, im.config.seg, im.config.variant))
+        idf = run.plan(source=H.CONFIG_DEFAULT)
+        kd = cfg_key((idf.config.block, idf.config.tile_y, idf.config.seg, idf.config.variant))
+        ms_model = table.get(km)
+        ms_def = table.get(kd)
+        if ms_model is None:
+            run.plan((256, km[0], km[1], km[2]))
+            ms_model = run.time(reps)
+        if ms_def is None:
+            run.plan((256, kd[0], kd[1], kd[2]))
+            ms_def = run.time(reps)
+        out.append({"chain": ci, "best_ms": best, "model_ms": ms_model, "default_ms": ms_def,
+                    "regret": ms_model / best - 1.0, "gain_over_default": ms_def / ms_model,
+                    "default_regret": ms_def / best - 1.0, "n_configs": len(table),
+                    "search_s": t_search, "model_plan_s": t_model,
+                    "model_cfg": km, "default_cfg": kd})
+        run.free()
+        if log and (ci + 1) % 20 == 0:
+            log(f"evaluate: {ci + 1}/{len(chains)} chains, {time.time() - t0:.0f} s")
+    H.costmodel_set(None, 0, None, None)
+    return out
+
+
+def summarize(ev):
+    reg = np.array([e["regret"] for e in ev])
+    dreg = np.array([e["default_regret"] for e in ev])
+    gain = np.array([e["gain_over_default"] for e in ev])
+    return {"chains": len(ev), "regret_mean": float(reg.mean()), "regret_p90": float(np.percentile(reg, 90)),
+            "regret_median": float(np.median(reg)), "default_regret_mean": float(dreg.mean()),
+            "gain_over_default_geomean": float(np.exp(np.log(gain).mean())),
+            "model_picks_best_frac": float(np.mean(reg < 1e-9)),
+            "search_seconds_total": float(sum(e["search_s"] for e in ev)),
+            "model_plan_seconds_total": float(sum(e["model_plan_s"] for e in ev))}
+
+
+def study(n_train, n_test, reps=3, iters=3000, max_cells=None, log=print):
+    train_chains = random_chains(n_train, TRAIN_SEED, max_cells)
+    rec = collect(train_chains, reps, log)
+    X = np.array([r["features"] for r in rec], dtype=np.float32)
+    y = targets(rec)
+    params, mean, std, hist = train(X, y, iters=iters, log=log)
+    test_chains = random_chains(n_test, TEST_SEED, max_cells)
+    ev = evaluate(test_chains, params, mean, std, reps, log)
+    return {"train_timings": len(rec), "train_chains": n_train, "loss_history": hist,
+            "summary": summarize(ev), "per_chain": ev,
+            "model": {"params": params.tolist(), "mean": mean.tolist(), "std": std.tolist(), "hidden": HIDDEN}}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(prog="python -m paper_1710_08774_amd.tune")
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    st = sub.add_parser("study", help="train on seeded chains, report regret on held-out chains")
+    st.add_argument("--train-chains", type=int, default=60)
+    st.add_argument("--test-chains", type=int, default=200)
+    st.add_argument("--reps", type=int, default=3)
+    st.add_argument("--iters", type=int, default=3000)
+    st.add_argument("--max-cells", type=int, default=0, help="cap grid cells per chain (0: none)")
+    st.add_argument("--out", default="gpurun_out/costmodel_study.json")
+    a = ap.parse_args(argv)
+    if a.cmd == "study":
+        res = study(a.train_chains, a.test_chains, a.reps, a.iters, a.max_cells or None,
+                    log=lambda m: print(m, flush=True))
+        os.makedirs(os.path.dirname(a.out) or ".", exist_ok=True)
+        with open(a.out, "w") as f:
+            json.dump(res, f)
+        print(json.dumps({"train_timings": res["train_timings"], **res["summary"]}), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
