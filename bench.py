@@ -88,6 +88,11 @@ def run_gpu(mode, steps, warmup, U0, timing=True, dtype=None):
         out["y_ms"] = sum(e[1].elapsed_time(e[2]) for e in evs) / steps
     out["state_finite"] = bool(torch.isfinite(st.state()).all())
     out["info_fused"] = int(st.ix.fused and st.iy.fused)
+    # kernel names of the fused sweeps (variant 3 selects the strip kernels)
+    out["x_kernel"] = "euler_x_strip_kernel" if st.ix.config.variant == 3 else "euler_x_kernel"
+    out["y_kernel"] = "euler_y_strip_kernel" if st.iy.config.variant == 3 else "euler_y_kernel"
+    out["x_config"] = [st.ix.config.block, st.ix.config.seg, st.ix.config.variant]
+    out["y_config"] = [st.iy.config.block, st.iy.config.seg, st.iy.config.variant]
     return out
 
 
@@ -151,6 +156,56 @@ def bandwidth_chains(reps=10, which=("hdiff", "biharm64", "biharm32"), unfused=T
     return out
 
 
+def batched_grids(steps=50, loop_steps=4):
+    """512 independent grids of uneven sizes (sides 64..1024), each with its
+    own dt: the batched persistent sweeps with `steps` steps captured in one
+    HIP graph, against a loop of per-grid fused launches."""
+    import torch
+    from paper_1710_08774_amd import inputs
+    from paper_1710_08774_amd.euler import EulerBatchStepper, EulerStepper
+
+    sizes = inputs.batch_sizes(512)
+    states = inputs.batch_ic(sizes=sizes)
+    cells = sum(nx * ny for nx, ny in sizes)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    bt = EulerBatchStepper(sizes)
+    bt.load(states)
+    bt.step(2)
+    bt.capture(steps)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    bt.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_batch = e0.elapsed_time(e1) / steps
+    finite = bool(torch.isfinite(bt.U[0]).all())
+    del bt
+    torch.cuda.empty_cache()
+    loop = []
+    for (nx, ny), U in zip(sizes, states):
+        st = EulerStepper(nx, ny)
+        st.load(U)
+        loop.append(st)
+    for st in loop:
+        st.step(1)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(loop_steps):
+        for st in loop:
+            st.step(1)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_loop = e0.elapsed_time(e1) / loop_steps
+    del loop
+    torch.cuda.empty_cache()
+    return {"grids": len(sizes), "cells": cells, "steps_graphed": steps, "ms_per_step": ms_batch,
+            "cell_updates_per_s": cells / (ms_batch * 1e-3), "compulsory_GBs": 128 * cells / (ms_batch * 1e-3) / 1e9,
+            "loop_of_per_grid_launches": {"ms_per_step": ms_loop, "cell_updates_per_s": cells / (ms_loop * 1e-3),
+                                          "steps": loop_steps},
+            "batched_over_loop": ms_loop / ms_batch, "state_finite": finite}
+
+
 def cpu_baseline(U0, budget_s=12.0):
     import oracle
     cores = oracle.num_threads()
@@ -180,8 +235,8 @@ def main(argv=None):
                     help="only run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--no-aux", action="store_true",
                     help="skip the bandwidth-bound chains and the FP32 hydro variant")
-    ap.add_argument("--only", choices=["hdiff", "biharm64", "biharm32"], default=None,
-                    help="only time one bandwidth-bound chain (for profiling)")
+    ap.add_argument("--only", choices=["hdiff", "biharm64", "biharm32", "batch"], default=None,
+                    help="only time one bandwidth-bound chain, or the batched grids (for profiling)")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(f"bench.py: this build measures one GPU only; --gpus {a.gpus} is not supported "
@@ -204,6 +259,9 @@ def main(argv=None):
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": n * 8, "launches": 3}), flush=True)
+        return 0
+    if a.only == "batch":
+        print(json.dumps({"workload": "batch", **batched_grids()}), flush=True)
         return 0
     if a.only:
         res = bandwidth_chains(reps=a.steps, which=(a.only,), unfused=not a.no_unfused)
@@ -236,20 +294,22 @@ def main(argv=None):
         line["fused_over_unfused"] = unf["ms_per_step"] / fused["ms_per_step"]
     if timing:
         kx, ky = fused["x_ms"], fused["y_ms"]
-        dom, dur = ("euler_x_kernel", kx) if kx >= ky else ("euler_y_kernel", ky)
+        dom, dur = (fused["x_kernel"], kx) if kx >= ky else (fused["y_kernel"], ky)
         flops = FLOPS_PER_CELL_SWEEP * cells
         achieved = flops / (dur * 1e-3) / 1e12
         line["roofline"] = {"bound": "alu", "kernel": dom, "achieved": achieved,
                             "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                             "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": load_traffic(dom),
                             "avg_launch_ms": dur, "x_sweep_ms": kx, "y_sweep_ms": ky,
-                            "flops_per_launch": flops}
+                            "flops_per_launch": flops, "x_config": fused["x_config"],
+                            "y_config": fused["y_config"]}
     if not a.no_aux:
         aux = bandwidth_chains()
         f32 = run_gpu(H.MODE_FUSED, a.steps, a.warmup, U0, False, dtype=torch.float32)
         aux["euler_f32_state_f64_riemann"] = {
             "ms_per_step": f32["ms_per_step"], "cell_updates_per_s": cells / (f32["ms_per_step"] * 1e-3),
             "compulsory_GBs": 64 * cells / (f32["ms_per_step"] * 1e-3) / 1e9}
+        aux["batch_512_grids"] = batched_grids()
         line["aux"] = aux
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(U0)

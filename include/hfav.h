@@ -193,7 +193,12 @@ typedef struct {
     int tile_y;     /* family-specific second tile parameter (prefetch depth
                        of the 7-point chain), or 1 */
     int seg;        /* cells streamed per thread along the streamed axis */
-    int variant;    /* family-specific kernel variant, 0 = default */
+    int variant;    /* family-specific kernel variant, 0 = default.
+                       EULER_X / EULER_Y: 0 register budget free, 1 at least
+                       4 waves per SIMD, 2 at least 5, 3 LDS-ring strip
+                       kernel (y: block = 64 columns x 2, 4 or 8 rows).
+                       HDIFF: row prefetch depth 1 -> 1, 2 -> 2, 4 -> 8,
+                       otherwise 4.  LAP7_CHAIN and STAR_CHAIN: tile shape. */
     int xcd;        /* workgroup order over the 8 XCDs: 0 = hardware order,
                        G > 0 = runs of G consecutive tiles per XCD,
                        -1 = one contiguous range of tiles per XCD */

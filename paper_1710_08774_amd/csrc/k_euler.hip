@@ -301,6 +301,146 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(WPE))) void e
     if (a.smax_out) block_max_to<B>(smax, a.smax_out);
 }
 
+// ------------------------------------------------------------------ strip pass
+// Either direction: a workgroup of W x C lanes sweeps W adjacent lines (rows
+// for x, columns for y; lane w of a chunk row handles line line0 + w) over
+// the cells j0 .. j1-1 of each line, C cells of every line per chunk.
+// Neighbours along the sweep are other lanes, so the contracted windows are
+// LDS rings (primitive state 3 cells, plus-face state 2 cells, flux 2
+// interfaces), each value produced once; the segment recomputes two halo
+// cells and one interface at its start.  With W = 64 along x for the y pass,
+// every global access of a wave is one coalesced 512-byte row piece.
+template <class T, int W, int C>
+struct SLds {
+    static constexpr int RW = C + 2;    // cells c0-1 .. c0+C
+    static constexpr int RF = C + 1;    // cells c0-1 .. c0+C-1
+    T w[5][RW][W];      // primitive state
+    T f[4][RF][W];      // plus-face state
+    T F[4][RF][W];      // flux F(p-1/2) in the slot of cell p
+};
+
+// index along the sweep with the boundary applied (division only off the grid)
+__device__ __forceinline__ int wrap_cell(int i, int n, int bc) {
+    return (unsigned)i < (unsigned)n ? i : bwrap(i, n, bc);
+}
+
+template <class T, class A, bool G14, int W, int C>
+__device__ __forceinline__ double strip(const EArgs<T> &a, const EView<T> &v, bool xdir, int line0, int j0, int j1,
+                                        double dt, bool want_smax, SLds<T, W, C> &S) {
+    using L = SLds<T, W, C>;
+    const int t = threadIdx.x, wl = t % W, q = t / W;
+    const int n = xdir ? v.nx : v.ny;
+    const int nlines = xdir ? v.ny : v.nx;
+    const bool lact = line0 + wl < nlines;
+    const size_t sa = xdir ? (size_t)1 : (size_t)v.nx;          // stride along the sweep
+    const size_t lb = (size_t)(line0 + wl) * (xdir ? (size_t)v.nx : (size_t)1);
+    const T g = (T)a.g;
+    const T nu = (T)dt;
+    const A nuA = (A)dt;
+    double smax = 0.0;
+    auto addr = [&](int cell) { return lb + (size_t)wrap_cell(cell, n, a.bc) * sa; };
+    auto ws = [&](int cell) { return (cell - j0 + 2) % L::RW; };
+    auto fs = [&](int cell) { return (cell - j0 + 2) % L::RF; };
+    auto put = [&](int cell, const Prim<T> &w) {
+        const int sl = ws(cell);
+        S.w[0][sl][wl] = w.r; S.w[1][sl][wl] = w.un; S.w[2][sl][wl] = w.ut; S.w[3][sl][wl] = w.p;
+        S.w[4][sl][wl] = w.c;
+    };
+    auto get = [&](int cell) {
+        const int sl = ws(cell);
+        Prim<T> w;
+        w.r = S.w[0][sl][wl]; w.un = S.w[1][sl][wl]; w.ut = S.w[2][sl][wl]; w.p = S.w[3][sl][wl];
+        w.c = S.w[4][sl][wl];
+        return w;
+    };
+
+    __syncthreads();            // a previous segment of a persistent loop is done with the rings
+    // prologue: cells j0-2, j0-1, j0 (C may be below 3) and the plus face of
+    // cell j0-1
+    for (int k = q; lact && k < 3; k += C) {
+        const size_t o = addr(j0 - 2 + k);
+        put(j0 - 2 + k, euler_prim(v.rho[o], v.mn[o], v.mt[o], v.E[o], g));
+    }
+    __syncthreads();
+    if (lact && q == 0) {
+        T plus[4], minus[4];
+        slope_trace(get(j0 - 2), get(j0 - 1), get(j0), nu, plus, minus);
+        const int sl = fs(j0 - 1);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) S.f[k][sl][wl] = plus[k];
+    }
+    for (int c0 = j0; c0 <= j1; c0 += C) {
+        const int p = c0 + q;
+        const bool act = lact && p <= j1;
+        // stage 1: the cell entering the window
+        T un[4];
+        if (act) {
+            const size_t o = addr(p + 1);
+            un[0] = v.rho[o]; un[1] = v.mn[o]; un[2] = v.mt[o]; un[3] = v.E[o];
+        }
+        __syncthreads();        // the previous chunk's reads of these slots are done
+        if (act) put(p + 1, euler_prim(un[0], un[1], un[2], un[3], g));
+        __syncthreads();
+        // stage 2: slopes and trace of cell p; the plus face goes to the
+        // lane of cell p+1 through LDS, the minus face stays in registers
+        T minus[4];
+        if (act) {
+            T plus[4];
+            slope_trace(get(p - 1), get(p), get(p + 1), nu, plus, minus);
+            const int sl = fs(p);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) S.f[k][sl][wl] = plus[k];
+        }
+        __syncthreads();
+        // stage 3: Riemann problem and flux at interface p-1/2
+        if (act) {
+            T Lf[4], G[4], F[4];
+            const int sm = fs(p - 1), s0 = fs(p);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) Lf[k] = S.f[k][sm][wl];
+            riemann_T<T, G14>(Lf, minus, g, a.niter, G);
+            euler_flux(G, g, F);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) S.F[k][s0][wl] = F[k];
+        }
+        __syncthreads();
+        // stage 4: conservative update of cell p-1 (inside the grid: no wrap)
+        if (act && p > j0) {
+            const size_t o = lb + (size_t)(p - 1) * sa;
+            const int sm = fs(p - 1), s0 = fs(p);
+            const T r = euler_update(v.rho[o], S.F[0][s0][wl], S.F[0][sm][wl], nuA);
+            const T mn = euler_update(v.mn[o], S.F[1][s0][wl], S.F[1][sm][wl], nuA);
+            const T mt = euler_update(v.mt[o], S.F[2][s0][wl], S.F[2][sm][wl], nuA);
+            const T e = euler_update(v.E[o], S.F[3][s0][wl], S.F[3][sm][wl], nuA);
+            v.orho[o] = r; v.omn[o] = mn; v.omt[o] = mt; v.oE[o] = e;
+            if (want_smax) smax = fmax(smax, (double)euler_speed(r, mt, mn, e, g));
+        }
+    }
+    return smax;
+}
+
+// x pass as strips: one workgroup per row (W = 1, C = B lanes along it)
+template <class T, class A, bool G14, int B>
+__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(4))) void euler_x_strip_kernel(EArgs<T> a) {
+    __shared__ SLds<T, 1, B> S;
+    const int j = xcd_tile(blockIdx.x, a.ny, a.xcd);
+    strip<T, A, G14, 1, B>(a, full_view(a), true, j, 0, a.nx, read_dt(a.dt_src, a.dt_mode, a.cfl), false, S);
+}
+
+// y pass as strips: 64 columns x C rows per chunk, segments of a.seg rows
+template <class T, class A, bool G14, int C>
+__global__ __launch_bounds__(64 * C) __attribute__((amdgpu_waves_per_eu(4))) void euler_y_strip_kernel(EArgs<T> a) {
+    __shared__ SLds<T, 64, C> S;
+    const int ntx = (a.nx + 63) / 64, nsg = (a.ny + a.seg - 1) / a.seg;
+    const int tile = xcd_tile(blockIdx.x, ntx * nsg, a.xcd);
+    const int i0 = (tile % ntx) * 64;
+    const int j0 = (tile / ntx) * a.seg;
+    const int j1 = min(j0 + a.seg, a.ny);
+    const double smax = strip<T, A, G14, 64, C>(a, full_view(a), false, i0, j0, j1,
+                                                read_dt(a.dt_src, a.dt_mode, a.cfl), a.smax_out != nullptr, S);
+    if (a.smax_out) block_max_to<64 * C>(smax, a.smax_out);
+}
+
 // ------------------------------------------------------------------ batches
 // Many independent grids in packed buffers: grid g's plane q starts at
 // base + off_g with off_g the sum of nx*ny over the grids before it.  A
@@ -337,7 +477,7 @@ __device__ __forceinline__ EView<T> grid_view(const EArgs<T> &a, const BatchDims
 }
 
 template <class T, class A, bool G14, int B>
-__global__ __launch_bounds__(B) void euler_x_batch_kernel(EArgs<T> a, BatchDims d, long long items) {
+__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(4))) void euler_x_batch_kernel(EArgs<T> a, BatchDims d, long long items) {
     __shared__ XLds<T, B> S;
     Cursor c{0, 0, 0};
     auto rows = [&](int g) { return (long long)d.ny[g]; };
@@ -350,7 +490,7 @@ __global__ __launch_bounds__(B) void euler_x_batch_kernel(EArgs<T> a, BatchDims 
 }
 
 template <class T, class A, bool G14, int B>
-__global__ __launch_bounds__(B) void euler_y_batch_kernel(EArgs<T> a, BatchDims d, long long items) {
+__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(4))) void euler_y_batch_kernel(EArgs<T> a, BatchDims d, long long items) {
     __shared__ T s_u[3][4][B];
     Cursor c{0, 0, 0};
     auto tiles = [&](int g) {
@@ -415,20 +555,33 @@ static EArgs<T> make_args(const EulerLaunch &L) {
     return a;
 }
 
-// variant 1 asks the compiler for at least 4 waves per SIMD (the register
-// budget drops to 128 and the Riemann solver's state partly spills)
-#define EX_LAUNCH(BB, W) hipLaunchKernelGGL((euler_x_kernel<T, A, G14, BB, W>), grid, dim3(BB), 0, s, a)
-#define EY_LAUNCH(BB, W) hipLaunchKernelGGL((euler_y_kernel<T, A, G14, BB, W>), grid, dim3(BB), 0, s, a)
+// The variant sets the occupancy the compiler must reach: 0 leaves the
+// register budget free, 1 asks for at least 4 waves per SIMD (at most 128
+// VGPRs), 2 for 5 waves (96 VGPRs; the Riemann solver's state partly spills
+// to scratch).
+#define E_LAUNCH(KER, BB)                                                                     \
+    switch (L.cfg.variant) {                                                                  \
+    case 1: hipLaunchKernelGGL((KER<T, A, G14, BB, 4>), grid, dim3(BB), 0, s, a); break;      \
+    case 2: hipLaunchKernelGGL((KER<T, A, G14, BB, 5>), grid, dim3(BB), 0, s, a); break;      \
+    default: hipLaunchKernelGGL((KER<T, A, G14, BB, 1>), grid, dim3(BB), 0, s, a); break;     \
+    }
 
 template <class T, class A, bool G14>
 static hipError_t euler_x_dispatch(const EulerLaunch &L, hipStream_t s) {
     EArgs<T> a = make_args<T>(L);
     dim3 grid(L.ny);
-    const bool w4 = L.cfg.variant == 1;
+    if (L.cfg.variant == 3) {
+        switch (L.cfg.block) {
+        case 64: hipLaunchKernelGGL((euler_x_strip_kernel<T, A, G14, 64>), grid, dim3(64), 0, s, a); break;
+        case 128: hipLaunchKernelGGL((euler_x_strip_kernel<T, A, G14, 128>), grid, dim3(128), 0, s, a); break;
+        default: hipLaunchKernelGGL((euler_x_strip_kernel<T, A, G14, 256>), grid, dim3(256), 0, s, a); break;
+        }
+        return hipGetLastError();
+    }
     switch (L.cfg.block) {
-    case 64: if (w4) EX_LAUNCH(64, 4); else EX_LAUNCH(64, 1); break;
-    case 128: if (w4) EX_LAUNCH(128, 4); else EX_LAUNCH(128, 1); break;
-    default: if (w4) EX_LAUNCH(256, 4); else EX_LAUNCH(256, 1); break;
+    case 64: E_LAUNCH(euler_x_kernel, 64); break;
+    case 128: E_LAUNCH(euler_x_kernel, 128); break;
+    default: E_LAUNCH(euler_x_kernel, 256); break;
     }
     return hipGetLastError();
 }
@@ -436,18 +589,26 @@ static hipError_t euler_x_dispatch(const EulerLaunch &L, hipStream_t s) {
 template <class T, class A, bool G14>
 static hipError_t euler_y_dispatch(const EulerLaunch &L, hipStream_t s) {
     EArgs<T> a = make_args<T>(L);
+    if (L.cfg.variant == 3) {
+        // 64 columns per workgroup, block / 64 rows per chunk
+        dim3 grid(((L.nx + 63) / 64) * ((L.ny + a.seg - 1) / a.seg));
+        switch (L.cfg.block) {
+        case 128: hipLaunchKernelGGL((euler_y_strip_kernel<T, A, G14, 2>), grid, dim3(128), 0, s, a); break;
+        case 512: hipLaunchKernelGGL((euler_y_strip_kernel<T, A, G14, 8>), grid, dim3(512), 0, s, a); break;
+        default: hipLaunchKernelGGL((euler_y_strip_kernel<T, A, G14, 4>), grid, dim3(256), 0, s, a); break;
+        }
+        return hipGetLastError();
+    }
     const int B = (L.cfg.block == 64 || L.cfg.block == 128 || L.cfg.block == 256) ? L.cfg.block : 64;
     dim3 grid(((L.nx + B - 1) / B) * ((L.ny + a.seg - 1) / a.seg));
-    const bool w4 = L.cfg.variant == 1;
     switch (B) {
-    case 128: if (w4) EY_LAUNCH(128, 4); else EY_LAUNCH(128, 1); break;
-    case 256: if (w4) EY_LAUNCH(256, 4); else EY_LAUNCH(256, 1); break;
-    default: if (w4) EY_LAUNCH(64, 4); else EY_LAUNCH(64, 1); break;
+    case 128: E_LAUNCH(euler_y_kernel, 128); break;
+    case 256: E_LAUNCH(euler_y_kernel, 256); break;
+    default: E_LAUNCH(euler_y_kernel, 64); break;
     }
     return hipGetLastError();
 }
-#undef EX_LAUNCH
-#undef EY_LAUNCH
+#undef E_LAUNCH
 
 template <bool X>
 static hipError_t euler_dispatch(const EulerLaunch &L, hipStream_t s) {
@@ -514,7 +675,8 @@ static hipError_t batch_dispatch(const EulerLaunch &L, const EulerBatch &Bt, boo
     const int B = 64;
     for (int g = 0; g < Bt.n; ++g)
         items += x ? Bt.ny[g] : (long long)((Bt.nx[g] + B - 1) / B) * ((Bt.ny[g] + Bt.seg[g] - 1) / Bt.seg[g]);
-    const long long cap = (long long)(Bt.workgroups > 0 ? Bt.workgroups : 256 * 12);
+    // one-wave workgroups, four resident per SIMD
+    const long long cap = (long long)(Bt.workgroups > 0 ? Bt.workgroups : 256 * 16);
     const unsigned nwg = (unsigned)(items < cap ? items : cap);
     if (nwg == 0) return hipSuccess;
     if (x) hipLaunchKernelGGL((euler_x_batch_kernel<T, A, G14, 64>), dim3(nwg), dim3(64), 0, s, a, d, items);

@@ -3,6 +3,11 @@
 // kernel families and the unfused one-kernel-per-rule path call the same
 // functions, so the two paths evaluate identical arithmetic per cell.
 //
+// Quotients and square-root reciprocals of the Euler rules use the hardware
+// estimates refined to about one unit in the last place (frcp, frsq) rather
+// than correctly rounded division: the results differ from the oracle's by
+// rounding only, at a fraction of the instruction count.
+//
 // Template parameter T is the storage/arithmetic type (double or float).
 // In the F32_F64ACC precision the Riemann pressure iteration and the
 // conservative-update accumulation run in double whatever T is.
@@ -48,6 +53,22 @@ __device__ __forceinline__ T axpy(T a, T b, T alpha) {
 }
 
 // ------------------------------------------------------------------ euler
+// Reciprocal from the hardware estimate refined by one Newton step
+// (relative error about one unit in the last place); float keeps division.
+__device__ __forceinline__ double frcp(double d) {
+    const double r = __builtin_amdgcn_rcp(d);
+    return fma(r, fma(-d, r, 1.0), r);
+}
+__device__ __forceinline__ float frcp(float d) { return 1.0f / d; }
+
+// 1/sqrt(x) for positive finite x: hardware estimate and one third-order
+// correction (relative error about one unit in the last place)
+__device__ __forceinline__ double frsq(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y, y, 1.0);
+    return fma(y * e, fma(e, 0.375, 0.5), y);
+}
+
 // Primitive state of one cell: constoprim + equation_of_state.
 template <class T>
 struct Prim { T r, un, ut, p, c; };
@@ -56,10 +77,11 @@ template <class T>
 __device__ __forceinline__ Prim<T> euler_prim(T rho, T mn, T mt, T E, T g) {
     Prim<T> w;
     w.r = rho;
-    w.un = mn / rho;
-    w.ut = mt / rho;
+    const T ir = frcp(rho);
+    w.un = mn * ir;
+    w.ut = mt * ir;
     w.p = (g - T(1)) * (E - T(0.5) * rho * (w.un * w.un + w.ut * w.ut));
-    w.c = sqrt(g * w.p / rho);
+    w.c = sqrt(g * w.p * ir);
     return w;
 }
 
@@ -67,7 +89,7 @@ __device__ __forceinline__ Prim<T> euler_prim(T rho, T mn, T mt, T E, T g) {
 template <class T>
 __device__ __forceinline__ T vanleer(T wm, T w0, T wp) {
     T a = w0 - wm, b = wp - w0;
-    return (a * b > T(0)) ? T(2) * a * b / (a + b) : T(0);
+    return (a * b > T(0)) ? T(2) * a * b * frcp(a + b) : T(0);
 }
 
 // Characteristic half-step trace to both faces.  A wave of speed >= 0
@@ -77,12 +99,13 @@ template <class T>
 __device__ __forceinline__ void euler_trace(const Prim<T>& w, T dr, T du, T dv, T dp, T nu,
                                             T* plus, T* minus) {
     const T r = w.r, un = w.un, c = w.c;
-    const T ic2 = T(1) / (c * c);
+    const T ic = frcp(c), ic2 = ic * ic;
     const T lam0 = un - c, lam1 = un, lam3 = un + c;
-    const T a0 = T(0.5) * (dp * ic2 - r * du / c);
+    const T rduc = r * du * ic;
+    const T a0 = T(0.5) * (dp * ic2 - rduc);
     const T a1 = dr - dp * ic2;
     const T a2 = dv;
-    const T a3 = T(0.5) * (dp * ic2 + r * du / c);
+    const T a3 = T(0.5) * (dp * ic2 + rduc);
     const T h = T(0.5);
     T cp0 = lam0 >= T(0) ? h * (T(1) - nu * lam0) * a0 : T(0);
     T cp1 = lam1 >= T(0) ? h * (T(1) - nu * lam1) * a1 : T(0);
@@ -92,7 +115,7 @@ __device__ __forceinline__ void euler_trace(const Prim<T>& w, T dr, T du, T dv, 
     T cm1 = lam1 <= T(0) ? h * (T(1) + nu * lam1) * a1 : T(0);
     T cm2 = lam1 <= T(0) ? h * (T(1) + nu * lam1) * a2 : T(0);
     T cm3 = lam3 <= T(0) ? h * (T(1) + nu * lam3) * a3 : T(0);
-    const T cr = c / r, cc = c * c;
+    const T cr = c * frcp(r), cc = c * c;
     plus[0] = r + (cp0 + cp1 + cp3);
     plus[1] = un + cr * (cp3 - cp0);
     plus[2] = w.ut + cp2;
@@ -103,27 +126,26 @@ __device__ __forceinline__ void euler_trace(const Prim<T>& w, T dr, T du, T dv, 
     minus[3] = w.p - cc * (cm0 + cm3);
 }
 
-// Reciprocal from the hardware estimate refined by one Newton step
-// (relative error about one unit in the last place).
-__device__ __forceinline__ double frcp(double d) {
-    const double r = __builtin_amdgcn_rcp(d);
-    return fma(r, fma(-d, r, 1.0), r);
-}
-
 // x^(-1/7) for x > 0: a single-precision hardware log2/exp2 estimate
 // (relative error e0 ~ 1e-7) refined by one third-order step of the
 // iteration for w^-7 = x: with e = 1 - x w^7, the exact correction factor is
 // (1 - e)^(-1/7) = 1 + e/7 + 4e^2/49 + O(e^3), so the error after the step is
-// O(e0^3), far below double rounding.  Outside the single-precision normal
-// range it defers to pow.
+// O(e0^3), far below double rounding.  Arguments outside the
+// single-precision normal range are first scaled exactly by 2^(-7k), with k
+// from the binary exponent, and the root by 2^k afterwards.
 __device__ __forceinline__ double rroot7(double x) {
-    if (!(x > 1e-30 && x < 1e30)) return pow(x, -1.0 / 7.0);
+    int k = 0;
+    if (!(x > 1e-30 && x < 1e30)) {
+        k = __builtin_amdgcn_frexp_exp(x);                      // x = m 2^e, m in [1/2, 1)
+        k = (k >= 0 ? k : k - 6) / 7;                           // floor(e / 7)
+        x = __builtin_amdgcn_ldexp(x, -7 * k);
+    }
     const float l = __builtin_amdgcn_logf((float)x);            // log2
     const double w = (double)__builtin_amdgcn_exp2f(l * (-1.0f / 7.0f));
     const double w2 = w * w, w4 = w2 * w2, w7 = w4 * w2 * w;
     const double e = fma(-x, w7, 1.0);
     const double t = e * fma(e, 4.0 / 49.0, 1.0 / 7.0);
-    return fma(w, t, w);
+    return __builtin_amdgcn_ldexp(fma(w, t, w), -k);
 }
 
 // Pressure-function data of one side of the Riemann problem (Toro ch. 4).
@@ -140,11 +162,11 @@ template <bool G14>
 __device__ __forceinline__ Side make_side(double r, double u, double p, double g) {
     Side s;
     s.r = r; s.u = u; s.p = p;
-    const double t = rsqrt(g * p * r);        // 1/(rho c), since rho c = sqrt(g p rho)
+    const double t = frsq(g * p * r);         // 1/(rho c), since rho c = sqrt(g p rho)
     s.irc = t;
     s.c = g * p * t;                          // c = sqrt(g p / rho)
     s.ip = frcp(p);
-    s.sA = sqrt(2.0 / (g + 1.0)) * rsqrt(r);  // sqrt(2/((g+1) rho))
+    s.sA = sqrt(2.0 / (g + 1.0)) * frsq(r);   // sqrt(2/((g+1) rho))
     s.B = (g - 1.0) / (g + 1.0) * p;
     s.k2 = 2.0 / (g - 1.0) * s.c;
     return s;
@@ -156,7 +178,7 @@ __device__ __forceinline__ Side make_side(double r, double u, double p, double g
 template <bool G14>
 __device__ __forceinline__ void pres_fun(const Side& s, double p, double g, double& f, double& fd) {
     if (p > s.p) {
-        double rs = rsqrt(p + s.B);           // 1/sqrt(p+B)
+        double rs = frsq(p + s.B);            // 1/sqrt(p+B)
         double q = s.sA * rs;
         double dp = p - s.p;
         f = dp * q;
@@ -238,7 +260,7 @@ __device__ __forceinline__ void riemann0(const double* L, const double* R, doubl
         double pm = p * s.ip;
         double sk = uk - s.c * sqrt(g2 * pm + g1);
         if (0.0 <= sk) { rr = s.r; uu = uk; pp = s.p; }
-        else { rr = s.r * (pm + g6) / (pm * g6 + 1.0); uu = ustar; pp = p; }
+        else { rr = s.r * (pm + g6) * frcp(pm * g6 + 1.0); uu = ustar; pp = p; }
     } else {                                 // rarefaction
         double sh = uk - s.c;
         if (0.0 <= sh) { rr = s.r; uu = uk; pp = s.p; }
@@ -248,7 +270,7 @@ __device__ __forceinline__ void riemann0(const double* L, const double* R, doubl
             double st = ustar - s.c * z;
             if (0.0 > st) { rr = s.r * zig; uu = ustar; pp = p; }
             else {
-                double cf = g5 + g6 / s.c * uk;
+                double cf = g5 + g6 * frcp(s.c) * uk;
                 double c5, c7;
                 pow_fan<G14>(cf, g, c5, c7);
                 rr = s.r * c5;
@@ -266,7 +288,7 @@ __device__ __forceinline__ void riemann0(const double* L, const double* R, doubl
 template <class T>
 __device__ __forceinline__ void euler_flux(const T* G, T g, T* F) {
     const T r = G[0], un = G[1], ut = G[2], p = G[3];
-    const T et = p / (g - T(1)) + T(0.5) * r * (un * un + ut * ut);
+    const T et = p * frcp(g - T(1)) + T(0.5) * r * (un * un + ut * ut);
     F[0] = r * un;
     F[1] = r * un * un + p;
     F[2] = r * un * ut;
@@ -282,9 +304,10 @@ __device__ __forceinline__ T euler_update(T u, T fp, T fm, A nu) {
 // Largest signal speed of one cell, max(|u|+c, |v|+c).
 template <class T>
 __device__ __forceinline__ T euler_speed(T rho, T mx, T my, T E, T g) {
-    T u = mx / rho, v = my / rho;
+    const T ir = frcp(rho);
+    T u = mx * ir, v = my * ir;
     T p = (g - T(1)) * (E - T(0.5) * rho * (u * u + v * v));
-    T c = sqrt(g * p / rho);
+    T c = sqrt(g * p * ir);
     return fmax(fabs(u) + c, fabs(v) + c);
 }
 

@@ -24,14 +24,31 @@ hfav_config hfav_default_config(int family, int dtype, const int dims[3]) {
     // hydro, 512^3 biharmonic); the autotuner refines these per size
     switch (family) {
     case HFAV_FAMILY_HDIFF: c.block = 256; c.seg = 128; c.variant = 0; break;
-    case HFAV_FAMILY_EULER_X: c.block = 64; break;
-    case HFAV_FAMILY_EULER_Y: c.block = 64; c.seg = 16; break;
+    case HFAV_FAMILY_EULER_X:   // one workgroup per row: wide rows take 4 waves
+        c.block = dims[0] >= 1024 ? 256 : (dims[0] >= 256 ? 128 : 64);
+        c.variant = 1;
+        break;
+    case HFAV_FAMILY_EULER_Y:
+        if (dims[0] >= 1024 && dims[1] >= 1024) {
+            // LDS-ring strips of 64 columns x 8 rows per chunk; segments as
+            // long as keeps about 512 eight-wave workgroups in flight
+            const double cells = (double)dims[0] * dims[1];
+            int seg = 16;
+            while (seg < 128 && cells / (64.0 * 2 * seg) >= 512) seg *= 2;
+            c.block = 512;
+            c.seg = seg;
+            c.variant = 3;
+        } else {                // one lane per column, windows in registers
+            c.block = 64;
+            c.seg = 16;
+            c.variant = 1;
+        }
+        break;
     case HFAV_FAMILY_LAP7_CHAIN:
         c.block = 1024; c.seg = 64; c.variant = 5; c.tile_y = dtype == HFAV_F64 ? 2 : 4;
         break;
     default: break;
     }
-    (void)dims;
     return c;
 }
 

@@ -93,7 +93,9 @@ def test_euler_sweep_parity(shape, direction, mode):
 
 
 @pytest.mark.parametrize("direction,cfg", [(0, (64, 1, 0, 0)), (0, (256, 1, 0, 0)),
-                                           (1, (128, 1, 3, 0)), (1, (256, 1, 64, 0)), (1, (64, 1, 1, 0))])
+                                           (1, (128, 1, 3, 0)), (1, (256, 1, 64, 0)), (1, (64, 1, 1, 0)),
+                                           (0, (64, 1, 0, 3)), (0, (256, 1, 0, 3)), (1, (256, 1, 16, 3)),
+                                           (1, (128, 1, 5, 3)), (1, (512, 1, 64, 3)), (1, (256, 1, 1, 3))])
 def test_euler_sweep_tile_configs(direction, cfg):
     U = inputs.euler_ic(300, 70, seed=12, amp=0.05)
     dt = 0.5 / oracle.euler_smax(U)
@@ -103,7 +105,8 @@ def test_euler_sweep_tile_configs(direction, cfg):
 
 
 @pytest.mark.parametrize("direction", [0, 1])
-def test_euler_transmissive_sweep(direction):
+@pytest.mark.parametrize("strip", [False, True])
+def test_euler_transmissive_sweep(direction, strip):
     n = 128
     x = (np.arange(n) + 0.5) / n
     rho = np.where(x < 0.5, 1.0, 0.125)
@@ -118,7 +121,8 @@ def test_euler_transmissive_sweep(direction):
         for _ in range(10):
             dt = 0.5 / oracle.euler_smax(V)
             V = oracle.euler_sweep(V, direction, dt, bc=oracle.BC_TRANSMISSIVE)
-            W = _sweep_gpu(W, direction, dt, mode, bc=H.BC_TRANSMISSIVE)
+            forced = ((256, 1, 16, 3) if strip else None) if mode == H.MODE_FUSED else None
+            W = _sweep_gpu(W, direction, dt, mode, bc=H.BC_TRANSMISSIVE, forced=forced)
         assert max(field_errs(W, V)) <= TOL64
 
 
@@ -140,6 +144,18 @@ def test_euler_run_parity(mode):
     st.step(steps)
     got = host(st.state())
     assert max(field_errs(got, ref)) <= TOL64
+
+
+@pytest.mark.parametrize("shape", [(96, 80), (200, 33)])
+def test_euler_run_parity_strip_kernels(shape):
+    # both sweeps as LDS-ring strips, the CFL reduction fused into the y strip
+    nx, ny = shape
+    U = inputs.euler_ic(nx, ny, seed=102)
+    ref, _ = oracle.euler_run(U, 30)
+    st = EulerStepper(nx, ny, forced_x=(256, 1, 0, 3), forced_y=(256, 1, 16, 3))
+    st.load(U)
+    st.step(30)
+    assert max(field_errs(host(st.state()), ref)) <= TOL64
 
 
 def test_euler_config_workload_two_steps_full_size():
@@ -185,6 +201,61 @@ def test_smax_reduction_matches_oracle():
     st.load(U)
     torch.cuda.synchronize()
     assert abs(float(st.smax[0]) - oracle.euler_smax(U)) <= 1e-15 * oracle.euler_smax(U)
+
+
+# ------------------------------------------------------------------ Riemann solver alone
+def _riemann_gpu(WL, WR, gamma=1.4):
+    """One EULER_RIEMANN rule over a 1 x n periodic row: interface m reads the
+    plus face at m and the minus face at m+1, so minus[m+1] = WR[m]."""
+    n = len(WL)
+    z, e = (0, 0, 0), (1, 0, 0)
+    plus, minus, gst = [f"p{q}" for q in range(4)], [f"m{q}" for q in range(4)], [f"g{q}" for q in range(4)]
+    spec = H.ChainSpec(ndim=2, axioms=[(t, 2) for t in plus + minus], goals=gst,
+                       rules=[H.Rule("EULER_RIEMANN", [(t, z) for t in plus] + [(t, e) for t in minus], gst,
+                                     [gamma, oracle.NEWTON_ITERS])])
+    c = H.Chain(spec)
+    info = c.plan((n, 1), mode=H.MODE_UNFUSED)
+    ins = [dev(WL[:, q][None, :]) for q in range(4)] + [dev(np.roll(WR[:, q], 1)[None, :]) for q in range(4)]
+    outs = [torch.empty((1, n), dtype=torch.float64, device="cuda") for _ in range(4)]
+    ws = torch.empty(info.workspace_bytes, dtype=torch.uint8, device="cuda") if info.workspace_bytes else None
+    c.execute(ins, outs, ws)
+    return np.stack([host(o)[0] for o in outs], axis=1)
+
+
+def _extreme_riemann_states():
+    """Double rarefactions whose star pressure falls 10..40 decades below the
+    side pressures (including vacuum generation, where the pressure floor
+    holds), and shock tubes with pressure jumps of up to 35 decades."""
+    rng = inputs.rng_for(inputs.BASE_SEED + 99)
+    L, R = [], []
+    for s in np.linspace(3.0, 5.5, 40):                  # u = s c on each side
+        pk = 10.0 ** rng.uniform(15, 30)
+        c = np.sqrt(1.4 * pk)
+        L.append((1.0, -s * c, 0.3, pk))
+        R.append((1.0, s * c, -0.2, pk))
+    for d in np.linspace(5, 35, 31):
+        L.append((1.0, 0.0, 0.0, 10.0 ** (d / 2)))
+        R.append((10.0 ** rng.uniform(-2, 2), 0.0, 0.0, 10.0 ** (-d / 2)))
+    return np.array(L), np.array(R)
+
+
+def test_riemann_rule_parity():
+    """The device Riemann solver against the oracle's, problem by problem,
+    on admissible random states and on extreme pressure ratios (the latter
+    reach the exact power-of-two range reduction of the seventh-root)."""
+    WL, WR = inputs.riemann_states(4096, seed=inputs.BASE_SEED + 98)
+    XL, XR = _extreme_riemann_states()
+    WL, WR = np.concatenate([WL, XL]), np.concatenate([WR, XR])
+    ref, ps, _, _ = oracle.riemann(WL, WR)
+    assert np.isfinite(ref).all()
+    x = np.minimum(ps / WL[:, 3], ps / WR[:, 3])
+    assert x.min() < 1e-35                               # the range-reduced branch is exercised
+    got = _riemann_gpu(WL, WR)
+    vscale = np.maximum.reduce([np.abs(WL[:, 1]), np.abs(WR[:, 1]), np.sqrt(1.4 * WL[:, 3] / WL[:, 0]),
+                                np.sqrt(1.4 * WR[:, 3] / WR[:, 0])])
+    for q, scale in ((0, np.abs(ref[:, 0])), (1, vscale), (2, np.abs(ref[:, 2]) + vscale), (3, np.abs(ref[:, 3]))):
+        err = np.abs(got[:, q] - ref[:, q]) / scale
+        assert err.max() <= TOL64, (q, int(err.argmax()), float(err.max()))
 
 
 # ------------------------------------------------------------------ biharmonic

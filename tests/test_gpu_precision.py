@@ -1,7 +1,10 @@
 """Precision variant: FP32 storage and arithmetic with the Riemann pressure
 iteration and the conservative-update accumulation in FP64, against the FP64
-oracle.  The per-field bounds below are the measured errors (rounded up to
-the next power of two); the JSON report in gpurun_out/ holds the values."""
+oracle.  Hydro bound: the state is rounded to FP32 once per sweep (relative
+error at most u = 2^-24 per element), and the scheme does not amplify
+perturbations, so after n steps (2n sweeps) the normwise relative error of
+each field stays below 2n u.  The measured errors, a few times smaller, are
+written to the JSON report in gpurun_out/."""
 import json
 import math
 import os
@@ -18,8 +21,10 @@ from paper_1710_08774_amd.euler import EulerStepper
 
 pytestmark = pytest.mark.gpu
 FIELDS = ("rho", "rho_u", "rho_v", "E")
-# normwise relative error bounds after 100 steps at 256x192 (FP32 state)
-BOUND_100 = {"rho": 2 ** -18, "rho_u": 2 ** -20, "rho_v": 2 ** -20, "E": 2 ** -20}
+# normwise relative error bound per field after 100 steps at 256x192 (FP32
+# state): one FP32 rounding per sweep, accumulated linearly
+U32 = 2.0 ** -24
+BOUND_100 = {f: 2 * 100 * U32 for f in ("rho", "rho_u", "rho_v", "E")}
 
 
 def _report(name, data):
