@@ -114,6 +114,117 @@ __global__ __launch_bounds__(B) void hdiff_kernel(HArgs<T> a) {
     }
 }
 
+// ------------------------------------------------------------------ DPP variant
+// Neighbour exchange along the lane axis through DPP lane shifts instead of
+// LDS ("inner rotation" in registers): lane l takes lane l-1's value with
+// wave_shr:1 and lane l+1's with wave_shl:1, a VALU move.  Each lane then
+// computes one Laplacian per row instead of three; only the two lanes at
+// the edges of each wave read their missing neighbour from the LDS row ring
+// (filled as in the kernel above).  The column's rows j .. j+2 stay in
+// registers.  Arithmetic is unchanged, so results are bit-identical.
+__device__ __forceinline__ int dpp_from_left(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false);    // wave_shr:1
+}
+__device__ __forceinline__ int dpp_from_right(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false);    // wave_shl:1
+}
+template <bool LEFT>
+__device__ __forceinline__ double lane_shift(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = (int)(b & 0xffffffffLL), hi = (int)(b >> 32);
+    const int rlo = LEFT ? dpp_from_left(lo) : dpp_from_right(lo);
+    const int rhi = LEFT ? dpp_from_left(hi) : dpp_from_right(hi);
+    return __longlong_as_double(((long long)rhi << 32) | (unsigned int)rlo);
+}
+template <bool LEFT>
+__device__ __forceinline__ float lane_shift(float v) {
+    const int b = __float_as_int(v);
+    return __int_as_float(LEFT ? dpp_from_left(b) : dpp_from_right(b));
+}
+
+template <class T, int B, int P>
+__global__ __launch_bounds__(B) void hdiff_dpp_kernel(HArgs<T> a) {
+    constexpr int W = B + 4;
+    __shared__ T ring[4][W];
+    const int t = threadIdx.x, lane = t & 63;
+    const int ni = a.ni, nj = a.nj;
+    const int ntx = (ni + B - 1) / B, nsg = (nj + a.seg - 1) / a.seg;
+    const int tile = xcd_tile(blockIdx.x, ntx * nsg * a.nk, a.xcd);
+    const int i0 = (tile % ntx) * B;
+    const int j0 = ((tile / ntx) % nsg) * a.seg;
+    const int j1 = min(j0 + a.seg, a.nj);
+    const int k = tile / (ntx * nsg);
+    const T *plane = a.in + (size_t)k * nj * ni;
+    T *oplane = a.out + (size_t)k * nj * ni;
+    const int col = pwrap(i0 + t, ni);
+    const int hs = t < 2 ? t : t + B;
+    const int hcol = pwrap(i0 - 2 + hs, ni);
+    const bool halo = t < 4;
+    auto fetch = [&](int j, T &v, T &h) {
+        const T *r = plane + (size_t)pwrap(j, nj) * ni;
+        v = r[col];
+        if (halo) h = r[hcol];
+    };
+    auto commit = [&](int j, T v, T h) {
+        T *s = ring[j & 3];
+        s[t + 2] = v;
+        if (halo) s[hs] = h;
+    };
+    auto L = [&](int j, int d) { return ring[j & 3][t + 2 + d]; };
+    auto lap_at = [&](int j, int d) {
+        return hdiff_lap(L(j, d), L(j, d + 1), L(j, d - 1), L(j + 1, d), L(j - 1, d));
+    };
+
+    T pv[P], ph[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        ph[q] = T(0);
+        pv[q] = T(0);
+        if (j0 + 2 + q <= j1 + 1) fetch(j0 + 2 + q, pv[q], ph[q]);
+    }
+    T u0 = T(0), u1 = T(0);
+    for (int r = -2; r <= 1; ++r) {
+        T v, h = T(0);
+        fetch(j0 + r, v, h);
+        commit(j0 + r, v, h);
+        if (r == 0) u0 = v;
+        if (r == 1) u1 = v;
+    }
+    __syncthreads();
+    T uw0 = L(j0, -1), ue0 = L(j0, 1);
+    T la = lap_at(j0, -1), lb = lap_at(j0, 0), lc = lap_at(j0, 1);
+    T fym = hdiff_flux(lap_at(j0 - 1, 0), lb, L(j0 - 1, 0), u0);
+    __syncthreads();
+
+    for (int jb = j0; jb < j1; jb += P) {
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            const int j = jb + q;
+            if (j >= j1) break;
+            const T u2 = pv[q];
+            commit(j + 2, pv[q], ph[q]);
+            if (j + 2 + P <= j1 + 1) fetch(j + 2 + P, pv[q], ph[q]);
+            __syncthreads();
+            // row j+1: neighbours by lane shifts, wave edges from the ring
+            T uw1 = lane_shift<true>(u1), ue1 = lane_shift<false>(u1);
+            if (lane == 0) uw1 = L(j + 1, -1);
+            if (lane == 63) ue1 = L(j + 1, 1);
+            const T nb = hdiff_lap(u1, ue1, uw1, u2, u0);
+            T na = lane_shift<true>(nb), nc = lane_shift<false>(nb);
+            if (lane == 0) na = lap_at(j + 1, -1);
+            if (lane == 63) nc = lap_at(j + 1, 1);
+            const T fx0 = hdiff_flux(lb, lc, u0, ue0);
+            const T fxm = hdiff_flux(la, lb, uw0, u0);
+            const T fy0 = hdiff_flux(lb, nb, u0, u1);
+            if (i0 + t < ni) oplane[(size_t)j * ni + i0 + t] = hdiff_out(u0, fx0, fxm, fy0, fym, a.coeff);
+            fym = fy0;
+            la = na; lb = nb; lc = nc;
+            uw0 = uw1; ue0 = ue1;
+            u0 = u1; u1 = u2;
+        }
+    }
+}
+
 template <class T>
 static hipError_t hdiff_dispatch(const HdiffLaunch &L, hipStream_t s) {
     HArgs<T> a;
@@ -125,10 +236,17 @@ static hipError_t hdiff_dispatch(const HdiffLaunch &L, hipStream_t s) {
     a.xcd = L.cfg.xcd;
     int B = L.cfg.block;
     if (B != 64 && B != 128 && B != 256 && B != 512) B = 256;
-    // variant: prefetch depth (rows in flight per workgroup) 1, 2, 4 or 8
-    const int P = L.cfg.variant == 1 ? 1 : L.cfg.variant == 2 ? 2 : L.cfg.variant == 4 ? 8 : 4;
+    // variant: bit 3 selects the DPP kernel; the low bits give the prefetch
+    // depth (rows in flight per workgroup) 1 -> 1, 2 -> 2, 4 -> 8, else 4
+    const bool dpp = (L.cfg.variant & 8) != 0;
+    const int pv = L.cfg.variant & 7;
+    const int P = pv == 1 ? 1 : pv == 2 ? 2 : pv == 4 ? 8 : 4;
     dim3 grid(((L.ni + B - 1) / B) * ((L.nj + a.seg - 1) / a.seg) * L.nk);
-#define HD_LAUNCH(BB, PP) hipLaunchKernelGGL((hdiff_kernel<T, BB, PP>), grid, dim3(BB), 0, s, a)
+#define HD_LAUNCH(BB, PP)                                                                        \
+    do {                                                                                         \
+        if (dpp) hipLaunchKernelGGL((hdiff_dpp_kernel<T, BB, PP>), grid, dim3(BB), 0, s, a);    \
+        else hipLaunchKernelGGL((hdiff_kernel<T, BB, PP>), grid, dim3(BB), 0, s, a);            \
+    } while (0)
 #define HD_P(BB)                               \
     switch (P) {                               \
     case 1: HD_LAUNCH(BB, 1); break;           \

@@ -127,6 +127,142 @@ __global__ __launch_bounds__(TX * TY) void lap7_chain_kernel(BArgs<T> a) {
     }
 }
 
+// Variant with the z windows in registers.  Every lane owns up to two points
+// of the (TX+4) x (TY+4) u tile for the whole segment and keeps, per point,
+// u at planes k..k+2 and lap1 at planes k-1..k in registers; only the x-y
+// neighbours go through LDS, one plane of u and one of lap1 at a time (each
+// double-buffered), so a plane costs 4 + 4 LDS reads per point instead of
+// 7 + 7 and needs no per-point index arithmetic.  Two barriers per plane.
+// Lane t owns point t; the points past NT are dealt out to the waves in
+// equal contiguous runs, so every wave carries the same load between
+// barriers and its accesses stay coalesced.
+template <class T, int TX, int TY, int P>
+__global__ __launch_bounds__(TX * TY) void lap7_reg_kernel(BArgs<T> a) {
+    constexpr int NT = TX * TY;
+    constexpr int UX = TX + 4, UY = TY + 4, NU = UX * UY;
+    constexpr int M = 2;
+    constexpr int NW = NT / 64;
+    constexpr int EW = (NU - NT + NW - 1) / NW;     // extra points per wave
+    static_assert(NT % 64 == 0 && NU > NT && EW <= 64, "tile must need at most two points per lane");
+    __shared__ T su[2][NU];
+    __shared__ T sl[2][NU];
+    const int tid = threadIdx.x;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY, nsg = (nz + a.seg - 1) / a.seg;
+    const int tile = xcd_tile(blockIdx.x, ntx * nty * nsg, a.xcd);
+    const int x0 = (tile % ntx) * TX, y0 = ((tile / ntx) % nty) * TY;
+    const int k0 = (tile / (ntx * nty)) * a.seg;
+    const int k1 = min(k0 + a.seg, nz);
+    const size_t plane = (size_t)nx * ny;
+    // owned points (index q in the u tile, row-major with row UX)
+    int qi[M], goff[M], obase[M];
+    bool ou[M], ol[M], oo[M];
+    qi[0] = tid;
+    qi[1] = (tid % 64) < EW ? NT + EW * (tid / 64) + tid % 64 : NU;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int q = qi[m];
+        const int px = q % UX, py = q / UX;
+        ou[m] = q < NU;
+        ol[m] = ou[m] && px >= 1 && px < UX - 1 && py >= 1 && py < UY - 1;
+        const int gx = x0 + px - 2, gy = y0 + py - 2;
+        oo[m] = ou[m] && px >= 2 && px < UX - 2 && py >= 2 && py < UY - 2 && gx < nx && gy < ny;
+        goff[m] = ou[m] ? w3(gy, ny) * nx + w3(gx, nx) : 0;
+        obase[m] = oo[m] ? gy * nx + gx : 0;
+    }
+    auto fetch = [&](int k, T *v) {
+        const T *p = a.in + (size_t)w3(k, nz) * plane;
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+            if (ou[m]) v[m] = p[goff[m]];
+    };
+    // 7-point Laplacian of a plane held in LDS at owned point m, with the
+    // z neighbours t (plane above) and b (plane below) from registers
+    auto lap_at = [&](const T *pl, int m, T c, T t, T b) {
+        const int q = qi[m];
+        return lap7(c, pl[q + 1], pl[q - 1], pl[q + UX], pl[q - UX], t, b);
+    };
+
+    T ua[M], ub[M], uc[M], la[M], lb[M];
+    T pv[P][M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        ua[m] = ub[m] = uc[m] = la[m] = lb[m] = T(0);
+#pragma unroll
+        for (int q = 0; q < P; ++q) pv[q][m] = T(0);
+    }
+    // prologue: u(k0-2) .. u(k0+2); lap1(k0-1) to registers, lap1(k0) to
+    // registers and LDS
+    {
+        T t0[M], t1[M];
+        fetch(k0 - 2, t0);
+        fetch(k0 - 1, t1);
+        fetch(k0, ua);
+        fetch(k0 + 1, ub);
+        fetch(k0 + 2, uc);
+#pragma unroll
+        for (int q = 0; q < P; ++q)
+            if (k0 + 3 + q <= k1 + 1) fetch(k0 + 3 + q, pv[q]);
+        T *s1 = su[(k0 - 1) & 1];
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+            if (ou[m]) s1[qi[m]] = t1[m];
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+            if (ol[m]) la[m] = lap_at(s1, m, t1[m], ua[m], t0[m]);
+        T *s0 = su[k0 & 1];
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+            if (ou[m]) s0[qi[m]] = ua[m];
+        __syncthreads();
+        T *l0 = sl[k0 & 1];
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+            if (ol[m]) {
+                lb[m] = lap_at(s0, m, ua[m], ub[m], t1[m]);
+                l0[qi[m]] = lb[m];
+            }
+    }
+    for (int kb = k0; kb < k1; kb += P) {
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            const int k = kb + q;
+            if (k >= k1) break;
+            T *sup = su[(k + 1) & 1];
+#pragma unroll
+            for (int m = 0; m < M; ++m)
+                if (ou[m]) sup[qi[m]] = ub[m];
+            __syncthreads();
+            // lap1 at plane k+1
+            T lc[M];
+            T *slp = sl[(k + 1) & 1];
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                lc[m] = T(0);
+                if (ol[m]) {
+                    lc[m] = lap_at(sup, m, ub[m], uc[m], ua[m]);
+                    slp[qi[m]] = lc[m];
+                }
+            }
+            __syncthreads();
+            // lap2 and the update at plane k
+            const T *slk = sl[k & 1];
+            T *out = a.out + (size_t)k * plane;
+#pragma unroll
+            for (int m = 0; m < M; ++m)
+                if (oo[m]) out[obase[m]] = axpy(ua[m], lap_at(slk, m, lb[m], lc[m], la[m]), a.alpha);
+            // rotate the z windows; the prefetched plane k+3 enters
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                ua[m] = ub[m]; ub[m] = uc[m]; uc[m] = pv[q][m];
+                la[m] = lb[m]; lb[m] = lc[m];
+            }
+            if (k + 3 + P <= k1 + 1) fetch(k + 3 + P, pv[q]);
+        }
+    }
+}
+
 template <class T>
 static hipError_t lap7_dispatch(const Lap7ChainLaunch &L, hipStream_t s) {
     BArgs<T> a;
@@ -142,7 +278,11 @@ static hipError_t lap7_dispatch(const Lap7ChainLaunch &L, hipStream_t s) {
     case 2: tx = 64; ty = 8; break;
     case 3: tx = 128; ty = 2; break;
     case 4: tx = 32; ty = 4; break;
-    case 5: tx = 64; ty = 16; break;
+    case 5: case 10: tx = 64; ty = 16; break;
+    case 11: tx = 64; ty = 8; break;
+    case 12: tx = 32; ty = 8; break;
+    case 13: tx = 128; ty = 8; break;
+    case 14: tx = 32; ty = 16; break;
     default: break;
     }
     // tile_y selects the prefetch depth (planes in flight): 1, 2 or 4
@@ -155,14 +295,28 @@ static hipError_t lap7_dispatch(const Lap7ChainLaunch &L, hipStream_t s) {
     case 4: B7(TX_, TY_, 4); break;   \
     default: B7(TX_, TY_, 2); break;  \
     }
+#define R7(TX_, TY_, PP) hipLaunchKernelGGL((lap7_reg_kernel<T, TX_, TY_, PP>), grid, dim3(TX_ * TY_), 0, s, a)
+#define R7P(TX_, TY_)                 \
+    switch (P) {                      \
+    case 1: R7(TX_, TY_, 1); break;   \
+    case 4: R7(TX_, TY_, 4); break;   \
+    default: R7(TX_, TY_, 2); break;  \
+    }
     switch (L.cfg.variant) {
     case 1: B7P(32, 8); break;
     case 2: B7P(64, 8); break;
     case 3: B7P(128, 2); break;
     case 4: B7P(32, 4); break;
     case 5: B7P(64, 16); break;
+    case 10: R7P(64, 16); break;
+    case 11: R7P(64, 8); break;
+    case 12: R7P(32, 8); break;
+    case 13: R7P(128, 8); break;
+    case 14: R7P(32, 16); break;
     default: B7P(64, 4); break;
     }
+#undef R7P
+#undef R7
 #undef B7P
 #undef B7
     return hipGetLastError();

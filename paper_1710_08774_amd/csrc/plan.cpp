@@ -820,7 +820,9 @@ extern "C" int hfav_plan_batch(hfav_chain *chain, const hfav_plan_opts *opts, in
         hfav_config cg = hfav_default_config(HFAV_FAMILY_EULER_Y, chain->dtype, gd);
         if (o.config_source == HFAV_CONFIG_FORCED) cg = o.forced;
         else if (o.config_source == HFAV_CONFIG_TUNED) hfav_tuned_config(HFAV_FAMILY_EULER_Y, chain->dtype, gd, &cg);
-        int seg = cg.seg > 0 ? cg.seg : 16;
+        // the batched y sweep keeps its windows in registers: a strip
+        // configuration (variant 3) carries no segment length for it
+        int seg = cg.seg > 0 && cg.variant != 3 ? cg.seg : 16;
         p.bseg[g] = seg > 255 ? 255 : seg;
     }
     p.btotal = off;

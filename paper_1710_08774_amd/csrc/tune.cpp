@@ -20,32 +20,46 @@ std::vector<Entry> g_table;
 
 hfav_config hfav_default_config(int family, int dtype, const int dims[3]) {
     hfav_config c{256, 1, 0, 0, 0};
-    // measured on MI355X at the workload sizes (64x2048x2048 hdiff, 2048^2
-    // hydro, 512^3 biharmonic); the autotuner refines these per size
+    // measured on MI355X (the autotuner's database at the workload sizes and
+    // at smaller shapes); the tuning table refines these per shape
+    const double cells = (double)dims[0] * dims[1] * (dims[2] > 0 ? dims[2] : 1);
     switch (family) {
-    case HFAV_FAMILY_HDIFF: c.block = 256; c.seg = 128; c.variant = 0; break;
-    case HFAV_FAMILY_EULER_X:   // one workgroup per row: wide rows take 4 waves
-        c.block = dims[0] >= 1024 ? 256 : (dims[0] >= 256 ? 128 : 64);
+    case HFAV_FAMILY_HDIFF: {
+        if (dtype == HFAV_F64) {    // 2 rows in flight, one tile range per XCD
+            c.block = 256; c.seg = 64; c.variant = 2; c.xcd = -1;
+        } else {
+            c.block = 256; c.seg = 128; c.variant = 0; c.xcd = 0;
+        }
+        // small grids: shorter segments, then narrower tiles, until about
+        // 2048 workgroups are in flight
+        auto wgs = [&](const hfav_config &k) {
+            return (double)((dims[0] + k.block - 1) / k.block) * ((dims[1] + k.seg - 1) / k.seg) *
+                   (dims[2] > 0 ? dims[2] : 1);
+        };
+        while (wgs(c) < 2048 && c.seg > 32) c.seg /= 2;
+        while (wgs(c) < 2048 && c.block > 128) c.block /= 2;
+        break;
+    }
+    case HFAV_FAMILY_EULER_X:   // one workgroup per row, up to 4 waves
+        c.block = dims[0] >= 256 ? 256 : (dims[0] >= 128 ? 128 : 64);
         c.variant = 1;
         break;
-    case HFAV_FAMILY_EULER_Y:
-        if (dims[0] >= 1024 && dims[1] >= 1024) {
-            // LDS-ring strips of 64 columns x 8 rows per chunk; segments as
-            // long as keeps about 512 eight-wave workgroups in flight
-            const double cells = (double)dims[0] * dims[1];
-            int seg = 16;
-            while (seg < 128 && cells / (64.0 * 2 * seg) >= 512) seg *= 2;
-            c.block = 512;
-            c.seg = seg;
-            c.variant = 3;
-        } else {                // one lane per column, windows in registers
-            c.block = 64;
-            c.seg = 16;
-            c.variant = 1;
-        }
+    case HFAV_FAMILY_EULER_Y: {
+        // LDS-ring strips of 64 columns x 8 rows per chunk; segments as long
+        // as keeps about 512 eight-wave workgroups in flight
+        int seg = 32;
+        while (seg < 128 && cells / (64.0 * 2 * seg) >= 512) seg *= 2;
+        c.block = 512;
+        c.seg = seg;
+        c.variant = 3;
         break;
+    }
     case HFAV_FAMILY_LAP7_CHAIN:
-        c.block = 1024; c.seg = 64; c.variant = 5; c.tile_y = dtype == HFAV_F64 ? 2 : 4;
+        if (cells >= 64.0 * 1024 * 1024) {      // 64 x 16 tiles, 4 planes in flight
+            c.block = 1024; c.seg = 128; c.variant = 5; c.tile_y = 4;
+        } else {                                // 32 x 8 tiles, 2 planes in flight
+            c.block = 256; c.seg = 64; c.variant = 1; c.tile_y = 2;
+        }
         break;
     default: break;
     }

@@ -1,6 +1,11 @@
-"""Autotuner and learned cost model for fused linear star chains.
+"""Autotuners, the tuning database, and the learned cost model.
 
-* `autotune`  times every feasible configuration of a chain (exhaustive
+* `tune_family` times every configuration of a fixed kernel family (hdiff,
+  the 7-point chain, the two hydro sweeps) at one shape; `build_db` runs it
+  over (family, dtype, shape) buckets and writes the tuning database (JSON),
+  `load_db` installs a database into the planner's tuning table, which
+  `hfav_plan(..., HFAV_CONFIG_TUNED)` reads (nearest shape bucket);
+* `autotune`  times every feasible configuration of a star chain (exhaustive
   search, the judge of the model's regret);
 * `collect`   builds a training set of (features, log time per cell) from the
   autotuner's timings on seeded random chains;
@@ -11,7 +16,7 @@
   gain over the planner's default configuration.
 
 Timing uses HIP events on the stream the chain runs on.
-Command line: python -m paper_1710_08774_amd.tune study --help
+Command line: python -m paper_1710_08774_amd.tune {db,study} --help
 """
 from __future__ import annotations
 
@@ -34,6 +39,153 @@ HIDDEN = 64
 
 def chain_dims(ch):
     return tuple(ch["dims"]) if ch["ndim"] == 3 else tuple(ch["dims"][:2])
+
+
+# ------------------------------------------------------------------ families
+FAMILY_ID = {"hdiff": 1, "euler_x": 2, "euler_y": 3, "lap7_chain": 4}
+DTYPE_NAME = {H.F64: "f64", H.F32: "f32"}
+
+
+def family_space(family):
+    """Configurations (block, tile_y, seg, variant, xcd) searched per family."""
+    out = []
+    if family == "hdiff":
+        for blk in (128, 256, 512):
+            for seg in (32, 64, 128):
+                for var in (0, 1, 2, 4, 8, 10):
+                    for xcd in (0, -1):
+                        out.append((blk, 1, seg, var, xcd))
+    elif family == "lap7_chain":
+        for var in (1, 2, 5, 10, 13):
+            for seg in (64, 128):
+                for depth in (2, 4):
+                    for xcd in (0, 8):
+                        out.append((1024, depth, seg, var, xcd))
+    elif family == "euler_x":
+        for blk in (64, 128, 256):
+            for var in (0, 1, 3):
+                out.append((blk, 1, 0, var, 0))
+    elif family == "euler_y":
+        for blk in (64, 128, 256):
+            for seg in (8, 16, 32):
+                for var in (0, 1):
+                    out.append((blk, 1, seg, var, 0))
+        for blk in (256, 512):
+            for seg in (32, 64, 128):
+                out.append((blk, 1, seg, 3, 0))
+    else:
+        raise ValueError(f"no search space for family {family!r}")
+    return out
+
+
+def _event_ms(fn, reps):
+    import torch
+    fn()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def tune_family(family, dims, dtype=H.F64, reps=5, space=None):
+    """Time every configuration of `family` at `dims` (x, y[, z]).
+
+    Returns (results sorted by time as [(ms, config)], default_ms)."""
+    import torch
+    space = family_space(family) if space is None else space
+    tdt = torch.float64 if dtype == H.F64 else torch.float32
+    res = []
+    if family in ("hdiff", "lap7_chain"):
+        nx, ny, nz = dims
+        spec = H.hdiff_spec(dtype=dtype) if family == "hdiff" else H.biharm_spec(dtype=dtype)
+        g = torch.Generator(device="cuda").manual_seed(0)
+        u = torch.rand((nz, ny, nx), dtype=tdt, device="cuda", generator=g)
+        o = torch.empty_like(u)
+        c = H.Chain(spec)
+        for cfg in space:
+            c.plan((nx, ny, nz), mode=H.MODE_FUSED, config_source=H.CONFIG_FORCED, forced=cfg)
+            res.append((_event_ms(lambda: c.execute([u], [o]), reps), tuple(cfg)))
+        c.plan((nx, ny, nz), mode=H.MODE_FUSED)
+        default_ms = _event_ms(lambda: c.execute([u], [o]), reps)
+    elif family in ("euler_x", "euler_y"):
+        from .euler import EulerStepper
+        nx, ny = dims[0], dims[1]
+        U = inputs.euler_ic(nx, ny)
+        x = family == "euler_x"
+        for cfg in space:
+            st = EulerStepper(nx, ny, dtype=tdt, **({"forced_x": cfg} if x else {"forced_y": cfg}))
+            st.load(U)
+            res.append((_event_ms(st.sweep_x if x else st.sweep_y, reps), tuple(cfg)))
+        st = EulerStepper(nx, ny, dtype=tdt)
+        st.load(U)
+        default_ms = _event_ms(st.sweep_x if x else st.sweep_y, reps)
+    else:
+        raise ValueError(f"no autotuner for family {family!r}")
+    res.sort(key=lambda r: r[0])
+    return res, default_ms
+
+
+# default buckets: the workload sizes and one smaller shape per family
+DB_BUCKETS = [
+    ("hdiff", H.F64, (2048, 2048, 64)), ("hdiff", H.F64, (256, 256, 8)), ("hdiff", H.F32, (2048, 2048, 64)),
+    ("lap7_chain", H.F64, (512, 512, 512)), ("lap7_chain", H.F32, (512, 512, 512)),
+    ("lap7_chain", H.F64, (128, 128, 128)),
+    ("euler_x", H.F64, (2048, 2048, 1)), ("euler_x", H.F64, (512, 512, 1)),
+    ("euler_y", H.F64, (2048, 2048, 1)), ("euler_y", H.F64, (512, 512, 1)),
+    ("euler_y", H.F64, (128, 128, 1)),
+]
+
+
+def build_db(buckets=None, reps=5, log=None):
+    """Autotune every (family, dtype, shape) bucket; returns the database."""
+    entries = []
+    for family, dtype, dims in (DB_BUCKETS if buckets is None else buckets):
+        t0 = time.time()
+        res, default_ms = tune_family(family, dims, dtype, reps)
+        best_ms, best = res[0]
+        entries.append({"family": family, "family_id": FAMILY_ID[family], "dtype": DTYPE_NAME[dtype],
+                        "dims": list(dims), "config": list(best), "ms": best_ms, "default_ms": default_ms,
+                        "n_configs": len(res), "search_s": time.time() - t0})
+        if log:
+            log(f"db: {family} {DTYPE_NAME[dtype]} {dims}: best {best} {best_ms:.4f} ms "
+                f"(default {default_ms:.4f} ms, {len(res)} configs)")
+    return {"version": 1, "entries": entries}
+
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_DB = os.path.join(HERE, "tuning_db.json")            # MI355X autotuner results
+DEFAULT_COSTMODEL = os.path.join(HERE, "costmodel_mi355x.json")  # MI355X-trained network
+
+
+def load_default_db():
+    """Install the shipped MI355X tuning database; returns its entry count."""
+    return load_db(DEFAULT_DB)
+
+
+def load_costmodel(path=DEFAULT_COSTMODEL):
+    """Install a trained cost-model network (JSON with params, mean, std,
+    hidden) so that hfav_plan(..., HFAV_CONFIG_MODEL) uses it."""
+    with open(path) as f:
+        m = json.load(f)
+    H.costmodel_set(m["params"], int(m["hidden"]), m["mean"], m["std"])
+    return m
+
+
+def load_db(db):
+    """Install a tuning database (dict or JSON path) into the planner's table."""
+    if isinstance(db, str):
+        with open(db) as f:
+            db = json.load(f)
+    H.tuning_clear()
+    for e in db["entries"]:
+        dtype = H.F64 if e["dtype"] == "f64" else H.F32
+        dims = list(e["dims"]) + [1] * (3 - len(e["dims"]))
+        H.tuning_add(int(e["family_id"]), dtype, dims, tuple(e["config"]))
+    return H.tuning_size()
 
 
 def cfg_key(cfg):
@@ -242,6 +394,9 @@ def study(n_train, n_test, reps=3, iters=3000, max_cells=None, log=print):
 def main(argv=None):
     ap = argparse.ArgumentParser(prog="python -m paper_1710_08774_amd.tune")
     sub = ap.add_subparsers(dest="cmd", required=True)
+    dbp = sub.add_parser("db", help="autotune the kernel families and write the tuning database")
+    dbp.add_argument("--reps", type=int, default=5)
+    dbp.add_argument("--out", default="gpurun_out/tuning_db.json")
     st = sub.add_parser("study", help="train on seeded chains, report regret on held-out chains")
     st.add_argument("--train-chains", type=int, default=60)
     st.add_argument("--test-chains", type=int, default=200)
@@ -250,6 +405,13 @@ def main(argv=None):
     st.add_argument("--max-cells", type=int, default=0, help="cap grid cells per chain (0: none)")
     st.add_argument("--out", default="gpurun_out/costmodel_study.json")
     a = ap.parse_args(argv)
+    if a.cmd == "db":
+        db = build_db(reps=a.reps, log=lambda m: print(m, flush=True))
+        os.makedirs(os.path.dirname(a.out) or ".", exist_ok=True)
+        with open(a.out, "w") as f:
+            json.dump(db, f, indent=1)
+        print(json.dumps({"entries": len(db["entries"]), "out": a.out}), flush=True)
+        return 0
     if a.cmd == "study":
         res = study(a.train_chains, a.test_chains, a.reps, a.iters, a.max_cells or None,
                     log=lambda m: print(m, flush=True))

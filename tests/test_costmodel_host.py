@@ -60,3 +60,30 @@ def test_installed_model_matches_oracle_forward():
     finally:
         H.costmodel_set(None, 0, None, None)
     assert c.plan(dims, mode=H.MODE_FUSED, config_source=H.CONFIG_MODEL).config_source == H.CONFIG_DEFAULT
+
+
+def test_shipped_tuning_db_and_costmodel_load():
+    """The MI355X tuning database and trained network shipped with the
+    package install and drive CONFIG_TUNED / CONFIG_MODEL plans."""
+    from paper_1710_08774_amd import tune
+    try:
+        n = tune.load_default_db()
+        assert n >= 8
+        c = H.Chain(H.hdiff_spec())
+        assert c.plan((2048, 2048, 64), config_source=H.CONFIG_TUNED).config_source == H.CONFIG_TUNED
+        m = tune.load_costmodel()
+        assert m["hidden"] == 64 and len(m["params"]) == H.mlp_nparams(len(m["mean"]), 64)
+        rng = inputs.rng_for(inputs.BASE_SEED + 123)
+        ch = inputs.random_chain(rng)
+        sc = H.Chain(H.star_chain_spec(ch, inputs.star_offsets))
+        dims = tuple(ch["dims"]) if ch["ndim"] == 3 else tuple(ch["dims"][:2])
+        info = sc.plan(dims, mode=H.MODE_FUSED, config_source=H.CONFIG_MODEL)
+        assert info.config_source == H.CONFIG_MODEL
+        cands = [tuple(x) for x in sc.candidates(dims)]
+        pred = [sc.predict(dims, k) for k in cands]
+        assert all(np.isfinite(pred))
+        best = cands[int(np.argmin(pred))]
+        assert (info.config.tile_y, info.config.seg, info.config.variant) == (best[1], best[2], best[3])
+    finally:
+        H.tuning_clear()
+        H.costmodel_set(None, 0, None, None)

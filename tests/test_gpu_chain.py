@@ -138,3 +138,44 @@ def test_cost_model_gains_over_default():
     print("cost model (reduced study):", s, flush=True)
     assert s["gain_over_default_geomean"] > 1.0
     assert s["regret_mean"] < s["default_regret_mean"]
+
+
+def test_family_autotuner_database_and_tuned_parity(tmp_path):
+    """The family autotuner times its space, the database it writes steers
+    hfav_plan(CONFIG_TUNED), and the tuned kernels match the oracle."""
+    import json
+    from gpu_util import field_errs
+    from paper_1710_08774_amd.euler import EulerStepper
+    space = [(64, 1, 8, 0, 0), (128, 1, 16, 8, -1), (256, 1, 32, 2, 0)]
+    res, default_ms = tune.tune_family("hdiff", (200, 70, 2), H.F64, reps=2, space=space)
+    assert len(res) == 3 and default_ms > 0
+    assert all(ms > 0 for ms, _ in res) and res[0][0] <= res[-1][0]
+    db = tune.build_db([("euler_y", H.F64, (96, 80, 1))], reps=1)
+    db["entries"].append({"family": "hdiff", "family_id": 1, "dtype": "f64", "dims": [200, 70, 2],
+                          "config": list(res[0][1])})
+    path = tmp_path / "db.json"
+    path.write_text(json.dumps(db))
+    assert tune.load_db(str(path)) == 2
+    try:
+        a = inputs.hdiff_input(2, 70, 200, seed=21)
+        c = H.Chain(H.hdiff_spec())
+        info = c.plan((200, 70, 2), config_source=H.CONFIG_TUNED)
+        assert info.config_source == H.CONFIG_TUNED
+        assert (info.config.block, info.config.seg, info.config.variant, info.config.xcd) == \
+            (res[0][1][0], res[0][1][2], res[0][1][3], res[0][1][4])
+        u = torch.tensor(a, device="cuda")
+        out = torch.empty_like(u)
+        c.execute([u], [out])
+        assert np.array_equal(host(out), oracle.hdiff(a))
+        # the hydro stepper with the tuned y configuration
+        U = inputs.euler_ic(96, 80, seed=22)
+        st = EulerStepper(96, 80, config_source=H.CONFIG_TUNED)
+        assert st.iy.config_source == H.CONFIG_TUNED
+        assert [st.iy.config.block, st.iy.config.tile_y, st.iy.config.seg, st.iy.config.variant,
+                st.iy.config.xcd] == db["entries"][0]["config"]
+        st.load(U)
+        st.step(5)
+        ref, _ = oracle.euler_run(U, 5)
+        assert max(field_errs(host(st.state()), ref)) <= 1e-12
+    finally:
+        H.tuning_clear()

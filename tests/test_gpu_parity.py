@@ -43,15 +43,31 @@ def test_hdiff_parity(shape, mode):
 
 
 @pytest.mark.parametrize("block,seg", [(64, 1), (64, 7), (128, 16), (512, 64)])
-def test_hdiff_tile_configs(block, seg):
+@pytest.mark.parametrize("variant", [0, 1, 4, 8, 9, 12])
+def test_hdiff_tile_configs(block, seg, variant):
+    # variants 8-12: neighbours along the lane axis by DPP lane shifts
     a = inputs.hdiff_input(2, 70, 200, seed=3)
     ref = oracle.hdiff(a)
     c = H.Chain(H.hdiff_spec())
-    c.plan((200, 70, 2), mode=H.MODE_FUSED, config_source=H.CONFIG_FORCED, forced=(block, 1, seg, 0))
+    c.plan((200, 70, 2), mode=H.MODE_FUSED, config_source=H.CONFIG_FORCED, forced=(block, 1, seg, variant))
     u = dev(a)
     out = torch.empty_like(u)
     c.execute([u], [out])
     assert np.array_equal(host(out), ref)
+
+
+@pytest.mark.parametrize("shape", [(1, 8, 8), (3, 13, 7), (2, 65, 3), (2, 100, 300)])
+def test_hdiff_dpp_parity_ragged(shape):
+    nk, nj, ni = shape
+    a = inputs.hdiff_input(nk, nj, ni, seed=sum(shape) + 11)
+    ref = oracle.hdiff(a)
+    for block in (64, 256):
+        c = H.Chain(H.hdiff_spec())
+        c.plan((ni, nj, nk), mode=H.MODE_FUSED, config_source=H.CONFIG_FORCED, forced=(block, 1, 5, 8))
+        u = dev(a)
+        out = torch.empty_like(u)
+        c.execute([u], [out])
+        assert np.array_equal(host(out), ref), block
 
 
 def test_hdiff_f32_error_bound():
@@ -276,13 +292,16 @@ def test_biharm_parity(shape, mode):
     assert np.array_equal(got, ref)
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
-def test_biharm_tile_variants(variant):
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 10, 11, 12, 13, 14])
+@pytest.mark.parametrize("depth,seg", [(1, 5), (4, 6), (2, 17)])
+def test_biharm_tile_variants(variant, depth, seg):
+    # ragged tiles in x and y, segments that do not divide nz, every
+    # prefetch depth; variants 10-14 keep the z windows in registers
     shape = (17, 40, 150)
     u = inputs.biharm_input(shape=shape, seed=5)
     ref = oracle.biharm(u)
     c = H.Chain(H.biharm_spec())
-    c.plan((150, 40, 17), mode=H.MODE_FUSED, config_source=H.CONFIG_FORCED, forced=(256, 1, 5, variant))
+    c.plan((150, 40, 17), mode=H.MODE_FUSED, config_source=H.CONFIG_FORCED, forced=(256, depth, seg, variant))
     d = dev(u)
     o = torch.empty_like(d)
     c.execute([d], [o])

@@ -253,6 +253,47 @@ def test_tuning_table_nearest_entry():
     assert c.plan((300, 200, 4), config_source=H.CONFIG_TUNED).config_source == H.CONFIG_DEFAULT
 
 
+def test_tuning_db_load_drives_tuned_plans(tmp_path):
+    import json
+    from paper_1710_08774_amd import tune
+    db = {"version": 1, "entries": [
+        {"family": "hdiff", "family_id": 1, "dtype": "f64", "dims": [2048, 2048, 64],
+         "config": [512, 1, 64, 2, -1]},
+        {"family": "euler_y", "family_id": 3, "dtype": "f64", "dims": [512, 512, 1],
+         "config": [128, 1, 32, 0, 0]},
+        {"family": "lap7_chain", "family_id": 4, "dtype": "f32", "dims": [512, 512, 512],
+         "config": [1024, 4, 128, 13, 8]}]}
+    path = tmp_path / "db.json"
+    path.write_text(json.dumps(db))
+    assert tune.load_db(str(path)) == 3
+    c = H.Chain(H.hdiff_spec())
+    i = c.plan((2000, 1900, 60), config_source=H.CONFIG_TUNED)
+    assert (i.config.block, i.config.seg, i.config.variant, i.config.xcd) == (512, 64, 2, -1)
+    assert i.config_source == H.CONFIG_TUNED
+    y = H.Chain(H.euler_sweep_spec(1))
+    i = y.plan((500, 520), config_source=H.CONFIG_TUNED)
+    assert (i.config.block, i.config.seg, i.config.variant) == (128, 32, 0)
+    b = H.Chain(H.biharm_spec(dtype=H.F32))
+    i = b.plan((500, 500, 500), config_source=H.CONFIG_TUNED)
+    assert (i.config.tile_y, i.config.variant, i.config.xcd) == (4, 13, 8)
+    # an entry of another dtype is not used
+    b64 = H.Chain(H.biharm_spec())
+    assert b64.plan((500, 500, 500), config_source=H.CONFIG_TUNED).config_source == H.CONFIG_DEFAULT
+    H.tuning_clear()
+
+
+def test_family_search_spaces_plan():
+    from paper_1710_08774_amd import tune
+    for fam, spec, dims in (("hdiff", H.hdiff_spec(), (64, 48, 2)), ("lap7_chain", H.biharm_spec(), (40, 36, 20)),
+                            ("euler_x", H.euler_sweep_spec(0), (64, 48)), ("euler_y", H.euler_sweep_spec(1), (64, 48))):
+        c = H.Chain(spec)
+        space = tune.family_space(fam)
+        assert len(space) == len(set(space)) >= 9
+        for cfg in space:
+            info = c.plan(dims, mode=H.MODE_FUSED, config_source=H.CONFIG_FORCED, forced=cfg)
+            assert info.fused and H.FAMILY[info.family] == fam
+
+
 def test_random_star_chain_plans():
     rng = inputs.rng_for(5)
     for _ in range(10):
