@@ -4,7 +4,7 @@ import pytest
 import torch
 
 import oracle
-from gpu_util import field_errs, host
+from gpu_util import host, hydro_errs
 from paper_1710_08774_amd import hfav as H
 from paper_1710_08774_amd import inputs
 from paper_1710_08774_amd.euler import EulerBatchStepper, EulerStepper
@@ -39,7 +39,7 @@ def test_batch_per_grid_dt_and_oracle_parity():
     torch.cuda.synchronize()
     for g, U in enumerate(states):
         ref, _ = oracle.euler_run(U, 10)
-        assert max(field_errs(host(bt.grid(g)), ref)) <= 1e-12, g
+        assert max(hydro_errs(host(bt.grid(g)), ref)) <= 1e-12, g
     # every grid advanced with its own time step
     assert len(set(np.round(host(bt.smax[0]), 12))) > 1
 
@@ -76,7 +76,7 @@ def test_batch_config_workload_sizes_two_steps():
     rng = np.random.default_rng(0)
     for g in rng.choice(512, 6, replace=False):
         ref, _ = oracle.euler_run(states[g], 2)
-        assert max(field_errs(host(bt.grid(g)), ref)) <= 1e-12, g
+        assert max(hydro_errs(host(bt.grid(g)), ref)) <= 1e-12, g
 
 
 def test_batch_errors():

@@ -144,7 +144,7 @@ def test_family_autotuner_database_and_tuned_parity(tmp_path):
     """The family autotuner times its space, the database it writes steers
     hfav_plan(CONFIG_TUNED), and the tuned kernels match the oracle."""
     import json
-    from gpu_util import field_errs
+    from gpu_util import hydro_errs
     from paper_1710_08774_amd.euler import EulerStepper
     space = [(64, 1, 8, 0, 0), (128, 1, 16, 8, -1), (256, 1, 32, 2, 0)]
     res, default_ms = tune.tune_family("hdiff", (200, 70, 2), H.F64, reps=2, space=space)
@@ -176,6 +176,6 @@ def test_family_autotuner_database_and_tuned_parity(tmp_path):
         st.load(U)
         st.step(5)
         ref, _ = oracle.euler_run(U, 5)
-        assert max(field_errs(host(st.state()), ref)) <= 1e-12
+        assert max(hydro_errs(host(st.state()), ref)) <= 1e-12
     finally:
         H.tuning_clear()

@@ -11,7 +11,7 @@ import pytest
 import torch
 
 import oracle
-from gpu_util import dev, field_errs, host, relerr
+from gpu_util import dev, host, hydro_errs, relerr
 from paper_1710_08774_amd import hfav as H
 from paper_1710_08774_amd import inputs
 from paper_1710_08774_amd.euler import EulerStepper
@@ -105,7 +105,7 @@ def test_euler_sweep_parity(shape, direction, mode):
     dt = 0.5 / oracle.euler_smax(U)
     ref = oracle.euler_sweep(U, direction, dt)
     got = _sweep_gpu(U, direction, dt, mode)
-    assert max(field_errs(got, ref)) <= TOL64
+    assert max(hydro_errs(got, ref)) <= TOL64
 
 
 @pytest.mark.parametrize("direction,cfg", [(0, (64, 1, 0, 0)), (0, (256, 1, 0, 0)),
@@ -117,7 +117,7 @@ def test_euler_sweep_tile_configs(direction, cfg):
     dt = 0.5 / oracle.euler_smax(U)
     ref = oracle.euler_sweep(U, direction, dt)
     got = _sweep_gpu(U, direction, dt, H.MODE_FUSED, forced=cfg)
-    assert max(field_errs(got, ref)) <= TOL64
+    assert max(hydro_errs(got, ref)) <= TOL64
 
 
 @pytest.mark.parametrize("direction", [0, 1])
@@ -139,7 +139,7 @@ def test_euler_transmissive_sweep(direction, strip):
             V = oracle.euler_sweep(V, direction, dt, bc=oracle.BC_TRANSMISSIVE)
             forced = ((256, 1, 16, 3) if strip else None) if mode == H.MODE_FUSED else None
             W = _sweep_gpu(W, direction, dt, mode, bc=H.BC_TRANSMISSIVE, forced=forced)
-        assert max(field_errs(W, V)) <= TOL64
+        assert max(hydro_errs(W, V)) <= TOL64
 
 
 def test_euler_constant_state_bitwise():
@@ -159,7 +159,7 @@ def test_euler_run_parity(mode):
     st.load(U)
     st.step(steps)
     got = host(st.state())
-    assert max(field_errs(got, ref)) <= TOL64
+    assert max(hydro_errs(got, ref)) <= TOL64
 
 
 @pytest.mark.parametrize("shape", [(96, 80), (200, 33)])
@@ -171,7 +171,7 @@ def test_euler_run_parity_strip_kernels(shape):
     st = EulerStepper(nx, ny, forced_x=(256, 1, 0, 3), forced_y=(256, 1, 16, 3))
     st.load(U)
     st.step(30)
-    assert max(field_errs(host(st.state()), ref)) <= TOL64
+    assert max(hydro_errs(host(st.state()), ref)) <= TOL64
 
 
 def test_euler_config_workload_two_steps_full_size():
@@ -183,7 +183,7 @@ def test_euler_config_workload_two_steps_full_size():
     st.load(U)
     st.step(2)
     got = host(st.state())
-    assert max(field_errs(got, ref)) <= TOL64
+    assert max(hydro_errs(got, ref)) <= TOL64
 
 
 def test_euler_hundred_steps_parity():
@@ -193,7 +193,7 @@ def test_euler_hundred_steps_parity():
     st = EulerStepper(nx, ny)
     st.load(U)
     st.step(100)
-    assert max(field_errs(host(st.state()), ref)) <= TOL64
+    assert max(hydro_errs(host(st.state()), ref)) <= TOL64
 
 
 def test_fused_matches_unfused_stepper():
@@ -208,7 +208,7 @@ def test_fused_matches_unfused_stepper():
     # identical rule bodies; the two paths differ only in where the compiler
     # forms fused multiply-adds (about one rounding per rule evaluation),
     # which ten steps grow to the 1e-14 level
-    assert max(field_errs(host(a.state()), host(b.state()))) <= 1e-13
+    assert max(hydro_errs(host(a.state()), host(b.state()))) <= 1e-13
 
 
 def test_smax_reduction_matches_oracle():
