@@ -36,8 +36,8 @@ hfav_config hfav_default_config(int family, int dtype, const int dims[3]) {
             return (double)((dims[0] + k.block - 1) / k.block) * ((dims[1] + k.seg - 1) / k.seg) *
                    (dims[2] > 0 ? dims[2] : 1);
         };
-        while (wgs(c) < 2048 && c.seg > 32) c.seg /= 2;
-        while (wgs(c) < 2048 && c.block > 128) c.block /= 2;
+        while (wgs(c) < 2048 && c.seg > 16) c.seg /= 2;
+        while (wgs(c) < 2048 && c.block > 64) c.block /= 2;
         break;
     }
     case HFAV_FAMILY_EULER_X:   // one workgroup per row, up to 4 waves

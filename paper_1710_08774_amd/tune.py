@@ -50,8 +50,8 @@ def family_space(family):
     """Configurations (block, tile_y, seg, variant, xcd) searched per family."""
     out = []
     if family == "hdiff":
-        for blk in (128, 256, 512):
-            for seg in (32, 64, 128):
+        for blk in (64, 128, 256, 512):
+            for seg in (16, 32, 64, 128):
                 for var in (0, 1, 2, 4, 8, 10):
                     for xcd in (0, -1):
                         out.append((blk, 1, seg, var, xcd))
