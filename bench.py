@@ -207,15 +207,25 @@ def batched_grids(steps=50, loop_steps=4):
     own dt: the batched persistent sweeps with `steps` steps captured in one
     HIP graph, against a loop of per-grid fused launches."""
     import torch
-    from paper_1710_08774_amd import inputs
+    from paper_1710_08774_amd import hfav as H
+    from paper_1710_08774_amd import inputs, tune
     from paper_1710_08774_amd.euler import EulerBatchStepper, EulerStepper
 
+    # per-size-bucket segment lengths of the batched y sweep from the
+    # autotuner's database
+    tune.load_default_db()
     sizes = inputs.batch_sizes(512)
     states = inputs.batch_ic(sizes=sizes)
     cells = sum(nx * ny for nx, ny in sizes)
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    bt = EulerBatchStepper(sizes)
+    bt = EulerBatchStepper(sizes, config_source=H.CONFIG_TUNED)
+    segs = {}
+    for (nx, ny), sg in zip(sizes, bt.y_segments()):
+        b = "64-255" if max(nx, ny) < 256 else ("256-511" if max(nx, ny) < 512 else "512-1024")
+        segs.setdefault(b, set()).add(int(sg))
+    segs = {b: sorted(v) for b, v in sorted(segs.items())}
+    H.tuning_clear()
     bt.load(states)
     bt.step(2)
     bt.capture(steps)
@@ -249,7 +259,8 @@ def batched_grids(steps=50, loop_steps=4):
             "cell_updates_per_s": cells / (ms_batch * 1e-3), "compulsory_GBs": 128 * cells / (ms_batch * 1e-3) / 1e9,
             "loop_of_per_grid_launches": {"ms_per_step": ms_loop, "cell_updates_per_s": cells / (ms_loop * 1e-3),
                                           "steps": loop_steps},
-            "batched_over_loop": ms_loop / ms_batch, "state_finite": finite}
+            "batched_over_loop": ms_loop / ms_batch, "state_finite": finite,
+            "y_segments_by_bucket": segs}
 
 
 def cpu_baseline(U0, budget_s=12.0):

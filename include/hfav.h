@@ -134,7 +134,10 @@ typedef enum {
     HFAV_FAMILY_EULER_Y = 3,
     HFAV_FAMILY_LAP7_CHAIN = 4,
     HFAV_FAMILY_STAR_CHAIN = 5,
-    HFAV_FAMILY_SMAX = 6
+    HFAV_FAMILY_SMAX = 6,
+    HFAV_FAMILY_EULER_Y_BATCH = 7  /* tuning-table key only: the segment length
+                                     (config.seg) of one grid's batched y
+                                     sweep, by that grid's (nx, ny) */
 } hfav_family;
 
 typedef enum {

@@ -817,15 +817,25 @@ extern "C" int hfav_plan_batch(hfav_chain *chain, const hfav_plan_opts *opts, in
         p.boff[g] = off;
         off += (int64_t)p.bnx[g] * p.bny[g];
         const int gd[3] = {p.bnx[g], p.bny[g], 1};
-        hfav_config cg = hfav_default_config(HFAV_FAMILY_EULER_Y, chain->dtype, gd);
+        // the batched y sweep keeps its windows in registers; its segment
+        // length per grid comes from the batch entries of the tuning table
+        // (nearest size bucket), else 16
+        hfav_config cg{64, 1, 16, 1, 0};
         if (o.config_source == HFAV_CONFIG_FORCED) cg = o.forced;
-        else if (o.config_source == HFAV_CONFIG_TUNED) hfav_tuned_config(HFAV_FAMILY_EULER_Y, chain->dtype, gd, &cg);
-        // the batched y sweep keeps its windows in registers: a strip
-        // configuration (variant 3) carries no segment length for it
+        else if (o.config_source == HFAV_CONFIG_TUNED)
+            hfav_tuned_config(HFAV_FAMILY_EULER_Y_BATCH, chain->dtype, gd, &cg);
         int seg = cg.seg > 0 && cg.variant != 3 ? cg.seg : 16;
         p.bseg[g] = seg > 255 ? 255 : seg;
     }
     p.btotal = off;
+    // record the batch in the plan's JSON: grid count and y segment lengths
+    if (!p.json.empty() && p.json.back() == '}') {
+        std::ostringstream bj;
+        bj << ",\"batch\":{\"grids\":" << n_grids << ",\"y_seg\":[";
+        for (int g = 0; g < n_grids; ++g) bj << (g ? "," : "") << (int)p.bseg[g];
+        bj << "]}";
+        p.json.insert(p.json.size() - 1, bj.str());
+    }
     return HFAV_OK;
 }
 

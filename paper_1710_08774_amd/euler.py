@@ -103,6 +103,10 @@ class EulerBatchStepper:
     def cells(self):
         return sum(a * b for a, b in self.sizes)
 
+    def y_segments(self):
+        """Segment length of every grid's batched y sweep (from the plan)."""
+        return self.cy.plan_json()["batch"]["y_seg"]
+
     def load(self, states):
         host = torch.empty((4, self.total), dtype=self.dtype)
         for g, U in enumerate(states):

@@ -35,7 +35,8 @@ BC_PERIODIC, BC_TRANSMISSIVE = 0, 1
 MODE_AUTO, MODE_FUSED, MODE_UNFUSED = 0, 1, 2
 PREC_NATIVE, PREC_F32_F64ACC = 0, 1
 CONFIG_DEFAULT, CONFIG_TUNED, CONFIG_MODEL, CONFIG_FORCED = 0, 1, 2, 3
-FAMILY = {0: "none", 1: "hdiff", 2: "euler_x", 3: "euler_y", 4: "lap7_chain", 5: "star_chain", 6: "smax"}
+FAMILY = {0: "none", 1: "hdiff", 2: "euler_x", 3: "euler_y", 4: "lap7_chain", 5: "star_chain", 6: "smax",
+          7: "euler_y_batch"}
 STORAGE = {0: "full", 1: "register", 2: "inner", 3: "outer", 4: "scalar"}
 MAX_RULES = 64
 COST_FEATURES = 24

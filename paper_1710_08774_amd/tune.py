@@ -42,7 +42,7 @@ def chain_dims(ch):
 
 
 # ------------------------------------------------------------------ families
-FAMILY_ID = {"hdiff": 1, "euler_x": 2, "euler_y": 3, "lap7_chain": 4}
+FAMILY_ID = {"hdiff": 1, "euler_x": 2, "euler_y": 3, "lap7_chain": 4, "euler_y_batch": 7}
 DTYPE_NAME = {H.F64: "f64", H.F32: "f32"}
 
 
@@ -138,10 +138,56 @@ DB_BUCKETS = [
     ("euler_y", H.F64, (2048, 2048, 1)), ("euler_y", H.F64, (512, 512, 1)),
     ("euler_y", H.F64, (128, 128, 1)),
 ]
+# size buckets of the batched y sweep (centres, log2-nearest assignment)
+BATCH_BUCKETS = ((128, 128, 1), (362, 362, 1), (724, 724, 1))
 
 
-def build_db(buckets=None, reps=5, log=None):
-    """Autotune every (family, dtype, shape) bucket; returns the database."""
+def tune_batch(sizes=None, segs=(8, 16, 32, 64), reps=3, dtype=H.F64, log=None):
+    """Segment length of the batched y sweep per size bucket, chosen by timing
+    the whole batch (its load balance depends on the mix): coordinate descent
+    over the buckets from seg 16 everywhere, two rounds.  Returns database
+    entries for HFAV_FAMILY_EULER_Y_BATCH."""
+    import torch
+    from .euler import EulerBatchStepper
+    sizes = inputs.batch_sizes(512) if sizes is None else sizes
+    states = inputs.batch_ic(sizes=sizes)
+    tdt = torch.float64 if dtype == H.F64 else torch.float32
+    bt = EulerBatchStepper(sizes, dtype=tdt)
+    bt.load(states)
+
+    def timed(choice):
+        H.tuning_clear()
+        for centre, seg in zip(BATCH_BUCKETS, choice):
+            H.tuning_add(FAMILY_ID["euler_y_batch"], dtype, centre, (64, 1, seg, 1, 0))
+        bt.iy = bt.cy.plan_batch(bt.sizes, config_source=H.CONFIG_TUNED)
+        return _event_ms(bt.step, reps)
+
+    choice = [16] * len(BATCH_BUCKETS)
+    best = timed(choice)
+    base = best
+    for _ in range(2):
+        for b in range(len(BATCH_BUCKETS)):
+            for seg in segs:
+                if seg == choice[b]:
+                    continue
+                trial = list(choice)
+                trial[b] = seg
+                ms = timed(trial)
+                if ms < best:
+                    best, choice = ms, trial
+    H.tuning_clear()
+    if log:
+        log(f"db: euler_y_batch {len(sizes)} grids: segments {choice} per bucket, {best:.3f} ms per step "
+            f"(16 everywhere: {base:.3f} ms)")
+    return [{"family": "euler_y_batch", "family_id": FAMILY_ID["euler_y_batch"], "dtype": DTYPE_NAME[dtype],
+             "dims": list(c), "config": [64, 1, seg, 1, 0], "ms": best, "default_ms": base,
+             "n_configs": len(segs) * len(BATCH_BUCKETS), "search_s": 0.0}
+            for c, seg in zip(BATCH_BUCKETS, choice)]
+
+
+def build_db(buckets=None, reps=5, log=None, batch=True):
+    """Autotune every (family, dtype, shape) bucket and the batch's segment
+    lengths; returns the database."""
     entries = []
     for family, dtype, dims in (DB_BUCKETS if buckets is None else buckets):
         t0 = time.time()
@@ -153,6 +199,8 @@ def build_db(buckets=None, reps=5, log=None):
         if log:
             log(f"db: {family} {DTYPE_NAME[dtype]} {dims}: best {best} {best_ms:.4f} ms "
                 f"(default {default_ms:.4f} ms, {len(res)} configs)")
+    if batch and buckets is None:
+        entries += tune_batch(log=log)
     return {"version": 1, "entries": entries}
 
 

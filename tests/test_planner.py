@@ -305,3 +305,20 @@ def test_random_star_chain_plans():
         halo = sum(s["r"] for s in ch["stages"])
         t = c.terms()
         assert t["x0"]["lo"][0] == -halo and t["x0"]["hi"][0] == halo
+
+
+def test_batch_segments_from_tuning_buckets():
+    c = H.Chain(H.euler_sweep_spec(1, dt_source="smax", with_smax=True))
+    H.tuning_clear()
+    try:
+        H.tuning_add(7, H.F64, (128, 128, 1), (64, 1, 8, 1, 0))
+        H.tuning_add(7, H.F64, (724, 724, 1), (64, 1, 32, 1, 0))
+        c.plan_batch([(100, 120), (700, 800), (90, 1000)], config_source=H.CONFIG_TUNED)
+        b = c.plan_json()["batch"]
+        assert b["grids"] == 3 and b["y_seg"][:2] == [8, 32]
+        c.plan_batch([(100, 120), (700, 800)])
+        assert c.plan_json()["batch"]["y_seg"] == [16, 16]
+        c.plan_batch([(100, 120)], config_source=H.CONFIG_FORCED, forced=(64, 1, 5, 1))
+        assert c.plan_json()["batch"]["y_seg"] == [5]
+    finally:
+        H.tuning_clear()
