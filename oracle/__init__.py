@@ -18,7 +18,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# HFAV_ORACLE_LIB points the tests at a deliberately broken build of the
+# oracle (tests/test_oracle_mutations.py checks that the pins catch it)
+_LIB_PATH = os.environ.get("HFAV_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 _dp = C.POINTER(C.c_double)

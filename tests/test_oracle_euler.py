@@ -234,3 +234,13 @@ def test_bruteforce_two_steps_8x8():
         assert np.abs(V - W).max() <= 1e-14 * np.abs(W).max()
     Vr, _ = oracle.euler_run(U, 2)
     assert np.array_equal(Vr, V)
+
+
+@pytest.mark.parametrize("u,v", [(0.3, -0.9), (-1.2, 0.4), (0.0, 0.0)])
+def test_smax_closed_form(u, v):
+    """Uniform state: the largest signal speed is max(|u|, |v|) + c with
+    c = sqrt(gamma p / rho)."""
+    rho, p = 0.7, 1.9
+    U = inputs.euler_state_from_prim(np.full((5, 6), rho), u, v, p)
+    expect = max(abs(u), abs(v)) + math.sqrt(G * p / rho)
+    assert abs(oracle.euler_smax(U) - expect) <= 1e-15 * expect
