@@ -122,8 +122,8 @@ typedef enum {
 } hfav_precision;
 typedef enum {
     HFAV_CONFIG_DEFAULT = 0,  /* built-in per-family default */
-    HFAV_CONFIG_TUNED = 1,    /* tuning table (hfav_set_tuning), else default */
-    HFAV_CONFIG_MODEL = 2,    /* learned cost model (hfav_set_cost_model), else default */
+    HFAV_CONFIG_TUNED = 1,    /* tuning table (hfav_tuning_add), else default */
+    HFAV_CONFIG_MODEL = 2,    /* learned cost model (hfav_costmodel_set), else default */
     HFAV_CONFIG_FORCED = 3    /* hfav_plan_opts.forced */
 } hfav_config_source;
 
@@ -268,9 +268,12 @@ int hfav_plan(hfav_chain *chain, const hfav_plan_opts *opts, hfav_plan_info *inf
  * stream).  axioms[] and goals[] are device pointers in declaration order.
  * `workspace` must hold info.workspace_bytes (it may be NULL when that is 0);
  * it is caller-owned device memory the call may overwrite.  Asynchronous: no
- * allocation, no synchronisation, no device-to-host read, so it can be
- * captured in a HIP graph.  Kernel faults surface at the caller's next
- * synchronisation.
+ * device allocation, no synchronisation, no device-to-host read, so it can
+ * be captured in a HIP graph.  One exception, the STAR_CHAIN family: its
+ * coefficient table travels with the call as an asynchronous host-to-device
+ * copy into the workspace from a pinned host buffer that the first execute
+ * after a plan allocates; capture such a chain only after one eager call.
+ * Kernel faults surface at the caller's next synchronisation.
  * Errors: ENOPLAN, EINVAL (null pointer), EALIAS, EDEVICE. */
 int hfav_execute(hfav_chain *chain, const void *const *axioms, void *const *goals,
                  void *workspace, void *stream);

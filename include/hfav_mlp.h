@@ -10,6 +10,10 @@
  * hfav_plan with config_source = HFAV_CONFIG_MODEL picks the candidate with
  * the smallest predicted time.
  *
+ * The paper tunes nothing automatically; this extension is the project's
+ * own (the network, its 24 features and the candidate set), trained with
+ * Adam (Kingma and Ba, 2015) on mean squared error.
+ *
  * Parameters are one flat float array: W1 (H,d) b1 (H) W2 (H,H) b2 (H)
  * W3 (H,H) b3 (H) W4 (1,H) b4 (1), row-major W[out][in].
  * Device entry points take DEVICE pointers and enqueue on `stream`; they

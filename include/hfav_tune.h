@@ -6,7 +6,7 @@
  * picks its configuration from one of three sources (hfav_plan_opts
  * .config_source): the built-in default, the tuning table below (filled
  * from exhaustive autotuner timings), or the learned cost model
- * (hfav_costmodel.h).  These calls are host-only and process-wide; they are
+ * (hfav_mlp.h).  These calls are host-only and process-wide; they are
  * safe to call from several threads.
  */
 #ifndef HFAV_TUNE_H
