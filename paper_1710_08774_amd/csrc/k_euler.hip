@@ -7,7 +7,7 @@
 // x pass (dependencies along the contiguous axis): one workgroup walks a row
 // in chunks of B cells, one lane per cell.  The contracted windows along i
 // (primitive state 3 cells, plus-face state 2 cells, flux 2 interfaces) are
-// LDS rings of 2B entries, so every value is produced once and read by its
+// LDS rings of B+4 entries, so every value is produced once and read by its
 // neighbour lanes: no halo recomputation except two cells per row.  Each
 // lane solves exactly one Riemann problem per chunk.
 //
@@ -84,7 +84,6 @@ template <class T, int B>
 struct XLds {
     static constexpr int R = B + 4;
     T w[5][R];      // primitive window (r, un, ut, p, c)
-    T u[4][R];      // conserved state, read back by the update
     T f[4][R];      // plus-face state
     T F[4][R];      // interface flux: slot of cell p holds F(p-1/2)
     T F0[4];        // F(-1/2) for the periodic wrap
@@ -98,7 +97,7 @@ __device__ __forceinline__ void x_row(const EArgs<T> &a, const EView<T> &v, int 
     const int nx = v.nx;
     const int t = threadIdx.x;
     const size_t row = (size_t)j * nx;
-    const T g = (T)a.g;
+    const T g = G14 ? T(1.4) : (T)a.g;     // gamma 7/5: constants fold
     const T nu = (T)dt;
     const A nuA = (A)dt;
     int ob = 0;                 // slot of cell c0 (c0 mod R)
@@ -115,8 +114,6 @@ __device__ __forceinline__ void x_row(const EArgs<T> &a, const EView<T> &v, int 
     auto put = [&](int sl, const T *u) {
         Prim<T> w = euler_prim(u[0], u[1], u[2], u[3], g);
         S.w[0][sl] = w.r; S.w[1][sl] = w.un; S.w[2][sl] = w.ut; S.w[3][sl] = w.p; S.w[4][sl] = w.c;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) S.u[q][sl] = u[q];
     };
     auto get_prim = [&](int sl) {
         Prim<T> w;
@@ -189,18 +186,20 @@ __device__ __forceinline__ void x_row(const EArgs<T> &a, const EView<T> &v, int 
         // stage 4: conservative update of cell p-1 (and of cell nx-1 at the end)
         if (act && p >= 1) {
             const size_t o = row + (p - 1);
-            v.orho[o] = euler_update(S.u[0][sm], S.F[0][s0], S.F[0][sm], nuA);
-            v.omn[o] = euler_update(S.u[1][sm], S.F[1][s0], S.F[1][sm], nuA);
-            v.omt[o] = euler_update(S.u[2][sm], S.F[2][s0], S.F[2][sm], nuA);
-            v.oE[o] = euler_update(S.u[3][sm], S.F[3][s0], S.F[3][sm], nuA);
+            // the conserved state of cell p-1 comes back from the cache (the
+            // lane two to the left loaded it two stages ago)
+            v.orho[o] = euler_update(v.rho[o], S.F[0][s0], S.F[0][sm], nuA);
+            v.omn[o] = euler_update(v.mn[o], S.F[1][s0], S.F[1][sm], nuA);
+            v.omt[o] = euler_update(v.mt[o], S.F[2][s0], S.F[2][sm], nuA);
+            v.oE[o] = euler_update(v.E[o], S.F[3][s0], S.F[3][sm], nuA);
         }
         if (act && p == nx - 1) {
             const size_t o = row + p;
             const T *Fp = a.bc == HFAV_BC_PERIODIC ? S.F0 : S.Fn;
-            v.orho[o] = euler_update(S.u[0][s0], Fp[0], S.F[0][s0], nuA);
-            v.omn[o] = euler_update(S.u[1][s0], Fp[1], S.F[1][s0], nuA);
-            v.omt[o] = euler_update(S.u[2][s0], Fp[2], S.F[2][s0], nuA);
-            v.oE[o] = euler_update(S.u[3][s0], Fp[3], S.F[3][s0], nuA);
+            v.orho[o] = euler_update(v.rho[o], Fp[0], S.F[0][s0], nuA);
+            v.omn[o] = euler_update(v.mn[o], Fp[1], S.F[1][s0], nuA);
+            v.omt[o] = euler_update(v.mt[o], Fp[2], S.F[2][s0], nuA);
+            v.oE[o] = euler_update(v.E[o], Fp[3], S.F[3][s0], nuA);
         }
     }
 }
@@ -239,7 +238,7 @@ __device__ __forceinline__ double y_tile(const EArgs<T> &a, const EView<T> &v, i
     const int nx = v.nx, ny = v.ny;
     const int t = threadIdx.x;
     const int i = i0 + t;
-    const T g = (T)a.g;
+    const T g = G14 ? T(1.4) : (T)a.g;     // gamma 7/5: constants fold
     const T nu = (T)dt;
     const A nuA = (A)dt;
     double smax = 0.0;
@@ -313,10 +312,11 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(WPE))) void e
 template <class T, int W, int C>
 struct SLds {
     static constexpr int RW = C + 2;    // cells c0-1 .. c0+C
-    static constexpr int RF = C + 1;    // cells c0-1 .. c0+C-1
+    static constexpr int RF = C + 2;    // cells c0-2 .. c0+C-1
     T w[5][RW][W];      // primitive state
-    T f[4][RF][W];      // plus-face state
-    T F[4][RF][W];      // flux F(p-1/2) in the slot of cell p
+    // plus-face state of cell p, replaced (once its reader has it) by the
+    // flux F(p+1/2): one ring serves both windows
+    T fF[4][RF][W];
 };
 
 // index along the sweep with the boundary applied (division only off the grid)
@@ -334,7 +334,7 @@ __device__ __forceinline__ double strip(const EArgs<T> &a, const EView<T> &v, bo
     const bool lact = line0 + wl < nlines;
     const size_t sa = xdir ? (size_t)1 : (size_t)v.nx;          // stride along the sweep
     const size_t lb = (size_t)(line0 + wl) * (xdir ? (size_t)v.nx : (size_t)1);
-    const T g = (T)a.g;
+    const T g = G14 ? T(1.4) : (T)a.g;     // gamma 7/5: constants fold
     const T nu = (T)dt;
     const A nuA = (A)dt;
     double smax = 0.0;
@@ -367,7 +367,7 @@ __device__ __forceinline__ double strip(const EArgs<T> &a, const EView<T> &v, bo
         slope_trace(get(j0 - 2), get(j0 - 1), get(j0), nu, plus, minus);
         const int sl = fs(j0 - 1);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) S.f[k][sl][wl] = plus[k];
+        for (int k = 0; k < 4; ++k) S.fF[k][sl][wl] = plus[k];
     }
     for (int c0 = j0; c0 <= j1; c0 += C) {
         const int p = c0 + q;
@@ -389,29 +389,37 @@ __device__ __forceinline__ double strip(const EArgs<T> &a, const EView<T> &v, bo
             slope_trace(get(p - 1), get(p), get(p + 1), nu, plus, minus);
             const int sl = fs(p);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) S.f[k][sl][wl] = plus[k];
+            for (int k = 0; k < 4; ++k) S.fF[k][sl][wl] = plus[k];
         }
         __syncthreads();
-        // stage 3: Riemann problem and flux at interface p-1/2
+        // stage 3: Riemann problem and flux at interface p-1/2; the flux
+        // takes the slot of the plus face of cell p-1 once every lane holds
+        // its left state
+        T Lf[4];
         if (act) {
-            T Lf[4], G[4], F[4];
-            const int sm = fs(p - 1), s0 = fs(p);
+            const int sm = fs(p - 1);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) Lf[k] = S.f[k][sm][wl];
+            for (int k = 0; k < 4; ++k) Lf[k] = S.fF[k][sm][wl];
+        }
+        __syncthreads();
+        if (act) {
+            T G[4], F[4];
             riemann_T<T, G14>(Lf, minus, g, a.niter, G);
             euler_flux(G, g, F);
+            const int sm = fs(p - 1);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) S.F[k][s0][wl] = F[k];
+            for (int k = 0; k < 4; ++k) S.fF[k][sm][wl] = F[k];
         }
         __syncthreads();
         // stage 4: conservative update of cell p-1 (inside the grid: no wrap)
+        // from F(p-1/2) (slot of p-1) and F(p-3/2) (slot of p-2)
         if (act && p > j0) {
             const size_t o = lb + (size_t)(p - 1) * sa;
-            const int sm = fs(p - 1), s0 = fs(p);
-            const T r = euler_update(v.rho[o], S.F[0][s0][wl], S.F[0][sm][wl], nuA);
-            const T mn = euler_update(v.mn[o], S.F[1][s0][wl], S.F[1][sm][wl], nuA);
-            const T mt = euler_update(v.mt[o], S.F[2][s0][wl], S.F[2][sm][wl], nuA);
-            const T e = euler_update(v.E[o], S.F[3][s0][wl], S.F[3][sm][wl], nuA);
+            const int s1 = fs(p - 1), s2 = fs(p - 2);
+            const T r = euler_update(v.rho[o], S.fF[0][s1][wl], S.fF[0][s2][wl], nuA);
+            const T mn = euler_update(v.mn[o], S.fF[1][s1][wl], S.fF[1][s2][wl], nuA);
+            const T mt = euler_update(v.mt[o], S.fF[2][s1][wl], S.fF[2][s2][wl], nuA);
+            const T e = euler_update(v.E[o], S.fF[3][s1][wl], S.fF[3][s2][wl], nuA);
             v.orho[o] = r; v.omn[o] = mn; v.omt[o] = mt; v.oE[o] = e;
             if (want_smax) smax = fmax(smax, (double)euler_speed(r, mt, mn, e, g));
         }

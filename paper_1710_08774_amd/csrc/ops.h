@@ -69,6 +69,11 @@ __device__ __forceinline__ double frsq(double x) {
     return fma(y * e, fma(e, 0.375, 0.5), y);
 }
 
+// sqrt(x) for positive finite x: x times the refined reciprocal square
+// root (about one unit in the last place); float keeps the library sqrt.
+__device__ __forceinline__ double fsqrt(double x) { return x * frsq(x); }
+__device__ __forceinline__ float fsqrt(float x) { return sqrtf(x); }
+
 // Primitive state of one cell: constoprim + equation_of_state.
 template <class T>
 struct Prim { T r, un, ut, p, c; };
@@ -81,7 +86,7 @@ __device__ __forceinline__ Prim<T> euler_prim(T rho, T mn, T mt, T E, T g) {
     w.un = mn * ir;
     w.ut = mt * ir;
     w.p = (g - T(1)) * (E - T(0.5) * rho * (w.un * w.un + w.ut * w.ut));
-    w.c = sqrt(g * w.p * ir);
+    w.c = fsqrt(g * w.p * ir);
     return w;
 }
 
@@ -126,26 +131,28 @@ __device__ __forceinline__ void euler_trace(const Prim<T>& w, T dr, T du, T dv, 
     minus[3] = w.p - cc * (cm0 + cm3);
 }
 
-// x^(-1/7) for x > 0: a single-precision hardware log2/exp2 estimate
-// (relative error e0 ~ 1e-7) refined by one third-order step of the
-// iteration for w^-7 = x: with e = 1 - x w^7, the exact correction factor is
-// (1 - e)^(-1/7) = 1 + e/7 + 4e^2/49 + O(e^3), so the error after the step is
-// O(e0^3), far below double rounding.  Arguments outside the
-// single-precision normal range are first scaled exactly by 2^(-7k), with k
-// from the binary exponent, and the root by 2^k afterwards.
-__device__ __forceinline__ double rroot7(double x) {
-    int k = 0;
-    if (!(x > 1e-30 && x < 1e30)) {
-        k = __builtin_amdgcn_frexp_exp(x);                      // x = m 2^e, m in [1/2, 1)
-        k = (k >= 0 ? k : k - 6) / 7;                           // floor(e / 7)
-        x = __builtin_amdgcn_ldexp(x, -7 * k);
-    }
+// x^(-6/7) for x > 0 (the rarefaction branch needs no other power: x^(1/7)
+// = x * x^(-6/7)).  A single-precision hardware log2/exp2 estimate w of
+// x^(-1/7) (relative error e0 ~ 1e-7) is corrected once: with
+// e = 1 - x w^7, the exact factor is (1 - e)^(-1/7) = 1 + t,
+// t = e/7 + 4e^2/49 + O(e^3), so x^(-6/7) = w^6 (1 + 6t + 15t^2 + O(t^3)),
+// an error O(e0^3) far below double rounding.
+__device__ __forceinline__ double rpow67_core(double x) {
     const float l = __builtin_amdgcn_logf((float)x);            // log2
     const double w = (double)__builtin_amdgcn_exp2f(l * (-1.0f / 7.0f));
-    const double w2 = w * w, w4 = w2 * w2, w7 = w4 * w2 * w;
+    const double w2 = w * w, w4 = w2 * w2, w6 = w4 * w2, w7 = w6 * w;
     const double e = fma(-x, w7, 1.0);
     const double t = e * fma(e, 4.0 / 49.0, 1.0 / 7.0);
-    return __builtin_amdgcn_ldexp(fma(w, t, w), -k);
+    return fma(w6, t * fma(t, 15.0, 6.0), w6);
+}
+// Arguments outside the single-precision normal range (rare) are first
+// scaled exactly by 2^(-7k), with k from the binary exponent, and the power
+// by 2^(-6k) afterwards.
+__device__ __forceinline__ double rpow67(double x) {
+    if (x > 1e-30 && x < 1e30) return rpow67_core(x);
+    int k = __builtin_amdgcn_frexp_exp(x);                      // x = m 2^e, m in [1/2, 1)
+    k = (k >= 0 ? k : k - 6) / 7;                               // floor(e / 7)
+    return __builtin_amdgcn_ldexp(rpow67_core(__builtin_amdgcn_ldexp(x, -7 * k)), -6 * k);
 }
 
 // Pressure-function data of one side of the Riemann problem (Toro ch. 4).
@@ -160,6 +167,7 @@ struct Side {
 
 template <bool G14>
 __device__ __forceinline__ Side make_side(double r, double u, double p, double g) {
+    if (G14) g = 1.4;     // the gamma constants below fold at compile time
     Side s;
     s.r = r; s.u = u; s.p = p;
     const double t = frsq(g * p * r);         // 1/(rho c), since rho c = sqrt(g p rho)
@@ -186,9 +194,8 @@ __device__ __forceinline__ void pres_fun(const Side& s, double p, double g, doub
     } else {
         double x = p * s.ip;
         if (G14) {
-            double w = rroot7(x);
-            double w2 = w * w, w6 = w2 * w2 * w2;
-            f = s.k2 * (x * w6 - 1.0);
+            const double w6 = rpow67(x);     // x^(-6/7)
+            f = s.k2 * fma(x, w6, -1.0);     // k2 (x^(1/7) - 1)
             fd = s.irc * w6;
         } else {
             f = s.k2 * (pow(x, (g - 1.0) / (2.0 * g)) - 1.0);
@@ -201,9 +208,7 @@ __device__ __forceinline__ void pres_fun(const Side& s, double p, double g, doub
 template <bool G14>
 __device__ __forceinline__ void pow_g1_ig(double x, double g, double& z, double& zig) {
     if (G14) {
-        double w = rroot7(x);
-        double w2 = w * w;
-        z = x * (w2 * w2 * w2);        // x^(1/7)
+        z = x * rpow67(x);             // x^(1/7)
         double z2 = z * z;
         zig = z2 * z2 * z;             // x^(5/7)
     } else {
@@ -229,6 +234,7 @@ __device__ __forceinline__ void pow_fan(double c, double g, double& c5, double& 
 template <bool G14>
 __device__ __forceinline__ void riemann0(const double* L, const double* R, double g, int niter,
                                          double* W) {
+    if (G14) g = 1.4;     // the gamma constants below fold at compile time
     const Side sl = make_side<G14>(L[0], L[1], L[3], g);
     const Side sr = make_side<G14>(R[0], R[1], R[3], g);
     const double du = sr.u - sl.u;
@@ -258,7 +264,7 @@ __device__ __forceinline__ void riemann0(const double* L, const double* R, doubl
     double rr, uu, pp;
     if (p > s.p) {                           // shock
         double pm = p * s.ip;
-        double sk = uk - s.c * sqrt(g2 * pm + g1);
+        double sk = uk - s.c * fsqrt(g2 * pm + g1);
         if (0.0 <= sk) { rr = s.r; uu = uk; pp = s.p; }
         else { rr = s.r * (pm + g6) * frcp(pm * g6 + 1.0); uu = ustar; pp = p; }
     } else {                                 // rarefaction
@@ -307,7 +313,7 @@ __device__ __forceinline__ T euler_speed(T rho, T mx, T my, T E, T g) {
     const T ir = frcp(rho);
     T u = mx * ir, v = my * ir;
     T p = (g - T(1)) * (E - T(0.5) * rho * (u * u + v * v));
-    T c = sqrt(g * p * ir);
+    T c = fsqrt(g * p * ir);
     return fmax(fabs(u) + c, fabs(v) + c);
 }
 
