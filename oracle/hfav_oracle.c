@@ -531,6 +531,68 @@ int oracle_biharm(const double *u, double *out, int nz, int ny, int nx, double n
 }
 
 /* ======================================================================
+ * Normalisation example (Design, "Reductions & broadcasts & splits";
+ * Performance, "Normalization Example"): one-dimensional flux differences
+ * of a system of nq fields u[q][j][i], periodic in i, each row's flux
+ * vectors normalised by the row's norm.  Five kernels visit the (j, i)
+ * space, one kernel works on rows only:
+ *   flux      f[q][j][i] = u[q][j][i+1] - u[q][j][i]
+ *   square    e[j][i]    = sum_q f[q][j][i]^2                (q order)
+ *   accumulate s[j]      = sum_i e[j][i]  (init 0, i order; rank 2 -> 1)
+ *   root      n[j]       = sqrt(s[j])                        (rank 1)
+ *   divide    d[q][j][i] = f[q][j][i] / n[j]   (0 when n[j] = 0; broadcast)
+ *   update    out[q][j][i] = u[q][j][i] - c d[q][j][i]
+ * Each kernel is a full-array pass.  n_o (nullable) receives n (nj).
+ * ====================================================================== */
+int oracle_normalize(const double *u, double *out, int nq, int nj, int ni, double c, double *n_o)
+{
+    if (!u || !out || nq <= 0 || nj <= 0 || ni <= 0) return ORA_EARG;
+    const size_t P = (size_t)nj * ni;
+    double *f = malloc(sizeof(double) * P * nq), *e = malloc(sizeof(double) * P);
+    double *d = malloc(sizeof(double) * P * nq), *sn = malloc(sizeof(double) * nj);
+    double *nn = malloc(sizeof(double) * nj);
+    if (!f || !e || !d || !sn || !nn) { free(f); free(e); free(d); free(sn); free(nn); return ORA_ENOMEM; }
+    #pragma omp parallel for collapse(2)
+    for (int q = 0; q < nq; ++q)
+        for (int j = 0; j < nj; ++j)
+            for (int i = 0; i < ni; ++i)
+                f[q * P + (size_t)j * ni + i] = u[q * P + (size_t)j * ni + wrap(i + 1, ni)] -
+                                                u[q * P + (size_t)j * ni + i];
+    #pragma omp parallel for
+    for (int j = 0; j < nj; ++j)
+        for (int i = 0; i < ni; ++i) {
+            double acc = 0.0;
+            for (int q = 0; q < nq; ++q) {
+                double v = f[q * P + (size_t)j * ni + i];
+                acc += v * v;
+            }
+            e[(size_t)j * ni + i] = acc;
+        }
+    #pragma omp parallel for
+    for (int j = 0; j < nj; ++j) {
+        double acc = 0.0;
+        for (int i = 0; i < ni; ++i) acc += e[(size_t)j * ni + i];
+        sn[j] = acc;
+    }
+    for (int j = 0; j < nj; ++j) nn[j] = sqrt(sn[j]);
+    #pragma omp parallel for collapse(2)
+    for (int q = 0; q < nq; ++q)
+        for (int j = 0; j < nj; ++j)
+            for (int i = 0; i < ni; ++i)
+                d[q * P + (size_t)j * ni + i] = nn[j] > 0.0 ? f[q * P + (size_t)j * ni + i] / nn[j] : 0.0;
+    #pragma omp parallel for collapse(2)
+    for (int q = 0; q < nq; ++q)
+        for (int j = 0; j < nj; ++j)
+            for (int i = 0; i < ni; ++i) {
+                size_t o = q * P + (size_t)j * ni + i;
+                out[o] = u[o] - c * d[o];
+            }
+    if (n_o) memcpy(n_o, nn, sizeof(double) * nj);
+    free(f); free(e); free(d); free(sn); free(nn);
+    return ORA_OK;
+}
+
+/* ======================================================================
  * Generic linear star-stencil chain interpreter.  Stage s maps f_in fields
  * to f_out fields:  out[o](x) = sum_f sum_q c[o][f][q] * in[f](x + off[q]),
  * accumulated from 0 in (f, q) order, periodic on every axis.  Offsets of

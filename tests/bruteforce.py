@@ -203,3 +203,24 @@ def euler_smax_bf(U, g=1.4):
             c = math.sqrt(g * p / r)
             s = max(s, abs(u) + c, abs(v) + c)
     return s
+
+
+def normalize_bf(u, c):
+    """Normalisation example from its definition, with plain loops: flux
+    differences along i (periodic), the row norm over all flux vectors of
+    the row, and out = u - c f / norm (0 where the norm is 0)."""
+    nq, nj, ni = len(u), len(u[0]), len(u[0][0])
+    out = [[[0.0] * ni for _ in range(nj)] for _ in range(nq)]
+    norms = []
+    for j in range(nj):
+        f = [[u[q][j][(i + 1) % ni] - u[q][j][i] for i in range(ni)] for q in range(nq)]
+        s = 0.0
+        for i in range(ni):
+            for q in range(nq):
+                s += f[q][i] * f[q][i]
+        n = math.sqrt(s)
+        norms.append(n)
+        for q in range(nq):
+            for i in range(ni):
+                out[q][j][i] = u[q][j][i] - c * (f[q][i] / n if n > 0 else 0.0)
+    return out, norms

@@ -18,6 +18,7 @@ SRC = os.path.join(ROOT, "oracle", "hfav_oracle.c")
 
 HDIFF, EULER, L7, MLP = ("test_oracle_hdiff.py", "test_oracle_euler.py", "test_oracle_biharm_chain.py",
                          "test_oracle_biharm_chain.py")
+NORM = "test_oracle_norm.py"
 
 # (name, original text, mutated text, pin file)
 MUTANTS = [
@@ -68,6 +69,12 @@ MUTANTS = [
      "gW3[(size_t)o * H + i] += d3[o] * h1[i];", MLP),
     ("Adam drops bias correction", "double mh = m[q] / c1, vh = v[q] / c2;", "double mh = m[q], vh = v[q] / c2;",
      MLP),
+    ("normalisation flux index", "u[q * P + (size_t)j * ni + wrap(i + 1, ni)] -",
+     "u[q * P + (size_t)j * ni + wrap(i + 2, ni)] -", NORM),
+    ("normalisation square dropped", "acc += v * v;", "acc += v;", NORM),
+    ("normalisation root dropped", "for (int j = 0; j < nj; ++j) nn[j] = sqrt(sn[j]);",
+     "for (int j = 0; j < nj; ++j) nn[j] = sn[j];", NORM),
+    ("normalisation update sign", "out[o] = u[o] - c * d[o];", "out[o] = u[o] + c * d[o];", NORM),
 ]
 
 
