@@ -156,6 +156,55 @@ def bandwidth_chains(reps=10, which=("hdiff", "biharm64", "biharm32"), unfused=T
     return out
 
 
+def norm_chain(reps=20, nq=4, nj=4096, ni=4096, unfused=True):
+    """Normalisation chain (flux differences, row norm, broadcast division,
+    update) on nq FP64 fields of nj rows x ni cells, fused (one workgroup per
+    row, both inner sweeps) and unfused (one kernel per rule), timed with HIP
+    events on the launch stream.  Compulsory bytes: each u read once and
+    each out written once, 2 nq 8 B per cell."""
+    import torch
+    from paper_1710_08774_amd import hfav as H
+    from paper_1710_08774_amd import inputs
+
+    u = torch.as_tensor(inputs.norm_input(nq, nj, ni)).to("cuda")
+    o = torch.empty_like(u)
+    cells = nj * ni
+    out = {"fields": nq, "rows": nj, "cells_per_row": ni, "dtype": "f64"}
+    stream = torch.cuda.current_stream()
+    for mode, name in ((H.MODE_FUSED, "fused"), (H.MODE_UNFUSED, "unfused")):
+        if mode == H.MODE_UNFUSED and not unfused:
+            continue
+        c = H.Chain(H.norm_spec(nq))
+        info = c.plan((ni, nj), mode=mode)
+        ws = torch.empty(max(1, info.workspace_bytes), dtype=torch.uint8, device="cuda")
+        args = ([u[q] for q in range(nq)], [o[q] for q in range(nq)], ws)
+        c.execute(*args)
+        torch.cuda.synchronize()
+        n = reps if mode == H.MODE_FUSED else max(2, reps // 4)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(n):
+            c.execute(*args)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / n
+        out[name + "_ms"] = ms
+        out[name + "_cell_updates_per_s"] = cells / (ms * 1e-3)
+        out["bytes_per_cell_" + name] = info.bytes_per_cell_fused if mode == H.MODE_FUSED \
+            else info.bytes_per_cell_unfused
+        if mode == H.MODE_FUSED:
+            gbs = 2 * nq * 8 * cells / (ms * 1e-3) / 1e9
+            out.update({"fused_GBs": gbs, "fused_frac_of_8TBs": gbs / HBM_PEAK_GBS,
+                        "config": [info.config.block, info.config.seg, info.config.variant],
+                        "nests": info.n_nests, "outer_of_nest": list(info.outer_of_nest[:info.n_nests])})
+        del ws
+    if "unfused_ms" in out:
+        out["fused_over_unfused"] = out["unfused_ms"] / out["fused_ms"]
+    del u, o
+    torch.cuda.empty_cache()
+    return out
+
+
 def hdiff_config_shape(execs=1000):
     """The horizontal-diffusion chain at 256x256x8 FP64: its 8 MiB working set
     stays in the caches and one execution is shorter than a launch, so the
@@ -292,7 +341,8 @@ def main(argv=None):
                     help="only run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--no-aux", action="store_true",
                     help="skip the bandwidth-bound chains and the FP32 hydro variant")
-    ap.add_argument("--only", choices=["hdiff", "biharm64", "biharm32", "batch", "hdiff_small"], default=None,
+    ap.add_argument("--only", choices=["hdiff", "biharm64", "biharm32", "batch", "hdiff_small", "norm"],
+                    default=None,
                     help="only time one bandwidth-bound chain, or the batched grids (for profiling)")
     a = ap.parse_args(argv)
     if a.gpus != 1:
@@ -319,6 +369,11 @@ def main(argv=None):
         return 0
     if a.only == "hdiff_small":
         print(json.dumps({"workload": "hdiff_256x256x8", **hdiff_config_shape()}), flush=True)
+        return 0
+    if a.only == "norm":
+        print(json.dumps({"workload": "norm_4x4096x4096_f64", **norm_chain(reps=a.steps,
+                                                                            unfused=not a.no_unfused)}),
+              flush=True)
         return 0
     if a.only == "batch":
         print(json.dumps({"workload": "batch", **batched_grids()}), flush=True)
@@ -371,6 +426,7 @@ def main(argv=None):
             "compulsory_GBs": 64 * cells / (f32["ms_per_step"] * 1e-3) / 1e9}
         aux["batch_512_grids"] = batched_grids()
         aux["hdiff_256x256x8"] = hdiff_config_shape()
+        aux["norm_4x4096x4096"] = norm_chain()
         line["aux"] = aux
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(U0)

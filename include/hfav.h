@@ -107,11 +107,26 @@ typedef enum {
     HFAV_OP_LAP7 = 20,         /* in: u(0), u(+i), u(-i), u(+j), u(-j), u(+k), u(-k)
                                   -> ((e+w)+(n+s))+(t+b) - 6c                      */
     HFAV_OP_AXPY = 21,         /* in: a, b -> a + param[0]*b                       */
-    HFAV_OP_STAR = 22          /* in: n refs -> sum_q param[q]*ref_q, accumulated
+    HFAV_OP_STAR = 22,         /* in: n refs -> sum_q param[q]*ref_q, accumulated
                                   in reference order from zero                    */
+    /* Reductions, broadcasts and splits (Design, "Reductions & broadcasts &
+     * splits"; the normalisation example of Performance, "Normalization
+     * Example").  A ROW TERM has rank ndim - 1: one value per row of the
+     * innermost axis i, indexed by the remaining axes (j, or (j, k)), stored
+     * as a dense array of dims[1] * dims[2] elements in the chain dtype.
+     * References to row terms take no offsets. */
+    HFAV_OP_SUMSQ = 30,        /* in: 1..24 grid refs -> sum_q ref_q^2, accumulated
+                                  in reference order from zero                    */
+    HFAV_OP_SUM_I = 31,        /* in: x (grid, offset 0) -> row term s = sum over i
+                                  of x; reduce must be HFAV_REDUCE_SUM (identity
+                                  0, any association order: the init, accumulate
+                                  and finalise phases of a reduction)             */
+    HFAV_OP_SQRT = 32,         /* in: x (grid or row term) -> sqrt(x), same rank  */
+    HFAV_OP_DIV0 = 33          /* in: a (grid), b (grid, or row term broadcast
+                                  along i) -> a / b, and 0 where b == 0           */
 } hfav_op;
 
-typedef enum { HFAV_REDUCE_NONE = 0, HFAV_REDUCE_MAX = 1 } hfav_reduce;
+typedef enum { HFAV_REDUCE_NONE = 0, HFAV_REDUCE_MAX = 1, HFAV_REDUCE_SUM = 2 } hfav_reduce;
 typedef enum { HFAV_BC_PERIODIC = 0, HFAV_BC_TRANSMISSIVE = 1 } hfav_bc;
 typedef enum { HFAV_MODE_AUTO = 0, HFAV_MODE_FUSED = 1, HFAV_MODE_UNFUSED = 2 } hfav_mode;
 typedef enum {
@@ -135,9 +150,14 @@ typedef enum {
     HFAV_FAMILY_LAP7_CHAIN = 4,
     HFAV_FAMILY_STAR_CHAIN = 5,
     HFAV_FAMILY_SMAX = 6,
-    HFAV_FAMILY_EULER_Y_BATCH = 7  /* tuning-table key only: the segment length
+    HFAV_FAMILY_EULER_Y_BATCH = 7, /* tuning-table key only: the segment length
                                      (config.seg) of one grid's batched y
                                      sweep, by that grid's (nx, ny) */
+    HFAV_FAMILY_NORM = 8      /* flux differences along i (STAR, two refs at
+                                 di = 0 and +1) of nq <= 8 fields, SUMSQ of the
+                                 fluxes, SUM_I, SQRT, one DIV0 and one AXPY per
+                                 field; optional row goal: the norm.  One
+                                 workgroup per row runs both inner sweeps */
 } hfav_family;
 
 typedef enum {
@@ -149,6 +169,9 @@ typedef enum {
                                   ("outer" rotation) */
     HFAV_STORE_SCALAR = 4      /* 0-D term */
 } hfav_storage;
+/* A row term produced and consumed inside one outer iteration is REGISTER
+ * (one value per row); a grid term passed between two inner sweeps of one
+ * outer iteration is OUTER with a window of one slab (the row). */
 
 /* --------------------------------------------------------------- the chain */
 typedef struct {
@@ -165,13 +188,14 @@ typedef struct {
     int n_param;
     const double *param;
     int reduce;                 /* hfav_reduce: MAX makes the (single) output a
-                                   0-D term accumulated over the iteration space */
+                                   0-D term accumulated over the iteration space
+                                   (EULER_SMAX); SUM goes with SUM_I */
 } hfav_rule;
 
 typedef struct {
     const char *name;
     int rank;                   /* 0 for a scalar (device pointer to one double),
-                                   otherwise the grid rank (must equal ndim) */
+                                   ndim for a grid, ndim - 1 for a row term */
 } hfav_term_decl;
 
 typedef struct {
@@ -236,6 +260,11 @@ typedef struct {
     double bytes_per_cell_fused;        /* compulsory HBM bytes per cell: axioms once + goals once */
     double bytes_per_cell_unfused;      /* HBM bytes per cell of the one-kernel-per-rule path */
     size_t workspace_bytes;             /* device workspace hfav_execute needs (0 for most fused) */
+    int outer_of_nest[HFAV_MAX_NESTS];  /* nests with the same value share their outer
+                                           loops (every axis but i): a split that only
+                                           the inner axis needs, such as a reduction
+                                           along i feeding a broadcast along i, leaves
+                                           one outer nest holding two inner sweeps */
 } hfav_plan_info;
 
 typedef struct {

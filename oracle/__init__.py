@@ -47,7 +47,7 @@ def _load():
     lib.oracle_euler_run.argtypes = [_dp, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
                                      C.c_int, C.c_int, _dp]
     lib.oracle_lap7.argtypes = [_dp, _dp, C.c_int, C.c_int, C.c_int]
-    lib.oracle_normalize.argtypes = [_dp, _dp, C.c_int, C.c_int, C.c_int, C.c_double, _dp]
+    lib.oracle_normalize.argtypes = [_dp, _dp, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, _dp]
     lib.oracle_biharm.argtypes = [_dp, _dp, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int,
                                   _dp, _dp]
     lib.oracle_linear_chain.argtypes = [C.c_int, _ip, _ip, _ip, _dp, _dp, _dp,
@@ -192,15 +192,16 @@ def euler_run(U, nsteps, gamma=GAMMA, cfl=CFL, bc=BC_PERIODIC, niter=NEWTON_ITER
 BIHARM_NU = 1.0 / 128.0
 
 
-def normalize(u, c=1.0, norms=False):
+def normalize(u, c=1.0, norms=False, periodic=True):
     """Normalisation example: u (nq, nj, ni); out = u - c * f / |f|_row with
-    f the flux differences along i and |f|_row the norm over the row's flux
+    f the flux differences along i (the row end wraps, or repeats the last
+    cell when periodic is False) and |f|_row the norm over the row's flux
     vectors (0 where the row norm is 0).  Returns out (and the row norms)."""
     a = _f64(u)
     nq, nj, ni = a.shape
     out = np.empty_like(a)
     n = np.empty(nj)
-    _check(_load().oracle_normalize(_ptr(a), _ptr(out), nq, nj, ni, float(c), _ptr(n)))
+    _check(_load().oracle_normalize(_ptr(a), _ptr(out), nq, nj, ni, float(c), int(bool(periodic)), _ptr(n)))
     return (out, n) if norms else out
 
 

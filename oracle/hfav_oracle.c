@@ -533,9 +533,10 @@ int oracle_biharm(const double *u, double *out, int nz, int ny, int nx, double n
 /* ======================================================================
  * Normalisation example (Design, "Reductions & broadcasts & splits";
  * Performance, "Normalization Example"): one-dimensional flux differences
- * of a system of nq fields u[q][j][i], periodic in i, each row's flux
- * vectors normalised by the row's norm.  Five kernels visit the (j, i)
- * space, one kernel works on rows only:
+ * of a system of nq fields u[q][j][i], each row's flux vectors normalised
+ * by the row's norm.  Along i the row end wraps (periodic != 0) or repeats
+ * the last cell (transmissive: the last flux is 0).  Five kernels visit the
+ * (j, i) space, one kernel works on rows only:
  *   flux      f[q][j][i] = u[q][j][i+1] - u[q][j][i]
  *   square    e[j][i]    = sum_q f[q][j][i]^2                (q order)
  *   accumulate s[j]      = sum_i e[j][i]  (init 0, i order; rank 2 -> 1)
@@ -544,7 +545,8 @@ int oracle_biharm(const double *u, double *out, int nz, int ny, int nx, double n
  *   update    out[q][j][i] = u[q][j][i] - c d[q][j][i]
  * Each kernel is a full-array pass.  n_o (nullable) receives n (nj).
  * ====================================================================== */
-int oracle_normalize(const double *u, double *out, int nq, int nj, int ni, double c, double *n_o)
+int oracle_normalize(const double *u, double *out, int nq, int nj, int ni, double c, int periodic,
+                     double *n_o)
 {
     if (!u || !out || nq <= 0 || nj <= 0 || ni <= 0) return ORA_EARG;
     const size_t P = (size_t)nj * ni;
@@ -556,8 +558,9 @@ int oracle_normalize(const double *u, double *out, int nq, int nj, int ni, doubl
     for (int q = 0; q < nq; ++q)
         for (int j = 0; j < nj; ++j)
             for (int i = 0; i < ni; ++i)
-                f[q * P + (size_t)j * ni + i] = u[q * P + (size_t)j * ni + wrap(i + 1, ni)] -
-                                                u[q * P + (size_t)j * ni + i];
+                f[q * P + (size_t)j * ni + i] =
+                    u[q * P + (size_t)j * ni + (periodic ? wrap(i + 1, ni) : clampi(i + 1, ni))] -
+                    u[q * P + (size_t)j * ni + i];
     #pragma omp parallel for
     for (int j = 0; j < nj; ++j)
         for (int i = 0; i < ni; ++i) {

@@ -39,6 +39,10 @@ static const OpSpec kOps[] = {
     {HFAV_OP_LAP7, "LAP7", 7, 1, 0, -1, 0},
     {HFAV_OP_AXPY, "AXPY", 2, 1, 1, -1, 0},
     {HFAV_OP_STAR, "STAR", -1, 1, 0, -1, 0},
+    {HFAV_OP_SUMSQ, "SUMSQ", -1, 1, 0, -1, 0},
+    {HFAV_OP_SUM_I, "SUM_I", 1, 1, 0, -1, 0},
+    {HFAV_OP_SQRT, "SQRT", 1, 1, 0, -1, 0},
+    {HFAV_OP_DIV0, "DIV0", 2, 1, 0, -1, 0},
 };
 
 const OpSpec *op_spec(int op) {
@@ -98,8 +102,8 @@ static int build(const hfav_chain_desc *d, hfav_chain *c) {
         const hfav_term_decl &ax = d->axioms[a];
         if (!ax.name || !*ax.name) return hfav_fail(HFAV_EINVAL, "axiom without a name");
         if (id.count(ax.name)) return hfav_fail(HFAV_EDUP, std::string("axiom declared twice: ") + ax.name);
-        if (ax.rank != 0 && ax.rank != d->ndim)
-            return hfav_fail(HFAV_EINVAL, std::string("axiom rank must be 0 or ndim: ") + ax.name);
+        if (ax.rank != 0 && ax.rank != d->ndim && ax.rank != d->ndim - 1)
+            return hfav_fail(HFAV_EINVAL, std::string("axiom rank must be 0, ndim - 1 or ndim: ") + ax.name);
         int t = intern(ax.name);
         c->terms[t].kind = TK_AXIOM;
         c->terms[t].rank = ax.rank;
@@ -126,8 +130,12 @@ static int build(const hfav_chain_desc *d, hfav_chain *c) {
             return hfav_fail(HFAV_EINVAL, "STAR rule with more than 96 references");
         if (sp->out_rank0 && sp->op == HFAV_OP_EULER_SMAX && dr.reduce != HFAV_REDUCE_MAX)
             return hfav_fail(HFAV_EINVAL, "EULER_SMAX must declare reduce = MAX");
-        if (dr.reduce != HFAV_REDUCE_NONE && sp->op != HFAV_OP_EULER_SMAX)
-            return hfav_fail(HFAV_EINVAL, "only EULER_SMAX reduces");
+        if (sp->op == HFAV_OP_SUM_I && dr.reduce != HFAV_REDUCE_SUM)
+            return hfav_fail(HFAV_EINVAL, "SUM_I must declare reduce = SUM");
+        if (dr.reduce != HFAV_REDUCE_NONE && sp->op != HFAV_OP_EULER_SMAX && sp->op != HFAV_OP_SUM_I)
+            return hfav_fail(HFAV_EINVAL, "only EULER_SMAX and SUM_I reduce");
+        if (sp->op == HFAV_OP_SUMSQ && dr.n_in > 24)
+            return hfav_fail(HFAV_EINVAL, "SUMSQ rule with more than 24 references");
         HRule h;
         h.op = dr.op;
         h.reduce = dr.reduce;
@@ -222,28 +230,40 @@ static int build(const hfav_chain_desc *d, hfav_chain *c) {
     for (int r = 0; r < nr; ++r) nlive += c->live[r];
     if ((int)c->topo.size() != nlive) return hfav_fail(HFAV_ECYCLE, "the dataflow graph has a cycle");
 
-    // term and rule ranks, in topological order
+    // term and rule ranks, in topological order.  Terms are 0-D, grids
+    // (rank ndim) or row terms (rank ndim - 1, one value per row of i).
+    // Row terms enter only where an op takes them: SQRT's input and DIV0's
+    // divisor (a broadcast along i); SUM_I is the reduction that makes one.
+    const int nd = c->ndim, row = c->ndim - 1;
     for (int r : c->topo) {
         HRule &R = c->rules[r];
         const OpSpec *sp = op_spec(R.op);
-        bool any_grid = false;
+        bool any_grid = false, any_row = false;
         for (size_t q = 0; q < R.in.size(); ++q) {
             const HTerm &T = c->terms[R.in[q].term];
             if (T.rank < 0) return hfav_fail(HFAV_EUNSAT, "term " + T.name + " has no producer before use");
             const bool want0 = (int)q == sp->scalar_in || (sp->op == HFAV_OP_EULER_DT);
-            if (want0 && T.rank != 0)
-                return hfav_fail(HFAV_EINVAL, std::string(sp->name) + ": input " + std::to_string(q) + " must be 0-D");
-            if (!want0 && T.rank == 0)
-                return hfav_fail(HFAV_EINVAL, std::string(sp->name) + ": input " + std::to_string(q) + " must be a grid term");
-            if (T.rank == 0) {
+            const bool row_ok = (sp->op == HFAV_OP_SQRT) || (sp->op == HFAV_OP_DIV0 && q == 1);
+            const std::string where = std::string(sp->name) + ": input " + std::to_string(q);
+            if (want0 && T.rank != 0) return hfav_fail(HFAV_EINVAL, where + " must be 0-D");
+            if (!want0 && T.rank == 0) return hfav_fail(HFAV_EINVAL, where + " must be a grid term");
+            if (T.rank == row && !row_ok) return hfav_fail(HFAV_EINVAL, where + " cannot be a row term");
+            if (T.rank == 0 || T.rank == row) {
                 for (int ax = 0; ax < 3; ++ax)
-                    if (R.in[q].off[ax] != 0) return hfav_fail(HFAV_EINVAL, "0-D reference with an offset");
-            } else {
-                any_grid = true;
+                    if (R.in[q].off[ax] != 0)
+                        return hfav_fail(HFAV_EINVAL, T.rank == 0 ? "0-D reference with an offset"
+                                                                  : "row-term reference with an offset");
             }
+            if (T.rank == nd) any_grid = true;
+            if (T.rank == row) any_row = true;
         }
-        R.rank = any_grid ? c->ndim : 0;
-        const int orank = sp->out_rank0 ? 0 : R.rank;
+        if (sp->op == HFAV_OP_SUM_I)
+            for (int ax = 0; ax < 3; ++ax)
+                if (R.in[0].off[ax] != 0) return hfav_fail(HFAV_EINVAL, "SUM_I reads its input at offset 0");
+        if (sp->op == HFAV_OP_DIV0 && c->terms[R.in[0].term].rank != nd)
+            return hfav_fail(HFAV_EINVAL, "DIV0: input 0 must be a grid term");
+        R.rank = any_grid ? nd : any_row ? row : 0;
+        const int orank = sp->out_rank0 ? 0 : sp->op == HFAV_OP_SUM_I ? row : R.rank;
         for (int t : R.out) c->terms[t].rank = orank;
     }
     return HFAV_OK;

@@ -39,7 +39,9 @@ size_t term_bytes(const hfav_chain *c, int t) {
     }
     if (c->terms[t].rank == 0) return 8;
     const int *d = c->plan.opts.dims;
-    return (size_t)d[0] * d[1] * d[2] * (c->dtype == HFAV_F64 ? 8 : 4);
+    const size_t es = c->dtype == HFAV_F64 ? 8 : 4;
+    if (c->terms[t].rank == c->ndim - 1) return (size_t)d[1] * d[2] * es;   // row term
+    return (size_t)d[0] * d[1] * d[2] * es;
 }
 
 bool overlap(const void *a, size_t na, const void *b, size_t nb) {
@@ -187,6 +189,25 @@ int run_fused(const hfav_chain *c, const Bind &B, hipStream_t s) {
         return dev_err(hfav::launch_euler_smax(U, d[0] * d[1] * d[2], p.fam_param[0], out, c->dtype, s),
                        "smax launch");
     }
+    case HFAV_FAMILY_NORM: {
+        hfav::NormLaunch L;
+        memset(&L, 0, sizeof(L));
+        L.nq = (int)p.fam_in.size();
+        for (int q = 0; q < L.nq; ++q) {
+            L.u[q] = B.ptr(p.fam_in[q]);
+            L.out[q] = B.wptr(p.fam_out[q]);
+            L.c0[q] = p.fam_param[3 * q];
+            L.cp[q] = p.fam_param[3 * q + 1];
+            L.alpha[q] = p.fam_param[3 * q + 2];
+        }
+        L.norm = p.fam_row_goal >= 0 ? B.wptr(p.fam_row_goal) : nullptr;
+        L.ni = d[0];
+        L.nrows = d[1] * d[2];
+        L.bc = p.opts.boundary[0];
+        L.dtype = c->dtype;
+        L.cfg = p.info.config;
+        return dev_err(hfav::launch_norm(L, s), "normalisation kernel launch");
+    }
     default:
         return hfav_fail(HFAV_EUNSUP, "no fused family");
     }
@@ -234,6 +255,7 @@ int run_unfused(const hfav_chain *c, const Bind &B, hipStream_t s) {
         for (int ax = 0; ax < 3; ++ax) U.bc[ax] = p.opts.boundary[ax];
         U.dtype = c->dtype;
         U.precision = p.opts.precision;
+        U.ndim = c->ndim;
         if (R.op == HFAV_OP_EULER_SMAX) {
             int rc = dev_err(hfav::launch_fill_scalar((double *)U.out[0], 0.0, s), "reduction init");
             if (rc) return rc;

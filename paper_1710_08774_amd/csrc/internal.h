@@ -18,7 +18,8 @@ struct HRule {
     std::vector<int> out;        // term ids
     std::vector<double> param;
     int reduce;
-    int rank;                    // iteration-space rank: 0 (scalar rule) or ndim
+    int rank;                    // iteration-space rank: 0 (scalar rule), ndim - 1
+                                 // (a rule over row terms) or ndim
 };
 
 enum { TK_AXIOM = 0, TK_INTER = 1, TK_GOAL = 2 };
@@ -36,7 +37,7 @@ struct HTerm {
 // An iteration nest with its three phases (Design, "Iteration nests").
 // Perfect nests have only a steady state.
 struct HNest {
-    int rank;                    // 0 for a scalar nest
+    int rank;                    // 0 for a scalar nest, ndim - 1 for a nest over rows
     std::vector<int> prologue, steady, epilogue;   // rule indices
 };
 
@@ -53,6 +54,7 @@ struct HPlan {
     hfav_plan_opts opts{};
     hfav_plan_info info{};
     std::vector<HNest> nests;
+    std::vector<int> outer;      // outer group per nest (nests sharing their outer loops)
     std::vector<HTermPlan> terms;
     int family = HFAV_FAMILY_NONE;
     // family bindings: term ids in the family's canonical argument order
@@ -62,6 +64,7 @@ struct HPlan {
     double fam_cfl = 0.0;
     int fam_smax_goal = -1;      // 0-D goal of a fused reduction, -1
     std::vector<double> fam_param;
+    int fam_row_goal = -1;       // NORM family: the row norm as a goal, -1
     // unfused: workspace offset per term (-1 = not in workspace)
     std::vector<int64_t> ws_off;
     size_t ws_bytes = 0;

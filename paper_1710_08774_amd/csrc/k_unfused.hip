@@ -17,6 +17,8 @@ struct UArgs {
     double param[UF_MAX_PARAM];
     int nx, ny, nz;
     int bc[3];
+    int n_in;
+    int brow;                         // in[1] is a row term (broadcast along i)
 };
 
 __device__ __forceinline__ int uwrap(int i, int n, int bc) {
@@ -89,8 +91,39 @@ __global__ __launch_bounds__(256) void rule_kernel(UArgs a) {
         st<T>(a, 0, idx, lap7(IN(0), IN(1), IN(2), IN(3), IN(4), IN(5), IN(6)));
     } else if constexpr (OP == HFAV_OP_AXPY) {
         st<T>(a, 0, idx, axpy(IN(0), IN(1), (T)a.param[0]));
+    } else if constexpr (OP == HFAV_OP_SUMSQ) {
+        T acc = T(0);
+        for (int r = 0; r < a.n_in; ++r) {
+            const T v = IN(r);
+            acc = fma(v, v, acc);
+        }
+        st<T>(a, 0, idx, acc);
+    } else if constexpr (OP == HFAV_OP_DIV0) {
+        const T b = a.brow ? ((const T *)a.in[1])[(size_t)k * a.ny + j] : IN(1);
+        st<T>(a, 0, idx, b != T(0) ? IN(0) / b : T(0));
     }
 #undef IN
+}
+
+// SQRT over n elements (a grid or a row term)
+template <class T>
+__global__ __launch_bounds__(256) void rule_sqrt_kernel(UArgs a, size_t n) {
+    const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx < n) ((T *)a.out[0])[idx] = sqrt(((const T *)a.in[0])[idx]);
+}
+
+// SUM_I: one workgroup per row of i, the row's sum into the row term
+template <class T>
+__global__ __launch_bounds__(256) void rule_sum_i_kernel(UArgs a) {
+    __shared__ T part[4];
+    const T *x = (const T *)a.in[0] + (size_t)blockIdx.x * a.nx;
+    T s = T(0);
+    for (int i = threadIdx.x; i < a.nx; i += 256) s += x[i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) ((T *)a.out[0])[blockIdx.x] = (part[0] + part[1]) + (part[2] + part[3]);
 }
 
 // reduction rule: accumulate max(|u|+c, |v|+c) into a 0-D term
@@ -136,6 +169,16 @@ static hipError_t dispatch_rule(const UnfusedRule &R, const UArgs &a, hipStream_
     case HFAV_OP_EULER_UPDATE: launch_op<HFAV_OP_EULER_UPDATE, T, A, G14>(a, n, s); break;
     case HFAV_OP_LAP7: launch_op<HFAV_OP_LAP7, T, A, G14>(a, n, s); break;
     case HFAV_OP_AXPY: launch_op<HFAV_OP_AXPY, T, A, G14>(a, n, s); break;
+    case HFAV_OP_SUMSQ: launch_op<HFAV_OP_SUMSQ, T, A, G14>(a, n, s); break;
+    case HFAV_OP_DIV0: launch_op<HFAV_OP_DIV0, T, A, G14>(a, n, s); break;
+    case HFAV_OP_SQRT: {
+        const size_t m = R.out_rank == R.ndim ? n : (size_t)R.ny * R.nz;
+        hipLaunchKernelGGL((rule_sqrt_kernel<T>), dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, a, m);
+        break;
+    }
+    case HFAV_OP_SUM_I:
+        hipLaunchKernelGGL((rule_sum_i_kernel<T>), dim3((unsigned)((size_t)R.ny * R.nz)), dim3(256), 0, s, a);
+        break;
     case HFAV_OP_EULER_SMAX: {
         unsigned nb = (unsigned)((n + 255) / 256);
         if (nb > 4096) nb = 4096;
@@ -161,6 +204,8 @@ hipError_t launch_unfused_rule(const UnfusedRule &R, hipStream_t s) {
     for (int q = 0; q < UF_MAX_PARAM; ++q) a.param[q] = R.param[q];
     a.nx = R.nx; a.ny = R.ny; a.nz = R.nz;
     for (int d = 0; d < 3; ++d) a.bc[d] = R.bc[d];
+    a.n_in = R.n_in;
+    a.brow = R.n_in > 1 && R.in_rank[1] == R.ndim - 1;
     double g = R.param[0];
     const bool g14 = (R.op == HFAV_OP_EULER_RIEMANN) && g == 1.4;
     if (R.dtype == HFAV_F64)

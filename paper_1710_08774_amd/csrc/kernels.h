@@ -73,6 +73,23 @@ struct Lap7ChainLaunch {
 };
 hipError_t launch_lap7_chain(const Lap7ChainLaunch &L, hipStream_t s);
 
+// ---- normalisation chain: one workgroup per row of i (NORM family)
+enum { NORM_MAX_Q = 8, NORM_REG_BUDGET = 32 };   // fields; register slots nq * cells per thread
+struct NormLaunch {
+    const void *u[NORM_MAX_Q];
+    void *out[NORM_MAX_Q];
+    void *norm;                       // row goal (nrows values), or null
+    double c0[NORM_MAX_Q], cp[NORM_MAX_Q], alpha[NORM_MAX_Q];
+    int nq, ni, nrows;
+    int bc;                           // boundary along i
+    int dtype;
+    hfav_config cfg;                  // block; seg = cells per thread (variant 0);
+                                      // variant 0 registers, 1 two streamed sweeps
+};
+bool norm_config_ok(int nq, int ni, const hfav_config &c);
+hfav_config norm_default_config(int nq, int ni);
+hipError_t launch_norm(const NormLaunch &L, hipStream_t s);
+
 // ---- unfused path: one kernel per rule over full arrays
 enum { UF_MAX_IN = 24, UF_MAX_OUT = 8, UF_MAX_PARAM = 4 };
 struct UnfusedRule {
@@ -88,6 +105,7 @@ struct UnfusedRule {
     int bc[3];
     int dtype;
     int precision;
+    int ndim;                         // row terms have rank ndim - 1
 };
 hipError_t launch_unfused_rule(const UnfusedRule &R, hipStream_t s);
 

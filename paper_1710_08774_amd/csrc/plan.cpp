@@ -291,6 +291,83 @@ bool match_lap7_chain(const hfav_chain *c, HPlan &p) {
     return true;
 }
 
+// Normalisation chain (Performance, "Normalization Example"): per field q
+// a flux f_q = STAR(u_q(0), u_q(+i)), e = SUMSQ(f_0 .. f_{nq-1}),
+// s = SUM_I(e), n = SQRT(s), d_q = DIV0(f_q, n), out_q = AXPY(u_q, d_q).
+// Family parameters per field: coefficient of u(0), of u(+i), the AXPY
+// factor.  Fields are numbered in the SUMSQ reference order.
+bool match_norm(const hfav_chain *c, HPlan &p) {
+    const int nd = c->ndim;
+    if (c->order[nd - 1] != 0) return false;
+    if (p.opts.boundary[0] != HFAV_BC_PERIODIC && p.opts.boundary[0] != HFAV_BC_TRANSMISSIVE) return false;
+    const int rsq = find_op(c, HFAV_OP_SUMSQ), rsu = find_op(c, HFAV_OP_SUM_I), rrt = find_op(c, HFAV_OP_SQRT);
+    if (rsq < 0 || rsu < 0 || rrt < 0) return false;
+    const HRule &SQ = c->rules[rsq], &SU = c->rules[rsu], &RT = c->rules[rrt];
+    const int nq = (int)SQ.in.size();
+    if (nq < 1 || nq > 8 || c->topo.size() != (size_t)(3 + 3 * nq)) return false;
+    const int e = SQ.out[0], s = SU.out[0], n = RT.out[0];
+    if (!is_inter(c, e) || !is_inter(c, s) || c->terms[s].rank != nd - 1) return false;
+    if (SU.in[0].term != e || RT.in[0].term != s) return false;
+    if (c->terms[n].kind == TK_GOAL) {
+        if (c->goals.size() != (size_t)nq + 1) return false;
+    } else if (c->goals.size() != (size_t)nq) {
+        return false;
+    }
+    std::vector<int> u(nq), out(nq), used;
+    std::vector<double> prm;
+    for (int q = 0; q < nq; ++q) {
+        const HRef &fr = SQ.in[q];
+        const int f = fr.term;
+        if (!ref_is(c, fr, f, 0, 0, 0) || !is_inter(c, f) || c->terms[f].rank != nd) return false;
+        for (int g = 0; g < q; ++g)
+            if (SQ.in[g].term == f) return false;
+        const HRule &F = c->rules[c->terms[f].producer];
+        if (F.op != HFAV_OP_STAR || F.in.size() != 2) return false;
+        const int uq = F.in[0].term;
+        if (c->terms[uq].kind != TK_AXIOM || c->terms[uq].rank != nd || F.in[1].term != uq) return false;
+        double c0 = 0.0, cp = 0.0;
+        bool have0 = false, havep = false;
+        for (int k = 0; k < 2; ++k) {
+            if (ref_is(c, F.in[k], uq, 0, 0, 0) && !have0) { c0 = F.param[k]; have0 = true; }
+            else if (ref_is(c, F.in[k], uq, 1, 0, 0) && !havep) { cp = F.param[k]; havep = true; }
+            else return false;
+        }
+        // the DIV0 and AXPY rules of this field
+        int rd = -1, ra = -1;
+        for (int r : c->topo) {
+            const HRule &R = c->rules[r];
+            if (R.op == HFAV_OP_DIV0 && R.in[0].term == f) {
+                if (rd >= 0 || !ref_is(c, R.in[0], f, 0, 0, 0) || R.in[1].term != n) return false;
+                rd = r;
+            }
+        }
+        if (rd < 0 || !is_inter(c, c->rules[rd].out[0])) return false;
+        const int d = c->rules[rd].out[0];
+        for (int r : c->topo) {
+            const HRule &R = c->rules[r];
+            if (R.op == HFAV_OP_AXPY && R.in[1].term == d) {
+                if (ra >= 0 || !ref_is(c, R.in[0], uq, 0, 0, 0) || !ref_is(c, R.in[1], d, 0, 0, 0)) return false;
+                ra = r;
+            }
+        }
+        if (ra < 0 || c->terms[c->rules[ra].out[0]].kind != TK_GOAL) return false;
+        for (int r : {c->terms[f].producer, rd, ra}) {
+            if (std::find(used.begin(), used.end(), r) != used.end()) return false;
+            used.push_back(r);
+        }
+        u[q] = uq;
+        out[q] = c->rules[ra].out[0];
+        prm.push_back(c0);
+        prm.push_back(cp);
+        prm.push_back(c->rules[ra].param[0]);
+    }
+    p.fam_in = u;
+    p.fam_out = out;
+    p.fam_param = prm;
+    p.fam_row_goal = c->terms[n].kind == TK_GOAL ? n : -1;
+    return true;
+}
+
 size_t esize(int dtype) { return dtype == HFAV_F64 ? 8 : 4; }
 
 void json_int3(std::ostringstream &o, const int *v) { o << "[" << v[0] << "," << v[1] << "," << v[2] << "]"; }
@@ -481,8 +558,11 @@ int hfav_plan_impl(hfav_chain *c, const hfav_plan_opts *o, hfav_plan_info *info)
         tp.storage = HFAV_STORE_FULL;
         for (int ax = 0; ax < 3; ++ax) tp.lo[ax] = tp.hi[ax] = 0;
     }
-    auto widen = [&](int t, const int *lo, const int *hi) {
+    auto widen = [&](int t, const int *lo_in, const int *hi_in) {
         HTermPlan &tp = p.terms[t];
+        // a row term has no i axis: its extent along i is a single point
+        int lo[3] = {lo_in[0], lo_in[1], lo_in[2]}, hi[3] = {hi_in[0], hi_in[1], hi_in[2]};
+        if (c->terms[t].rank == nd - 1) lo[0] = hi[0] = 0;
         if (!tp.has_ext) {
             tp.has_ext = true;
             for (int ax = 0; ax < 3; ++ax) { tp.lo[ax] = lo[ax]; tp.hi[ax] = hi[ax]; }
@@ -522,10 +602,43 @@ int hfav_plan_impl(hfav_chain *c, const hfav_plan_opts *o, hfav_plan_info *info)
         }
     }
 
-    // ---- storage classes and windows
+    // ---- outer groups.  Fusion above works at the level of the innermost
+    // axis; a split there (a reduction along i whose result a later rule
+    // broadcasts back along i) need not split the loops outside it (Design,
+    // "Fusing iteration nests": equal outer ranks fuse phase by phase, the
+    // split happens inside).  Consecutive nests that iterate every outer
+    // axis share one outer loop, each outer iteration running their inner
+    // sweeps in order, when every term passed from an earlier nest of the
+    // group to a later one is needed at the current outer point only: a
+    // grid term whose extent is zero along every outer axis, or a row term.
+    // A 0-D term (a reduction over the whole space) is complete only after
+    // the last outer iteration and always ends the group.  i must be the
+    // innermost axis.
     std::vector<int> nest_of(c->rules.size(), -1);
     for (size_t n = 0; n < p.nests.size(); ++n)
         for (int r : all_phases(p.nests[n])) nest_of[r] = (int)n;
+    std::vector<int> outer(p.nests.size(), 0);
+    {
+        const bool i_inner = c->order[nd - 1] == 0;
+        int g = 0;
+        for (size_t n = 1; n < p.nests.size(); ++n) {
+            bool join = i_inner && p.nests[n].rank >= nd - 1 && p.nests[n - 1].rank >= nd - 1;
+            for (int r : all_phases(p.nests[n]))
+                for (const HRef &ref : c->rules[r].in) {
+                    const int pr = c->terms[ref.term].producer;
+                    if (!join || pr < 0 || nest_of[pr] == (int)n || outer[nest_of[pr]] != g) continue;
+                    const HTermPlan &tp = p.terms[ref.term];
+                    if (c->terms[ref.term].rank == 0) join = false;
+                    for (int ax = 1; ax < nd; ++ax)
+                        if (tp.lo[ax] != 0 || tp.hi[ax] != 0) join = false;
+                }
+            if (!join) ++g;
+            outer[n] = g;
+        }
+    }
+
+    // ---- storage classes and windows
+    const int64_t nrows = (int64_t)o->dims[1] * o->dims[2];
     int64_t fp_un = 0, fp_con = 0;
     int maxw = 0;
     for (int t = 0; t < nt; ++t) {
@@ -534,11 +647,34 @@ int hfav_plan_impl(hfav_chain *c, const hfav_plan_opts *o, hfav_plan_info *info)
         if (T.rank == 0) { tp.storage = HFAV_STORE_SCALAR; continue; }
         if (T.kind != TK_INTER) { tp.storage = HFAV_STORE_FULL; continue; }
         if (T.producer < 0 || !c->live[T.producer]) continue;
-        fp_un += ncell;
-        bool same_nest = true;
+        const bool rowt = T.rank == nd - 1;
+        fp_un += rowt ? nrows : ncell;
+        bool same_nest = true, same_outer = true;
         for (int r : c->topo)
             for (const HRef &ref : c->rules[r].in)
-                if (ref.term == t && nest_of[r] != nest_of[T.producer]) same_nest = false;
+                if (ref.term == t) {
+                    if (nest_of[r] != nest_of[T.producer]) same_nest = false;
+                    if (outer[nest_of[r]] != outer[nest_of[T.producer]]) same_outer = false;
+                }
+        if (rowt) {                     // one value per outer iteration, or a row array
+            if (same_outer) {
+                tp.storage = HFAV_STORE_REGISTER;
+                tp.window = 1;
+                fp_con += 1;
+                maxw = std::max(maxw, 1);
+            } else {
+                fp_con += nrows;
+            }
+            continue;
+        }
+        if (!same_nest && same_outer) { // between two inner sweeps: one row slab
+            tp.storage = HFAV_STORE_OUTER;
+            tp.window_axis = c->order[nd - 2];
+            tp.window = 1;
+            fp_con += o->dims[0];
+            maxw = std::max(maxw, 1);
+            continue;
+        }
         if (!same_nest) {
             tp.storage = HFAV_STORE_FULL;
             fp_con += ncell;
@@ -580,20 +716,21 @@ int hfav_plan_impl(hfav_chain *c, const hfav_plan_opts *o, hfav_plan_info *info)
     // ---- byte counts
     const size_t es = esize(c->dtype);
     double bf = 0.0, bu = 0.0;
+    // (grid terms only: 0-D and row terms cost O(1 / ni) bytes per cell)
     for (int t : c->axioms)
-        if (c->terms[t].rank > 0) bf += es;
+        if (c->terms[t].rank == nd) bf += es;
     for (int t : c->goals)
-        if (c->terms[t].rank > 0) bf += es;
+        if (c->terms[t].rank == nd) bf += es;
     for (int r : c->topo) {
         const HRule &R = c->rules[r];
         if (R.rank == 0) continue;
         std::vector<int> seen;
         for (const HRef &ref : R.in)
-            if (c->terms[ref.term].rank > 0 && std::find(seen.begin(), seen.end(), ref.term) == seen.end())
+            if (c->terms[ref.term].rank == nd && std::find(seen.begin(), seen.end(), ref.term) == seen.end())
                 seen.push_back(ref.term);
         bu += es * seen.size();
         for (int t : R.out)
-            if (c->terms[t].rank > 0) bu += es;
+            if (c->terms[t].rank == nd) bu += es;
     }
 
     // ---- kernel family
@@ -605,6 +742,7 @@ int hfav_plan_impl(hfav_chain *c, const hfav_plan_opts *o, hfav_plan_info *info)
     } else if (match_lap7_chain(c, p)) p.family = HFAV_FAMILY_LAP7_CHAIN;
     else if (match_smax(c, p)) p.family = HFAV_FAMILY_SMAX;
     else if (match_star_chain(c, p)) p.family = HFAV_FAMILY_STAR_CHAIN;
+    else if (match_norm(c, p)) p.family = HFAV_FAMILY_NORM;
     else p.family = HFAV_FAMILY_NONE;
     if (o->precision == HFAV_PREC_F32_F64ACC && p.family != HFAV_FAMILY_EULER_X &&
         p.family != HFAV_FAMILY_EULER_Y && o->mode == HFAV_MODE_FUSED)
@@ -634,6 +772,19 @@ int hfav_plan_impl(hfav_chain *c, const hfav_plan_opts *o, hfav_plan_info *info)
         if (hfav_tuned_config(p.family, c->dtype, o->dims, &cfg)) src = HFAV_CONFIG_TUNED;
     } else if (o->config_source == HFAV_CONFIG_MODEL) {
         if (p.family == HFAV_FAMILY_STAR_CHAIN && star_model_choose(c, p, o->dims, &cfg)) src = HFAV_CONFIG_MODEL;
+    }
+
+    // ---- NORM: block and cells per thread from the field count and the
+    // row length (variant 0 holds the row in registers when it fits)
+    if (p.family == HFAV_FAMILY_NORM) {
+        const int nq = (int)p.fam_in.size();
+        if (src == HFAV_CONFIG_FORCED) {
+            if (!hfav::norm_config_ok(nq, o->dims[0], cfg))
+                return hfav_fail(HFAV_EUNSUP, "forced normalisation configuration does not cover the row");
+        } else if (src != HFAV_CONFIG_TUNED || !hfav::norm_config_ok(nq, o->dims[0], cfg)) {
+            cfg = hfav::norm_default_config(nq, o->dims[0]);
+            src = HFAV_CONFIG_DEFAULT;
+        }
     }
 
     // ---- STAR_CHAIN: groups of fused stages (config.tile_y = stages per
@@ -674,7 +825,7 @@ int hfav_plan_impl(hfav_chain *c, const hfav_plan_opts *o, hfav_plan_info *info)
             const HTerm &T = c->terms[t];
             if (T.kind != TK_INTER || T.producer < 0 || !c->live[T.producer]) continue;
             p.ws_off[t] = (int64_t)p.ws_bytes;
-            size_t b = T.rank == 0 ? 8 : (size_t)ncell * es;
+            size_t b = T.rank == 0 ? 8 : T.rank == nd - 1 ? (size_t)nrows * es : (size_t)ncell * es;
             p.ws_bytes += (b + 255) / 256 * 256;
         }
     }
@@ -694,7 +845,8 @@ int hfav_plan_impl(hfav_chain *c, const hfav_plan_opts *o, hfav_plan_info *info)
         }
     I.family = p.family;
     I.fused = fused ? 1 : 0;
-    I.streamed_axis = p.family == HFAV_FAMILY_EULER_X ? 0 : p.family == HFAV_FAMILY_LAP7_CHAIN ? 2 : 1;
+    I.streamed_axis = (p.family == HFAV_FAMILY_EULER_X || p.family == HFAV_FAMILY_NORM) ? 0
+                      : p.family == HFAV_FAMILY_LAP7_CHAIN ? 2 : 1;
     I.config = cfg;
     I.config_source = src;
     I.footprint_unfused = fp_un;
@@ -703,6 +855,8 @@ int hfav_plan_impl(hfav_chain *c, const hfav_plan_opts *o, hfav_plan_info *info)
     I.bytes_per_cell_fused = bf;
     I.bytes_per_cell_unfused = bu;
     I.workspace_bytes = p.ws_bytes;
+    for (size_t n = 0; n < p.nests.size(); ++n) I.outer_of_nest[n] = outer[n];
+    p.outer = outer;
 
     // ---- JSON
     std::ostringstream js;
@@ -714,7 +868,7 @@ int hfav_plan_impl(hfav_chain *c, const hfav_plan_opts *o, hfav_plan_info *info)
             for (size_t q = 0; q < v.size(); ++q) js << (q ? "," : "") << v[q];
             js << "]";
         };
-        js << (n ? "," : "") << "{\"rank\":" << N.rank << ",\"prologue\":";
+        js << (n ? "," : "") << "{\"rank\":" << N.rank << ",\"outer\":" << outer[n] << ",\"prologue\":";
         lst(N.prologue);
         js << ",\"steady\":";
         lst(N.steady);

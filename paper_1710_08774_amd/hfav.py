@@ -29,16 +29,18 @@ OP = {
     "EULER_PRIM": 10, "EULER_SLOPE": 11, "EULER_TRACE": 12, "EULER_RIEMANN": 13,
     "EULER_FLUX": 14, "EULER_UPDATE": 15, "EULER_SMAX": 16, "EULER_DT": 17,
     "LAP7": 20, "AXPY": 21, "STAR": 22,
+    "SUMSQ": 30, "SUM_I": 31, "SQRT": 32, "DIV0": 33,
 }
-REDUCE_NONE, REDUCE_MAX = 0, 1
+REDUCE_NONE, REDUCE_MAX, REDUCE_SUM = 0, 1, 2
 BC_PERIODIC, BC_TRANSMISSIVE = 0, 1
 MODE_AUTO, MODE_FUSED, MODE_UNFUSED = 0, 1, 2
 PREC_NATIVE, PREC_F32_F64ACC = 0, 1
 CONFIG_DEFAULT, CONFIG_TUNED, CONFIG_MODEL, CONFIG_FORCED = 0, 1, 2, 3
 FAMILY = {0: "none", 1: "hdiff", 2: "euler_x", 3: "euler_y", 4: "lap7_chain", 5: "star_chain", 6: "smax",
-          7: "euler_y_batch"}
+          7: "euler_y_batch", 8: "norm"}
 STORAGE = {0: "full", 1: "register", 2: "inner", 3: "outer", 4: "scalar"}
 MAX_RULES = 64
+MAX_NESTS = 8
 COST_FEATURES = 24
 COST_MAX_CANDIDATES = 64
 
@@ -81,7 +83,8 @@ class hfav_plan_info(C.Structure):
                 ("config", hfav_config), ("config_source", C.c_int),
                 ("footprint_unfused", C.c_int64), ("footprint_contracted", C.c_int64),
                 ("max_window", C.c_int), ("bytes_per_cell_fused", C.c_double),
-                ("bytes_per_cell_unfused", C.c_double), ("workspace_bytes", C.c_size_t)]
+                ("bytes_per_cell_unfused", C.c_double), ("workspace_bytes", C.c_size_t),
+                ("outer_of_nest", C.c_int * MAX_NESTS)]
 
 
 class hfav_term_info(C.Structure):
@@ -461,6 +464,25 @@ def biharm_spec(nu=1.0 / 128.0, dtype=F64) -> ChainSpec:
                      rules=[Rule("LAP7", lap7_refs("u"), ["lap1"]),
                             Rule("LAP7", lap7_refs("lap1"), ["lap2"]),
                             Rule("AXPY", [("u", (0, 0, 0)), ("lap2", (0, 0, 0))], ["out"], [-nu])])
+
+
+def norm_spec(nq=4, c=1.0, dtype=F64, ndim=2, with_norm=False, loop_order=None) -> ChainSpec:
+    """Normalisation chain (Performance, "Normalization Example") over nq
+    fields u0..u{nq-1}: flux f_q = u_q(i+1) - u_q(i), e = sum_q f_q^2,
+    s = row sum of e (a reduction along i to a row term), n = sqrt(s),
+    d_q = f_q / n (0 where n = 0; a broadcast of n along i) and
+    out_q = u_q - c d_q.  with_norm adds the row norm n as a goal."""
+    z = (0, 0, 0)
+    us = [f"u{q}" for q in range(nq)]
+    rules = [Rule("STAR", [(u, (1, 0, 0)), (u, z)], [f"f{q}"], [1.0, -1.0]) for q, u in enumerate(us)]
+    rules += [Rule("SUMSQ", [(f"f{q}", z) for q in range(nq)], ["e"]),
+              Rule("SUM_I", [("e", z)], ["s"], reduce=REDUCE_SUM),
+              Rule("SQRT", [("s", z)], ["n"])]
+    rules += [Rule("DIV0", [(f"f{q}", z), ("n", z)], [f"d{q}"]) for q in range(nq)]
+    rules += [Rule("AXPY", [(u, z), (f"d{q}", z)], [f"out{q}"], [-c]) for q, u in enumerate(us)]
+    goals = [f"out{q}" for q in range(nq)] + (["n"] if with_norm else [])
+    return ChainSpec(ndim=ndim, dtype=dtype, loop_order=loop_order, axioms=[(u, ndim) for u in us],
+                     goals=goals, rules=rules)
 
 
 def star_chain_spec(chain: dict, offsets_fn) -> ChainSpec:

@@ -14,6 +14,9 @@ these synthetic inputs stand in for them, Performance section):
 * biharm: sum of 8 random Fourier modes plus 1e-6 uniform noise on a cube.
 * batch:  many Sod-like grids with independent sides in [64, 1024].
 * chain:  random linear star-stencil chains for the tuning cost model.
+* norm:   a system of nq fields on rows of i: per row and field a sinusoid of
+          random wavenumber, amplitude and phase on a random offset, plus
+          small uniform noise; every 17th row constant (zero flux, zero norm).
 """
 from __future__ import annotations
 
@@ -21,7 +24,7 @@ import numpy as np
 
 # Base of the per-workload seeds: SeedSequence(BASE_SEED + workload index).
 BASE_SEED = 171008774
-W_HDIFF, W_EULER, W_PREC, W_BATCH, W_CHAIN = 0, 1, 2, 3, 4
+W_HDIFF, W_EULER, W_PREC, W_BATCH, W_CHAIN, W_NORM = 0, 1, 2, 3, 4, 5
 
 
 def seed_seq(seed) -> np.random.SeedSequence:
@@ -32,6 +35,24 @@ def seed_seq(seed) -> np.random.SeedSequence:
 
 def rng_for(seed) -> np.random.Generator:
     return np.random.Generator(np.random.PCG64(seed_seq(seed)))
+
+
+# ---------------------------------------------------------------- norm
+def norm_input(nq=4, nj=4096, ni=4096, seed=BASE_SEED + W_NORM, noise=1e-2, const_every=17) -> np.ndarray:
+    """(nq, nj, ni) float64: u[q, j, i] = b + A sin(2 pi k i / ni + phi) +
+    noise * U[-1, 1), with b ~ U[-1, 1), A ~ U[0.1, 2), k ~ U{1..8} and
+    phi ~ U[0, 2 pi) drawn per (q, j); rows j = 0 mod const_every hold the
+    constant b (their flux and norm are 0)."""
+    rng = rng_for(seed)
+    b = rng.uniform(-1.0, 1.0, (nq, nj, 1))
+    A = rng.uniform(0.1, 2.0, (nq, nj, 1))
+    k = rng.integers(1, 9, (nq, nj, 1))
+    phi = rng.uniform(0.0, 2 * np.pi, (nq, nj, 1))
+    i = np.arange(ni)[None, None, :]
+    u = b + A * np.sin(2 * np.pi * k * i / ni + phi) + noise * rng.uniform(-1.0, 1.0, (nq, nj, ni))
+    if const_every:
+        u[:, ::const_every, :] = b[:, ::const_every, :]
+    return np.ascontiguousarray(u)
 
 
 # ---------------------------------------------------------------- hdiff

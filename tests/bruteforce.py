@@ -205,15 +205,18 @@ def euler_smax_bf(U, g=1.4):
     return s
 
 
-def normalize_bf(u, c):
+def normalize_bf(u, c, periodic=True):
     """Normalisation example from its definition, with plain loops: flux
-    differences along i (periodic), the row norm over all flux vectors of
-    the row, and out = u - c f / norm (0 where the norm is 0)."""
+    differences along i (the right neighbour of the last cell is the first
+    cell, or the last cell itself when not periodic), the row norm over all
+    flux vectors of the row, and out = u - c f / norm (0 where the norm is
+    0)."""
     nq, nj, ni = len(u), len(u[0]), len(u[0][0])
     out = [[[0.0] * ni for _ in range(nj)] for _ in range(nq)]
     norms = []
     for j in range(nj):
-        f = [[u[q][j][(i + 1) % ni] - u[q][j][i] for i in range(ni)] for q in range(nq)]
+        right = [(i + 1) % ni if periodic else min(i + 1, ni - 1) for i in range(ni)]
+        f = [[u[q][j][right[i]] - u[q][j][i] for i in range(ni)] for q in range(nq)]
         s = 0.0
         for i in range(ni):
             for q in range(nq):

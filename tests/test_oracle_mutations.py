@@ -69,8 +69,10 @@ MUTANTS = [
      "gW3[(size_t)o * H + i] += d3[o] * h1[i];", MLP),
     ("Adam drops bias correction", "double mh = m[q] / c1, vh = v[q] / c2;", "double mh = m[q], vh = v[q] / c2;",
      MLP),
-    ("normalisation flux index", "u[q * P + (size_t)j * ni + wrap(i + 1, ni)] -",
-     "u[q * P + (size_t)j * ni + wrap(i + 2, ni)] -", NORM),
+    ("normalisation flux index", "(periodic ? wrap(i + 1, ni) : clampi(i + 1, ni))",
+     "(periodic ? wrap(i + 2, ni) : clampi(i + 1, ni))", NORM),
+    ("normalisation transmissive end wraps", "(periodic ? wrap(i + 1, ni) : clampi(i + 1, ni))",
+     "(periodic ? wrap(i + 1, ni) : wrap(i + 1, ni))", NORM),
     ("normalisation square dropped", "acc += v * v;", "acc += v;", NORM),
     ("normalisation root dropped", "for (int j = 0; j < nj; ++j) nn[j] = sqrt(sn[j]);",
      "for (int j = 0; j < nj; ++j) nn[j] = sn[j];", NORM),

@@ -13,13 +13,28 @@ from bruteforce import normalize_bf
 from paper_1710_08774_amd import inputs
 
 
+@pytest.mark.parametrize("periodic", [True, False])
 @pytest.mark.parametrize("shape", [(1, 1, 5), (3, 4, 6), (2, 3, 1), (4, 2, 9)])
-def test_normalize_bruteforce(shape):
+def test_normalize_bruteforce(shape, periodic):
     u = inputs.rng_for(sum(shape)).random(shape)
-    out, n = oracle.normalize(u, 0.7, norms=True)
-    ref, nref = normalize_bf(u.tolist(), 0.7)
+    out, n = oracle.normalize(u, 0.7, norms=True, periodic=periodic)
+    ref, nref = normalize_bf(u.tolist(), 0.7, periodic=periodic)
     assert np.allclose(out, np.array(ref), rtol=1e-14, atol=1e-15)
     assert np.allclose(n, nref, rtol=1e-14, atol=0)
+
+
+def test_normalize_transmissive_closed_form():
+    """Transmissive row end: the flux telescopes, sum_i f = u(ni-1) - u(0),
+    and a linear ramp u = a i has f = a except the last cell (0), so the
+    row norm is |a| sqrt(ni - 1) per field."""
+    ni = 17
+    a = np.array([0.5, -2.0])
+    u = a[:, None, None] * np.arange(ni)[None, None, :] + np.zeros((2, 3, ni))
+    out, n = oracle.normalize(u, 1.0, norms=True, periodic=False)
+    assert np.allclose(n, math.sqrt((a ** 2).sum() * (ni - 1)), rtol=1e-14)
+    d = u - out
+    assert np.allclose(d[:, :, -1], 0.0, atol=0) and np.allclose(d.sum(axis=2) * n[None, :],
+                                                                (u[:, :, -1] - u[:, :, 0]), rtol=1e-13)
 
 
 @pytest.mark.parametrize("k", [1, 3, 7])
