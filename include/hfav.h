@@ -225,7 +225,15 @@ typedef struct {
                        4 waves per SIMD, 2 at least 5, 3 LDS-ring strip
                        kernel (y: block = 64 columns x 2, 4 or 8 rows).
                        HDIFF: row prefetch depth 1 -> 1, 2 -> 2, 4 -> 8,
-                       otherwise 4.  LAP7_CHAIN and STAR_CHAIN: tile shape. */
+                       otherwise 4; + 8 DPP lane exchange; + 16
+                       non-temporal output stores.  LAP7_CHAIN: tile shape
+                       (1-5 plane rings, 10-14 z windows in registers);
+                       + 32 non-temporal output stores.  STAR_CHAIN: tile
+                       shape.
+                       NORM: 0 row in registers (block * seg >= the row,
+                       fields * seg <= 32), 1 two streamed sweeps (block
+                       64, 128 or 256, any row), 2 and 3 as 0 with
+                       non-temporal stores, or loads and stores. */
     int xcd;        /* workgroup order over the 8 XCDs: 0 = hardware order,
                        G > 0 = runs of G consecutive tiles per XCD,
                        -1 = one contiguous range of tiles per XCD */

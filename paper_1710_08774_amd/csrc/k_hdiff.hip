@@ -32,7 +32,7 @@ __device__ __forceinline__ int pwrap(int i, int n) {
     return i < 0 ? i + n : i;
 }
 
-template <class T, int B, int P>
+template <class T, int B, int P, bool NT>
 __global__ __launch_bounds__(B) void hdiff_kernel(HArgs<T> a) {
     constexpr int W = B + 4;              // row slot: columns i0-2 .. i0+B+1
     __shared__ T ring[4][W];
@@ -104,7 +104,7 @@ __global__ __launch_bounds__(B) void hdiff_kernel(HArgs<T> a) {
             const T fx0 = hdiff_flux(lb, lc, u, L(j, 1));
             const T fxm = hdiff_flux(la, lb, L(j, -1), u);
             const T fy0 = hdiff_flux(lb, nb, u, L(j + 1, 0));
-            if (i0 + t < ni) oplane[(size_t)j * ni + i0 + t] = hdiff_out(u, fx0, fxm, fy0, fym, a.coeff);
+            if (i0 + t < ni) store_out<NT>(oplane + (size_t)j * ni + i0 + t, hdiff_out(u, fx0, fxm, fy0, fym, a.coeff));
             fym = fy0;
             la = na; lb = nb; lc = nc;
             // no second barrier: the next write goes to row j-1's slot, which
@@ -142,7 +142,7 @@ __device__ __forceinline__ float lane_shift(float v) {
     return __int_as_float(LEFT ? dpp_from_left(b) : dpp_from_right(b));
 }
 
-template <class T, int B, int P>
+template <class T, int B, int P, bool NT>
 __global__ __launch_bounds__(B) void hdiff_dpp_kernel(HArgs<T> a) {
     constexpr int W = B + 4;
     __shared__ T ring[4][W];
@@ -216,7 +216,7 @@ __global__ __launch_bounds__(B) void hdiff_dpp_kernel(HArgs<T> a) {
             const T fx0 = hdiff_flux(lb, lc, u0, ue0);
             const T fxm = hdiff_flux(la, lb, uw0, u0);
             const T fy0 = hdiff_flux(lb, nb, u0, u1);
-            if (i0 + t < ni) oplane[(size_t)j * ni + i0 + t] = hdiff_out(u0, fx0, fxm, fy0, fym, a.coeff);
+            if (i0 + t < ni) store_out<NT>(oplane + (size_t)j * ni + i0 + t, hdiff_out(u0, fx0, fxm, fy0, fym, a.coeff));
             fym = fy0;
             la = na; lb = nb; lc = nc;
             uw0 = uw1; ue0 = ue1;
@@ -236,16 +236,20 @@ static hipError_t hdiff_dispatch(const HdiffLaunch &L, hipStream_t s) {
     a.xcd = L.cfg.xcd;
     int B = L.cfg.block;
     if (B != 64 && B != 128 && B != 256 && B != 512) B = 256;
-    // variant: bit 3 selects the DPP kernel; the low bits give the prefetch
-    // depth (rows in flight per workgroup) 1 -> 1, 2 -> 2, 4 -> 8, else 4
+    // variant: bit 4 makes the output stores non-temporal, bit 3 selects
+    // the DPP kernel; the low bits give the prefetch depth (rows in flight
+    // per workgroup) 1 -> 1, 2 -> 2, 4 -> 8, else 4
     const bool dpp = (L.cfg.variant & 8) != 0;
+    const bool nt = (L.cfg.variant & 16) != 0;
     const int pv = L.cfg.variant & 7;
     const int P = pv == 1 ? 1 : pv == 2 ? 2 : pv == 4 ? 8 : 4;
     dim3 grid(((L.ni + B - 1) / B) * ((L.nj + a.seg - 1) / a.seg) * L.nk);
-#define HD_LAUNCH(BB, PP)                                                                        \
-    do {                                                                                         \
-        if (dpp) hipLaunchKernelGGL((hdiff_dpp_kernel<T, BB, PP>), grid, dim3(BB), 0, s, a);    \
-        else hipLaunchKernelGGL((hdiff_kernel<T, BB, PP>), grid, dim3(BB), 0, s, a);            \
+#define HD_LAUNCH(BB, PP)                                                                             \
+    do {                                                                                              \
+        if (dpp && nt) hipLaunchKernelGGL((hdiff_dpp_kernel<T, BB, PP, true>), grid, dim3(BB), 0, s, a); \
+        else if (dpp) hipLaunchKernelGGL((hdiff_dpp_kernel<T, BB, PP, false>), grid, dim3(BB), 0, s, a); \
+        else if (nt) hipLaunchKernelGGL((hdiff_kernel<T, BB, PP, true>), grid, dim3(BB), 0, s, a);       \
+        else hipLaunchKernelGGL((hdiff_kernel<T, BB, PP, false>), grid, dim3(BB), 0, s, a);              \
     } while (0)
 #define HD_P(BB)                               \
     switch (P) {                               \

@@ -31,7 +31,7 @@ __device__ __forceinline__ int w3(int i, int n) {
     return i < 0 ? i + n : i;
 }
 
-template <class T, int TX, int TY, int P>
+template <class T, int TX, int TY, int P, bool NTS>
 __global__ __launch_bounds__(TX * TY) void lap7_chain_kernel(BArgs<T> a) {
     constexpr int NT = TX * TY;
     constexpr int UX = TX + 4, UY = TY + 4;     // u tile with halo 2
@@ -121,7 +121,7 @@ __global__ __launch_bounds__(TX * TY) void lap7_chain_kernel(BArgs<T> a) {
             const T lc = l0[hy][hx];
             const T lap2 = lap7(lc, l0[hy][hx + 1], l0[hy][hx - 1], l0[hy + 1][hx], l0[hy - 1][hx],
                                 sl[(k + 1) & 1][hy][hx], lm);
-            if (own) a.out[(size_t)k * plane + (size_t)gy * nx + gx] = axpy(su[k & 3][ty + 2][tx + 2], lap2, a.alpha);
+            if (own) store_out<NTS>(a.out + (size_t)k * plane + (size_t)gy * nx + gx, axpy(su[k & 3][ty + 2][tx + 2], lap2, a.alpha));
             lm = lc;
         }
     }
@@ -136,7 +136,7 @@ __global__ __launch_bounds__(TX * TY) void lap7_chain_kernel(BArgs<T> a) {
 // Lane t owns point t; the points past NT are dealt out to the waves in
 // equal contiguous runs, so every wave carries the same load between
 // barriers and its accesses stay coalesced.
-template <class T, int TX, int TY, int P>
+template <class T, int TX, int TY, int P, bool NTS>
 __global__ __launch_bounds__(TX * TY) void lap7_reg_kernel(BArgs<T> a) {
     constexpr int NT = TX * TY;
     constexpr int UX = TX + 4, UY = TY + 4, NU = UX * UY;
@@ -251,7 +251,7 @@ __global__ __launch_bounds__(TX * TY) void lap7_reg_kernel(BArgs<T> a) {
             T *out = a.out + (size_t)k * plane;
 #pragma unroll
             for (int m = 0; m < M; ++m)
-                if (oo[m]) out[obase[m]] = axpy(ua[m], lap_at(slk, m, lb[m], lc[m], la[m]), a.alpha);
+                if (oo[m]) store_out<NTS>(out + obase[m], axpy(ua[m], lap_at(slk, m, lb[m], lc[m], la[m]), a.alpha));
             // rotate the z windows; the prefetched plane k+3 enters
 #pragma unroll
             for (int m = 0; m < M; ++m) {
@@ -273,7 +273,11 @@ static hipError_t lap7_dispatch(const Lap7ChainLaunch &L, hipStream_t s) {
     a.alpha = (T)L.alpha;
     a.xcd = L.cfg.xcd;
     int tx = 64, ty = 4;
-    switch (L.cfg.variant) {
+    // variant: tile shape and kernel in the low 5 bits; bit 5 makes the
+    // output stores non-temporal
+    const int var = L.cfg.variant & 31;
+    const bool nt = (L.cfg.variant & 32) != 0;
+    switch (var) {
     case 1: tx = 32; ty = 8; break;
     case 2: tx = 64; ty = 8; break;
     case 3: tx = 128; ty = 2; break;
@@ -288,21 +292,29 @@ static hipError_t lap7_dispatch(const Lap7ChainLaunch &L, hipStream_t s) {
     // tile_y selects the prefetch depth (planes in flight): 1, 2 or 4
     const int P = L.cfg.tile_y == 1 ? 1 : L.cfg.tile_y == 4 ? 4 : 2;
     dim3 grid(((L.nx + tx - 1) / tx) * ((L.ny + ty - 1) / ty) * ((L.nz + a.seg - 1) / a.seg));
-#define B7(TX_, TY_, PP) hipLaunchKernelGGL((lap7_chain_kernel<T, TX_, TY_, PP>), grid, dim3(TX_ * TY_), 0, s, a)
+#define B7(TX_, TY_, PP)                                                                                   \
+    do {                                                                                                   \
+        if (nt) hipLaunchKernelGGL((lap7_chain_kernel<T, TX_, TY_, PP, true>), grid, dim3(TX_ * TY_), 0, s, a); \
+        else hipLaunchKernelGGL((lap7_chain_kernel<T, TX_, TY_, PP, false>), grid, dim3(TX_ * TY_), 0, s, a);   \
+    } while (0)
 #define B7P(TX_, TY_)                 \
     switch (P) {                      \
     case 1: B7(TX_, TY_, 1); break;   \
     case 4: B7(TX_, TY_, 4); break;   \
     default: B7(TX_, TY_, 2); break;  \
     }
-#define R7(TX_, TY_, PP) hipLaunchKernelGGL((lap7_reg_kernel<T, TX_, TY_, PP>), grid, dim3(TX_ * TY_), 0, s, a)
+#define R7(TX_, TY_, PP)                                                                                   \
+    do {                                                                                                   \
+        if (nt) hipLaunchKernelGGL((lap7_reg_kernel<T, TX_, TY_, PP, true>), grid, dim3(TX_ * TY_), 0, s, a);   \
+        else hipLaunchKernelGGL((lap7_reg_kernel<T, TX_, TY_, PP, false>), grid, dim3(TX_ * TY_), 0, s, a);     \
+    } while (0)
 #define R7P(TX_, TY_)                 \
     switch (P) {                      \
     case 1: R7(TX_, TY_, 1); break;   \
     case 4: R7(TX_, TY_, 4); break;   \
     default: R7(TX_, TY_, 2); break;  \
     }
-    switch (L.cfg.variant) {
+    switch (var) {
     case 1: B7P(32, 8); break;
     case 2: B7P(64, 8); break;
     case 3: B7P(128, 2); break;

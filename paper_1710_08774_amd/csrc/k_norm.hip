@@ -18,7 +18,9 @@
 // copy of every wave's first lane; the row end wraps (periodic) or repeats
 // the last cell (transmissive).  f is recomputed in the second sweep from
 // the same registers, so both sweeps see the same f bit for bit.
-// Variant 1 streams rows of any length twice (u is read twice).
+// Variant 1 streams rows of any length twice (u is read twice).  Variants
+// 2 and 3 are variant 0 with non-temporal stores (2) or non-temporal loads
+// and stores (3).
 //
 // The division runs as a multiply by 1/n, one reciprocal per row: at most
 // one rounding more than the quotient.
@@ -72,13 +74,18 @@ __device__ __forceinline__ T block_sum(T v, T *part) {
 // Row element at a 32-bit byte offset from a uniform row pointer (rows hold
 // fewer than 2^28 cells): the load takes the scalar-base + vector-offset form
 // instead of a 64-bit address per lane.
-template <class T>
+// NT: non-temporal (streaming) access, for data touched exactly once.
+template <bool NT, class T>
 __device__ __forceinline__ T row_ld(const T *row, unsigned i) {
-    return *(const T *)((const char *)row + i * (unsigned)sizeof(T));
+    const T *p = (const T *)((const char *)row + i * (unsigned)sizeof(T));
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
 }
-template <class T>
+template <bool NT, class T>
 __device__ __forceinline__ void row_st(T *row, unsigned i, T v) {
-    *(T *)((char *)row + i * (unsigned)sizeof(T)) = v;
+    T *p = (T *)((char *)row + i * (unsigned)sizeof(T));
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
 }
 
 template <class T>
@@ -86,7 +93,7 @@ __device__ __forceinline__ T flux(const NArgs<T> &a, int q, T u0, T u1) {
     return fma(a.cp[q], u1, a.c0[q] * u0);
 }
 
-template <class T, int NQ, int M>
+template <class T, int NQ, int M, int NT>
 __global__ __launch_bounds__(1024) void norm_reg_kernel(NArgs<T> a) {
     __shared__ T first[NQ][M][16];    // lane-0 value of every wave, per field and slot
     __shared__ T part[16];
@@ -108,7 +115,7 @@ __global__ __launch_bounds__(1024) void norm_reg_kernel(NArgs<T> a) {
         const int i = t + m * B;
         const unsigned ic = (unsigned)(i < ni ? i : ni - 1);
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) u[q][m] = row_ld(ur[q], ic);
+        for (int q = 0; q < NQ; ++q) u[q][m] = row_ld<(NT & 1) != 0>(ur[q], ic);
     }
     if (lane == 0) {
 #pragma unroll
@@ -169,7 +176,7 @@ __global__ __launch_bounds__(1024) void norm_reg_kernel(NArgs<T> a) {
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
                 const T f = flux(a, q, u[q][m], next(q, m));
-                row_st(orow[q], i, axpy(u[q][m], f * rn, a.alpha[q]));
+                row_st<(NT & 2) != 0>(orow[q], i, axpy(u[q][m], f * rn, a.alpha[q]));
             }
         }
         __builtin_amdgcn_sched_barrier(0);
@@ -208,32 +215,41 @@ __global__ __launch_bounds__(256) void norm_stream_kernel(NArgs<T> a) {
     }
 }
 
-template <class T, int NQ>
-hipError_t launch_q(const NArgs<T> &a, const NormLaunch &L, hipStream_t s) {
+template <class T, int NQ, int NT>
+hipError_t launch_reg(const NArgs<T> &a, const NormLaunch &L, hipStream_t s) {
     const dim3 grid((unsigned)L.nrows), blk((unsigned)L.cfg.block);
-    if (L.cfg.variant == 1) {
-        hipLaunchKernelGGL((norm_stream_kernel<T, NQ>), grid, blk, 0, s, a);
-        return hipGetLastError();
-    }
     switch (L.cfg.seg) {
-    case 1: hipLaunchKernelGGL((norm_reg_kernel<T, NQ, 1>), grid, blk, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((norm_reg_kernel<T, NQ, 2>), grid, blk, 0, s, a); break;
-    case 4: hipLaunchKernelGGL((norm_reg_kernel<T, NQ, 4>), grid, blk, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((norm_reg_kernel<T, NQ, 1, NT>), grid, blk, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((norm_reg_kernel<T, NQ, 2, NT>), grid, blk, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((norm_reg_kernel<T, NQ, 4, NT>), grid, blk, 0, s, a); break;
     case 8:
         if constexpr (NQ * 8 <= NORM_REG_BUDGET) {
-            hipLaunchKernelGGL((norm_reg_kernel<T, NQ, 8>), grid, blk, 0, s, a);
+            hipLaunchKernelGGL((norm_reg_kernel<T, NQ, 8, NT>), grid, blk, 0, s, a);
             break;
         }
         return hipErrorInvalidValue;
     case 16:
         if constexpr (NQ * 16 <= NORM_REG_BUDGET) {
-            hipLaunchKernelGGL((norm_reg_kernel<T, NQ, 16>), grid, blk, 0, s, a);
+            hipLaunchKernelGGL((norm_reg_kernel<T, NQ, 16, NT>), grid, blk, 0, s, a);
             break;
         }
         return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <class T, int NQ>
+hipError_t launch_q(const NArgs<T> &a, const NormLaunch &L, hipStream_t s) {
+    switch (L.cfg.variant) {
+    case 1:
+        hipLaunchKernelGGL((norm_stream_kernel<T, NQ>), dim3((unsigned)L.nrows), dim3((unsigned)L.cfg.block), 0,
+                           s, a);
+        return hipGetLastError();
+    case 2: return launch_reg<T, NQ, 2>(a, L, s);
+    case 3: return launch_reg<T, NQ, 3>(a, L, s);
+    default: return launch_reg<T, NQ, 0>(a, L, s);
+    }
 }
 
 template <class T>
@@ -268,14 +284,17 @@ hipError_t launch_t(const NormLaunch &L, hipStream_t s) {
 bool norm_config_ok(int nq, int ni, const hfav_config &c) {
     if (nq < 1 || nq > NORM_MAX_Q || ni < 1) return false;
     if (c.variant == 1) return c.block == 64 || c.block == 128 || c.block == 256;
-    if (c.variant != 0) return false;
+    if (c.variant != 0 && c.variant != 2 && c.variant != 3) return false;
     if (c.block < 64 || c.block > 1024 || (c.block & 63)) return false;
     if (c.seg != 1 && c.seg != 2 && c.seg != 4 && c.seg != 8 && c.seg != 16) return false;
     if (nq * c.seg > NORM_REG_BUDGET) return false;
     return (int64_t)c.block * c.seg >= ni;
 }
 
-hfav_config norm_default_config(int nq, int ni) {
+hfav_config norm_default_config(int nq, int ni, int dtype) {
+    // measured on MI355X (4 fields, rows of 1024 and 4096 cells): rows of
+    // about 256 lanes of up to 8 cells, non-temporal loads and stores in
+    // FP64, non-temporal stores in FP32
     hfav_config c{256, 1, 0, 1, 0};
     int mmax = 1;
     while (mmax < 16 && nq * mmax * 2 <= NORM_REG_BUDGET) mmax *= 2;
@@ -286,7 +305,7 @@ hfav_config norm_default_config(int nq, int ni) {
     if ((int64_t)b * m >= ni) {
         c.block = b;
         c.seg = m;
-        c.variant = 0;
+        c.variant = dtype == HFAV_F64 ? 3 : 2;
     }
     return c;
 }

@@ -83,11 +83,13 @@ struct NormLaunch {
     int nq, ni, nrows;
     int bc;                           // boundary along i
     int dtype;
-    hfav_config cfg;                  // block; seg = cells per thread (variant 0);
-                                      // variant 0 registers, 1 two streamed sweeps
+    hfav_config cfg;                  // block; seg = cells per thread (variants 0, 2, 3);
+                                      // variant 0 registers, 1 two streamed sweeps,
+                                      // 2 registers + non-temporal stores, 3 registers
+                                      // + non-temporal loads and stores
 };
 bool norm_config_ok(int nq, int ni, const hfav_config &c);
-hfav_config norm_default_config(int nq, int ni);
+hfav_config norm_default_config(int nq, int ni, int dtype);
 hipError_t launch_norm(const NormLaunch &L, hipStream_t s);
 
 // ---- unfused path: one kernel per rule over full arrays

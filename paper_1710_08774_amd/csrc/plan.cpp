@@ -782,7 +782,7 @@ int hfav_plan_impl(hfav_chain *c, const hfav_plan_opts *o, hfav_plan_info *info)
             if (!hfav::norm_config_ok(nq, o->dims[0], cfg))
                 return hfav_fail(HFAV_EUNSUP, "forced normalisation configuration does not cover the row");
         } else if (src != HFAV_CONFIG_TUNED || !hfav::norm_config_ok(nq, o->dims[0], cfg)) {
-            cfg = hfav::norm_default_config(nq, o->dims[0]);
+            cfg = hfav::norm_default_config(nq, o->dims[0], c->dtype);
             src = HFAV_CONFIG_DEFAULT;
         }
     }

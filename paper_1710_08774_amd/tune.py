@@ -52,11 +52,11 @@ def family_space(family):
     if family == "hdiff":
         for blk in (64, 128, 256, 512):
             for seg in (16, 32, 64, 128):
-                for var in (0, 1, 2, 4, 8, 10):
+                for var in (0, 1, 2, 4, 8, 10, 18):
                     for xcd in (0, -1):
                         out.append((blk, 1, seg, var, xcd))
     elif family == "lap7_chain":
-        for var in (1, 2, 5, 10, 13):
+        for var in (1, 2, 5, 10, 13, 37):
             for seg in (64, 128):
                 for depth in (2, 4):
                     for xcd in (0, 8):

@@ -72,6 +72,7 @@ def _reg_configs(nq, ni):
         for blk in (64, 128, 256, 512, 1024):
             if blk * seg >= ni:
                 out.append((blk, 1, seg, 0, 0))
+    out += [(b, t, seg, v, x) for (b, t, seg, _, x) in out for v in (2, 3)]
     return out + [(b, 1, 0, 1, 0) for b in (64, 128, 256)]
 
 

@@ -43,9 +43,10 @@ def test_hdiff_parity(shape, mode):
 
 
 @pytest.mark.parametrize("block,seg", [(64, 1), (64, 7), (128, 16), (512, 64)])
-@pytest.mark.parametrize("variant", [0, 1, 4, 8, 9, 12])
+@pytest.mark.parametrize("variant", [0, 1, 4, 8, 9, 12, 18, 26])
 def test_hdiff_tile_configs(block, seg, variant):
-    # variants 8-12: neighbours along the lane axis by DPP lane shifts
+    # variants 8-12: neighbours along the lane axis by DPP lane shifts;
+    # + 16: non-temporal output stores
     a = inputs.hdiff_input(2, 70, 200, seed=3)
     ref = oracle.hdiff(a)
     c = H.Chain(H.hdiff_spec())
@@ -292,7 +293,7 @@ def test_biharm_parity(shape, mode):
     assert np.array_equal(got, ref)
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 10, 11, 12, 13, 14])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 10, 11, 12, 13, 14, 37, 42])
 @pytest.mark.parametrize("depth,seg", [(1, 5), (4, 6), (2, 17)])
 def test_biharm_tile_variants(variant, depth, seg):
     # ragged tiles in x and y, segments that do not divide nz, every

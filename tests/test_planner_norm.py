@@ -57,11 +57,13 @@ def test_norm_row_goal_and_3d_rows():
 
 
 def test_norm_default_configs_cover_the_row():
-    for nq, ni, expect in [(4, 4096, (512, 8, 0)), (1, 4096, (256, 16, 0)), (8, 4096, (1024, 4, 0)),
-                           (4, 100, (128, 1, 0)), (4, 1, (64, 1, 0)), (4, 9000, (256, 0, 1))]:
+    for nq, ni, expect in [(4, 4096, (512, 8, 3)), (1, 4096, (256, 16, 3)), (8, 4096, (1024, 4, 3)),
+                           (4, 100, (128, 1, 3)), (4, 1, (64, 1, 3)), (4, 9000, (256, 0, 1))]:
         _, info = _plan(H.norm_spec(nq), (ni, 8))
         cfg = info.config
         assert (cfg.block, cfg.seg, cfg.variant) == expect, (nq, ni)
+    _, info = _plan(H.norm_spec(4, dtype=H.F32), (4096, 8))
+    assert (info.config.block, info.config.seg, info.config.variant) == (512, 8, 2)
 
 
 def test_norm_loop_order_with_i_outer_is_not_fused():
