@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 #include "kernels.h"
 #include "ops.h"
+#include "store.h"
 #include "xcd.h"
 
 namespace hfav {

@@ -17,14 +17,6 @@
 
 namespace hfav {
 
-// Store of a value written exactly once and not read again by this launch:
-// NT selects the non-temporal (streaming) form.
-template <bool NT, class T>
-__device__ __forceinline__ void store_out(T *p, T v) {
-    if constexpr (NT) __builtin_nontemporal_store(v, p);
-    else *p = v;
-}
-
 // ------------------------------------------------------------------ hdiff
 // COSMO horizontal diffusion (Performance, "COSMO Micro-Kernels").
 // These bandwidth-bound rules are evaluated without FMA contraction, in the
