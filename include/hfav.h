@@ -315,6 +315,28 @@ int hfav_plan(hfav_chain *chain, const hfav_plan_opts *opts, hfav_plan_info *inf
 int hfav_execute(hfav_chain *chain, const void *const *axioms, void *const *goals,
                  void *workspace, void *stream);
 
+/* Create a chain by inference from rule patterns (Implementation,
+ * "Inference").  The descriptor is that of hfav_chain_create, except that
+ * rule term names may contain pattern variables: an identifier ending in
+ * '?' (as in the paper's "q?") matches any non-empty substring with
+ * balanced parentheses, with one value per variable per rule application.
+ * Term names are expressions, e.g. a rule with input "q?" and output
+ * "laplace(q?)" derives "laplace(laplace(cell))" from the axiom "cell" in
+ * two applications.  Offsets are relative to the output point as in
+ * hfav_chain_create (the paper's j?-1, i?+1).  Axioms and goals are
+ * concrete.  Every variable of a rule must occur in each of its outputs.
+ * Working backward from the goals in order, each needed term that is not
+ * an axiom or already produced is produced by the first rule (descriptor
+ * order, then output order) that matches it and whose inputs can all be
+ * derived, trying the next on failure; cycles and derivations deeper than
+ * 64 applications fail.  The resulting concrete rules (one per
+ * application, in derivation order) are validated as by
+ * hfav_chain_create; hfav_plan_json lists each with its pattern index and
+ * binding.  Errors: EINVAL (malformed pattern, concrete axioms or goals
+ * required, too many applications), EUNSAT (a goal is not derivable), and
+ * those of hfav_chain_create.  *out is NULL on error. */
+int hfav_chain_infer(const hfav_chain_desc *patterns, hfav_chain **out);
+
 /* Release a chain (NULL is allowed). */
 void hfav_chain_destroy(hfav_chain *chain);
 

@@ -3,6 +3,7 @@
 #include <array>
 #include <cstdint>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/hfav.h"
@@ -96,6 +97,8 @@ struct hfav_chain {
     std::vector<bool> live;      // rule needed for some goal
     std::vector<int> topo;       // topological order of live rules
     std::vector<int> axioms, goals;  // term ids in declaration order
+    // inferred chains: the pattern rule and variable binding of each rule
+    std::vector<std::pair<int, std::string>> origin;
     HPlan plan;
     void *pinned = nullptr;      // pinned host copy of the plan's coefficient table
     size_t pinned_bytes = 0;

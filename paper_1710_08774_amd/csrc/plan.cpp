@@ -372,6 +372,17 @@ size_t esize(int dtype) { return dtype == HFAV_F64 ? 8 : 4; }
 
 void json_int3(std::ostringstream &o, const int *v) { o << "[" << v[0] << "," << v[1] << "," << v[2] << "]"; }
 
+// a name as a JSON string (quotes, backslashes and control characters escaped)
+std::string jstr(const std::string &s) {
+    std::string o = "\"";
+    for (char ch : s) {
+        if (ch == '"' || ch == '\\') { o += '\\'; o += ch; }
+        else if ((unsigned char)ch < 0x20) { char b[8]; snprintf(b, sizeof b, "\\u%04x", ch); o += b; }
+        else o += ch;
+    }
+    return o + "\"";
+}
+
 }  // namespace
 
 static bool star_ref_is(const hfav_chain *c, const HRef &r, int term, int di, int dj, int dk) {
@@ -880,7 +891,7 @@ int hfav_plan_impl(hfav_chain *c, const hfav_plan_opts *o, hfav_plan_info *info)
     for (int t = 0; t < nt; ++t) {
         const HTerm &T = c->terms[t];
         const HTermPlan &tp = p.terms[t];
-        js << (t ? "," : "") << "{\"name\":\"" << T.name << "\",\"kind\":" << T.kind << ",\"rank\":" << T.rank
+        js << (t ? "," : "") << "{\"name\":" << jstr(T.name) << ",\"kind\":" << T.kind << ",\"rank\":" << T.rank
            << ",\"lo\":";
         json_int3(js, tp.lo);
         js << ",\"hi\":";
@@ -908,6 +919,20 @@ int hfav_plan_impl(hfav_chain *c, const hfav_plan_opts *o, hfav_plan_info *info)
         for (size_t q = 0; q < refs.size(); ++q)
             js << (q ? "," : "") << "[" << refs[q][0] << "," << refs[q][1] << "," << refs[q][2] << "]";
         js << "]}";
+    }
+    js << "],\"rules\":[";
+    for (size_t r = 0; r < c->rules.size(); ++r) {
+        const HRule &R = c->rules[r];
+        js << (r ? "," : "") << "{\"op\":" << R.op << ",\"live\":" << (c->live[r] ? 1 : 0) << ",\"in\":[";
+        for (size_t q = 0; q < R.in.size(); ++q)
+            js << (q ? "," : "") << "[" << jstr(c->terms[R.in[q].term].name) << "," << R.in[q].off[0] << ","
+               << R.in[q].off[1] << "," << R.in[q].off[2] << "]";
+        js << "],\"out\":[";
+        for (size_t q = 0; q < R.out.size(); ++q) js << (q ? "," : "") << jstr(c->terms[R.out[q]].name);
+        js << "]";
+        if (r < c->origin.size())
+            js << ",\"pattern\":" << c->origin[r].first << ",\"binding\":" << jstr(c->origin[r].second);
+        js << "}";
     }
     js << "],\"footprint_unfused\":" << fp_un << ",\"footprint_contracted\":" << fp_con
        << ",\"max_window\":" << maxw << ",\"bytes_per_cell_fused\":" << bf

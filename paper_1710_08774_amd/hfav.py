@@ -95,7 +95,7 @@ class hfav_term_info(C.Structure):
 
 # ----------------------------------------------------------------- library
 _lib = None
-EXPORTS = ["hfav_chain_create", "hfav_plan", "hfav_execute", "hfav_chain_destroy", "hfav_last_error",
+EXPORTS = ["hfav_chain_create", "hfav_chain_infer", "hfav_plan", "hfav_execute", "hfav_chain_destroy", "hfav_last_error",
            "hfav_version", "hfav_num_terms", "hfav_plan_term", "hfav_plan_json",
            "hfav_tuning_clear", "hfav_tuning_add", "hfav_tuning_size"]
 
@@ -110,6 +110,7 @@ def lib():
                           "(there is no fallback implementation)")
     L = C.CDLL(LIB_PATH)
     L.hfav_chain_create.argtypes = [C.POINTER(hfav_chain_desc), C.POINTER(C.c_void_p)]
+    L.hfav_chain_infer.argtypes = [C.POINTER(hfav_chain_desc), C.POINTER(C.c_void_p)]
     L.hfav_plan.argtypes = [C.c_void_p, C.POINTER(hfav_plan_opts), C.POINTER(hfav_plan_info)]
     L.hfav_execute.argtypes = [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_void_p,
                                C.c_void_p]
@@ -218,11 +219,13 @@ def _ptr(x):
 class Chain:
     """A created chain handle (hfav_chain_create) with plan and execute."""
 
-    def __init__(self, spec: ChainSpec):
+    def __init__(self, spec: ChainSpec, infer: bool = False):
+        """infer=True: the spec's rules are patterns (hfav_chain_infer)."""
         self.spec = spec
         d, keep = spec.to_c()
         h = C.c_void_p()
-        _check(lib().hfav_chain_create(C.byref(d), C.byref(h)))
+        create = lib().hfav_chain_infer if infer else lib().hfav_chain_create
+        _check(create(C.byref(d), C.byref(h)))
         self._h = h
         self.info = None
 
@@ -324,6 +327,11 @@ class Chain:
 
 def chain_create(spec: ChainSpec) -> Chain:
     return Chain(spec)
+
+
+def chain_infer(spec: ChainSpec) -> Chain:
+    """Chain inferred from rule patterns (pattern variables "q?")."""
+    return Chain(spec, infer=True)
 
 
 def tuning_clear():

@@ -136,3 +136,18 @@ def test_row_axiom_broadcast_and_sqrt_of_grid():
     bad = _spec([H.Rule("SQRT", [("x", Z)], ["y"])], [("x", 0)], ["y"])
     with pytest.raises(H.HfavError):
         H.Chain(bad)
+
+
+def test_broadcast_goes_into_the_prologue():
+    """A rule over rows (rank ndim - 1) whose result a grid rule broadcasts
+    along i is fused into the prologue of the grid nest (Design,
+    "Reductions & broadcasts & splits"); a reduction's finalisation goes
+    into the epilogue (the norm root above)."""
+    spec = _spec([H.Rule("SQRT", [("r", Z)], ["n"]), H.Rule("DIV0", [("x", Z), ("n", Z)], ["y"])],
+                 [("x", 2), ("r", 1)], ["y"])
+    c, info = _plan(spec, (50, 6))
+    assert info.n_nests == 1
+    assert [info.phase_of_rule[r] for r in range(2)] == [0, 1]
+    assert c.terms()["n"]["storage"] == "register"
+    j = c.plan_json()
+    assert j["nests"][0]["prologue"] == [0] and j["nests"][0]["steady"] == [1]
