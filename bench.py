@@ -205,6 +205,43 @@ def norm_chain(reps=20, nq=4, nj=4096, ni=4096, unfused=True):
     return out
 
 
+def hdiff_in_place(reps=10, dims=(2048, 2048, 64)):
+    """Horizontal diffusion written over its input (declared alias): the
+    halo columns and rows at tile boundaries are saved by a copy kernel, the
+    fused kernel then runs in place.  Footprint: one field plus the saved
+    halos, against two fields out of place."""
+    import torch
+    from paper_1710_08774_amd import hfav as H
+
+    ni, nj, nk = dims
+    g = torch.Generator(device="cuda").manual_seed(4)
+    u = torch.rand((nk, nj, ni), dtype=torch.float64, device="cuda", generator=g)
+    c = H.Chain(H.hdiff_spec())
+    c.alias("out", "u")
+    info = c.plan(dims, mode=H.MODE_FUSED)
+    ws = torch.empty(max(1, info.workspace_bytes), dtype=torch.uint8, device="cuda")
+    c.execute([u], [u], ws)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        c.execute([u], [u], ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    cells = ni * nj * nk
+    field = cells * 8
+    out = {"dims": list(dims), "dtype": "f64", "ms": ms, "cell_updates_per_s": cells / (ms * 1e-3),
+           "compulsory_GBs": 2 * field / (ms * 1e-3) / 1e9,
+           "footprint_bytes_in_place": field + info.workspace_bytes, "footprint_bytes_out_of_place": 2 * field,
+           "halo_copy_bytes": info.workspace_bytes,
+           "config": [info.config.block, info.config.seg, info.config.variant]}
+    del u, ws
+    torch.cuda.empty_cache()
+    return out
+
+
 def hdiff_config_shape(execs=1000):
     """The horizontal-diffusion chain at 256x256x8 FP64: its 8 MiB working set
     stays in the caches and one execution is shorter than a launch, so the
@@ -341,7 +378,8 @@ def main(argv=None):
                     help="only run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--no-aux", action="store_true",
                     help="skip the bandwidth-bound chains and the FP32 hydro variant")
-    ap.add_argument("--only", choices=["hdiff", "biharm64", "biharm32", "batch", "hdiff_small", "norm"],
+    ap.add_argument("--only", choices=["hdiff", "biharm64", "biharm32", "batch", "hdiff_small", "norm",
+                                       "hdiff_in_place"],
                     default=None,
                     help="only time one bandwidth-bound chain, or the batched grids (for profiling)")
     a = ap.parse_args(argv)
@@ -369,6 +407,9 @@ def main(argv=None):
         return 0
     if a.only == "hdiff_small":
         print(json.dumps({"workload": "hdiff_256x256x8", **hdiff_config_shape()}), flush=True)
+        return 0
+    if a.only == "hdiff_in_place":
+        print(json.dumps({"workload": "hdiff_in_place_64x2048x2048", **hdiff_in_place(reps=a.steps)}), flush=True)
         return 0
     if a.only == "norm":
         print(json.dumps({"workload": "norm_4x4096x4096_f64", **norm_chain(reps=a.steps,
@@ -427,6 +468,7 @@ def main(argv=None):
         aux["batch_512_grids"] = batched_grids()
         aux["hdiff_256x256x8"] = hdiff_config_shape()
         aux["norm_4x4096x4096"] = norm_chain()
+        aux["hdiff_in_place_64x2048x2048"] = hdiff_in_place()
         line["aux"] = aux
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(U0)

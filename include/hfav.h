@@ -310,7 +310,8 @@ int hfav_plan(hfav_chain *chain, const hfav_plan_opts *opts, hfav_plan_info *inf
  * coefficient table travels with the call as an asynchronous host-to-device
  * copy into the workspace from a pinned host buffer that the first execute
  * after a plan allocates; capture such a chain only after one eager call.
- * Kernel faults surface at the caller's next synchronisation.
+ * Kernel faults surface at the caller's next synchronisation.  A goal may
+ * share an axiom's buffer only as a pair declared with hfav_chain_alias.
  * Errors: ENOPLAN, EINVAL (null pointer), EALIAS, EDEVICE. */
 int hfav_execute(hfav_chain *chain, const void *const *axioms, void *const *goals,
                  void *workspace, void *stream);
@@ -336,6 +337,24 @@ int hfav_execute(hfav_chain *chain, const void *const *axioms, void *const *goal
  * required, too many applications), EUNSAT (a goal is not derivable), and
  * those of hfav_chain_create.  *out is NULL on error. */
 int hfav_chain_infer(const hfav_chain_desc *patterns, hfav_chain **out);
+
+/* Declare that `goal` will be written over `axiom` (the same device
+ * buffer passed in both places: an in-place update).  Design, "In/out
+ * chaining": by default terminals do not alias; a declared pair lets
+ * hfav_execute accept goals[g] == axioms[a] for that pair (exactly the same
+ * pointer; any other overlap is still EALIAS).  The next hfav_plan finds
+ * which of the axiom's values a goal reads after they may have been
+ * overwritten and saves them first: nothing for the normalisation kernel
+ * (a row is on chip before it is written), the halo columns and rows at the
+ * tile and segment boundaries for the horizontal-diffusion kernel (a copy
+ * kernel into the workspace), and for the unfused path nothing when the
+ * goal's producer is the last rule to read the axiom and reads it at offset
+ * 0 only, else a copy of the whole axiom.  Other fused families fall back
+ * to the unfused path (AUTO) or fail with EUNSUP (FUSED).  The plan JSON
+ * lists each pair with the axiom's extent and the handling chosen.  The
+ * goal and the axiom must have the same nonzero rank; each at most once.
+ * Errors: EINVAL, EDUP. */
+int hfav_chain_alias(hfav_chain *chain, const char *goal, const char *axiom);
 
 /* Release a chain (NULL is allowed). */
 void hfav_chain_destroy(hfav_chain *chain);

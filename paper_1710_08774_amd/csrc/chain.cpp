@@ -296,4 +296,22 @@ hfav_chain::~hfav_chain() {
 
 extern "C" void hfav_chain_destroy(hfav_chain *c) { delete c; }
 
+extern "C" int hfav_chain_alias(hfav_chain *c, const char *goal, const char *axiom) {
+    if (!c || !goal || !axiom) return hfav_fail(HFAV_EINVAL, "null argument");
+    int g = -1, a = -1;
+    for (int t : c->goals)
+        if (c->terms[t].name == goal) g = t;
+    for (int t : c->axioms)
+        if (c->terms[t].name == axiom) a = t;
+    if (g < 0) return hfav_fail(HFAV_EINVAL, std::string("not a goal: ") + goal);
+    if (a < 0) return hfav_fail(HFAV_EINVAL, std::string("not an axiom: ") + axiom);
+    if (c->terms[g].rank != c->terms[a].rank || c->terms[a].rank == 0)
+        return hfav_fail(HFAV_EINVAL, "an alias pairs a goal and an axiom of the same nonzero rank");
+    for (const auto &pr : c->alias)
+        if (pr.first == g || pr.second == a) return hfav_fail(HFAV_EDUP, "goal or axiom already aliased");
+    c->alias.push_back({g, a});
+    c->plan.valid = false;
+    return HFAV_OK;
+}
+
 extern "C" int hfav_num_terms(const hfav_chain *c) { return c ? (int)c->terms.size() : 0; }

@@ -17,8 +17,11 @@ struct Bind {
     const void *const *ax;
     void *const *go;
     char *ws;
+    std::vector<std::pair<int, const void *>> redirect;   // axioms read from a saved copy
     const void *ptr(int t) const {
         const HTerm &T = c->terms[t];
+        for (const auto &r : redirect)
+            if (r.first == t) return r.second;
         if (T.kind == TK_AXIOM) return ax[T.axiom_slot];
         if (T.kind == TK_GOAL) return go[T.goal_slot];
         const int64_t off = c->plan.ws_off[t];
@@ -99,6 +102,9 @@ int run_fused(const hfav_chain *c, const Bind &B, hipStream_t s) {
         L.coeff = p.fam_param[0];
         L.dtype = c->dtype;
         L.cfg = p.info.config;
+        L.halo = nullptr;
+        for (size_t q = 0; q < c->alias.size(); ++q)
+            if (p.alias_handling[q] == HPlan::ALIAS_TILE_HALOS && L.in == L.out) L.halo = B.ws + p.alias_ws[q];
         return dev_err(hfav::launch_hdiff(L, s), "hdiff kernel launch");
     }
     case HFAV_FAMILY_EULER_X:
@@ -213,9 +219,21 @@ int run_fused(const hfav_chain *c, const Bind &B, hipStream_t s) {
     }
 }
 
-int run_unfused(const hfav_chain *c, const Bind &B, hipStream_t s) {
+int run_unfused(const hfav_chain *c, Bind &B, hipStream_t s) {
     const HPlan &p = c->plan;
     const int *d = p.opts.dims;
+    // in/out chaining: save an aliased axiom that a rule reads after its
+    // goal is written (or at a neighbour's offset while writing it)
+    for (size_t q = 0; q < c->alias.size(); ++q) {
+        if (p.alias_handling[q] != HPlan::ALIAS_FULL_COPY) continue;
+        const int g = c->alias[q].first, a = c->alias[q].second;
+        const void *src = B.ptr(a);
+        if (src != B.ptr(g)) continue;          // not actually in place
+        void *dst = B.ws + p.alias_ws[q];
+        int rc = dev_err(hipMemcpyAsync(dst, src, term_bytes(c, a), hipMemcpyDeviceToDevice, s), "alias copy");
+        if (rc) return rc;
+        B.redirect.push_back({a, dst});
+    }
     for (int r : p.exec_order) {
         const HRule &R = c->rules[r];
         if (R.op == HFAV_OP_STAR) {
@@ -281,16 +299,23 @@ extern "C" int hfav_execute(hfav_chain *c, const void *const *axioms, void *cons
         return hfav_fail(HFAV_ENOPLAN, "this plan needs a workspace of " + std::to_string(c->plan.ws_bytes) + " bytes");
     for (size_t g = 0; g < c->goals.size(); ++g) {
         const size_t ng = term_bytes(c, c->goals[g]);
-        for (size_t a = 0; a < c->axioms.size(); ++a)
-            if (overlap(goals[g], ng, axioms[a], term_bytes(c, c->axioms[a])))
-                return hfav_fail(HFAV_EALIAS, "goal " + c->terms[c->goals[g]].name + " overlaps axiom " +
-                                                  c->terms[c->axioms[a]].name);
+        for (size_t a = 0; a < c->axioms.size(); ++a) {
+            if (!overlap(goals[g], ng, axioms[a], term_bytes(c, c->axioms[a]))) continue;
+            // a declared in-place pair may share exactly the same buffer
+            bool declared = false;
+            for (const auto &pr : c->alias)
+                if (pr.first == c->goals[g] && pr.second == c->axioms[a]) declared = true;
+            if (declared && goals[g] == axioms[a]) continue;
+            return hfav_fail(HFAV_EALIAS, "goal " + c->terms[c->goals[g]].name + " overlaps axiom " +
+                                              c->terms[c->axioms[a]].name +
+                                              (declared ? " other than exactly" : " (declare it with hfav_chain_alias)"));
+        }
         for (size_t h = g + 1; h < c->goals.size(); ++h)
             if (overlap(goals[g], ng, goals[h], term_bytes(c, c->goals[h])))
                 return hfav_fail(HFAV_EALIAS, "goals " + c->terms[c->goals[g]].name + " and " +
                                                   c->terms[c->goals[h]].name + " overlap");
     }
-    Bind B{c, axioms, goals, (char *)workspace};
+    Bind B{c, axioms, goals, (char *)workspace, {}};
     hipStream_t s = (hipStream_t)stream;
     try {
         return c->plan.info.fused ? run_fused(c, B, s) : run_unfused(c, B, s);

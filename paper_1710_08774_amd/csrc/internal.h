@@ -81,6 +81,11 @@ struct HPlan {
     std::vector<int> scoff;                     // first coefficient of each stage
     std::vector<int> sgroups;                   // first stage of each fused group
     int64_t ws_coeff = -1;                      // workspace offset of the coefficient table
+    // in/out chaining: per declared alias (goal, axiom) how the plan keeps
+    // it correct, and where the saved input values live in the workspace
+    enum { ALIAS_SAFE = 0, ALIAS_TILE_HALOS = 1, ALIAS_FULL_COPY = 2, ALIAS_ROWS_ON_CHIP = 3 };
+    std::vector<int> alias_handling;
+    std::vector<int64_t> alias_ws;              // workspace offset of the saved values, -1
     // batched plans: per-grid sizes, y-pass segment lengths and offsets
     bool batch = false;
     std::vector<int> bnx, bny, bseg;
@@ -97,6 +102,8 @@ struct hfav_chain {
     std::vector<bool> live;      // rule needed for some goal
     std::vector<int> topo;       // topological order of live rules
     std::vector<int> axioms, goals;  // term ids in declaration order
+    // declared in/out aliases: (goal term, axiom term) pairs sharing storage
+    std::vector<std::pair<int, int>> alias;
     // inferred chains: the pattern rule and variable binding of each rule
     std::vector<std::pair<int, std::string>> origin;
     HPlan plan;

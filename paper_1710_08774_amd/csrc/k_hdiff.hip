@@ -12,6 +12,7 @@
 // exchanged.  One barrier per row.  Row loads are software-pipelined P rows
 // ahead through registers so that enough bytes are in flight per CU to cover
 // HBM latency.
+#include <algorithm>
 #include <hip/hip_runtime.h>
 #include "kernels.h"
 #include "ops.h"
@@ -26,6 +27,10 @@ struct HArgs {
     T *out;
     int ni, nj, nk, seg, xcd;
     T coeff;
+    // in-place: original values of the columns i0-2 .. i0+1 at every x-tile
+    // boundary i0 (xb[((k*nj + j)*ntx + tile)*4 + c]) and of the rows
+    // j0-2 .. j0+1 at every row-segment start j0 (yb[((k*nsg + s)*4 + r)*ni + i])
+    const T *xb, *yb;
 };
 
 __device__ __forceinline__ int pwrap(int i, int n) {
@@ -33,7 +38,35 @@ __device__ __forceinline__ int pwrap(int i, int n) {
     return i < 0 ? i + n : i;
 }
 
-template <class T, int B, int P, bool NT>
+// In/out chaining (Design, "In/out chaining"): out may alias in.  Within a
+// tile every input row is fetched before the tile writes it and rows j-2 ..
+// j+1 stay in the LDS ring (the rolling input buffer), so only values that
+// another tile reads are at risk: the 2-wide halo columns at each x-tile
+// boundary and the 2 halo rows at each segment boundary.  A copy kernel
+// saves them before the fused kernel runs; with IP the fused kernel reads
+// every value outside its own tile from those copies.
+template <class T>
+__global__ __launch_bounds__(256) void hdiff_halo_copy_kernel(HArgs<T> a, int B) {
+    const int ni = a.ni, nj = a.nj, nk = a.nk;
+    const int ntx = (ni + B - 1) / B, nsg = (nj + a.seg - 1) / a.seg;
+    T *xb = const_cast<T *>(a.xb), *yb = const_cast<T *>(a.yb);
+    const size_t nx = (size_t)nk * nj * ntx * 4, ny = (size_t)nk * nsg * 4 * ni;
+    for (size_t q = (size_t)blockIdx.x * 256 + threadIdx.x; q < nx + ny; q += (size_t)gridDim.x * 256) {
+        if (q < nx) {
+            const int c = (int)(q & 3), t = (int)((q >> 2) % ntx);
+            const size_t kj = (q >> 2) / ntx;                         // k*nj + j
+            xb[q] = a.in[kj * ni + pwrap(t * B - 2 + c, ni)];
+        } else {
+            const size_t r = q - nx;
+            const int i = (int)(r % ni), row = (int)((r / ni) & 3);
+            const size_t ks = (r / ni) >> 2;                          // k*nsg + s
+            const int k = (int)(ks / nsg), sg = (int)(ks % nsg);
+            yb[r] = a.in[((size_t)k * nj + pwrap(sg * a.seg - 2 + row, nj)) * ni + i];
+        }
+    }
+}
+
+template <class T, int B, int P, bool NT, bool IP = false>
 __global__ __launch_bounds__(B) void hdiff_kernel(HArgs<T> a) {
     constexpr int W = B + 4;              // row slot: columns i0-2 .. i0+B+1
     __shared__ T ring[4][W];
@@ -56,6 +89,26 @@ __global__ __launch_bounds__(B) void hdiff_kernel(HArgs<T> a) {
     const bool halo = t < 4;
 
     auto fetch = [&](int j, T &v, T &h) {
+        if constexpr (IP) {
+            if (j < j0 || j >= j1) {        // another segment's row: its saved copy
+                const int sg = j < j0 ? tile / ntx % nsg : (tile / ntx % nsg + 1) % nsg;
+                const int row = j < j0 ? j - j0 + 2 : j - j1 + 2;
+                const T *r = a.yb + ((size_t)k * nsg + sg) * 4 * ni + (size_t)row * ni;
+                v = r[col];
+                if (halo) h = r[hcol];
+                return;
+            }
+            // own row: own columns from the field, the rest from the saved
+            // boundary columns (left halo: this tile's boundary; right halo
+            // and lanes past the row end: the next boundary, wrapped)
+            const int tx = tile % ntx;
+            const T *xr = a.xb + ((size_t)k * nj + j) * ntx * 4;
+            const T *xl = xr + (size_t)tx * 4, *xn = xr + (size_t)((tx + 1) % ntx) * 4;
+            const int w = i0 + t - ni;      // >= 0: past the row end, wrapped to column w
+            v = w < 0 ? plane[(size_t)j * ni + i0 + t] : xn[2 + (w < 2 ? w : 1)];
+            if (halo) h = t < 2 ? xl[t] : xn[2 + (t - 2)];
+            return;
+        }
         const T *r = plane + (size_t)pwrap(j, nj) * ni;
         v = r[col];
         if (halo) h = r[hcol];
@@ -143,7 +196,7 @@ __device__ __forceinline__ float lane_shift(float v) {
     return __int_as_float(LEFT ? dpp_from_left(b) : dpp_from_right(b));
 }
 
-template <class T, int B, int P, bool NT>
+template <class T, int B, int P, bool NT, bool IP = false>
 __global__ __launch_bounds__(B) void hdiff_dpp_kernel(HArgs<T> a) {
     constexpr int W = B + 4;
     __shared__ T ring[4][W];
@@ -162,6 +215,26 @@ __global__ __launch_bounds__(B) void hdiff_dpp_kernel(HArgs<T> a) {
     const int hcol = pwrap(i0 - 2 + hs, ni);
     const bool halo = t < 4;
     auto fetch = [&](int j, T &v, T &h) {
+        if constexpr (IP) {
+            if (j < j0 || j >= j1) {        // another segment's row: its saved copy
+                const int sg = j < j0 ? tile / ntx % nsg : (tile / ntx % nsg + 1) % nsg;
+                const int row = j < j0 ? j - j0 + 2 : j - j1 + 2;
+                const T *r = a.yb + ((size_t)k * nsg + sg) * 4 * ni + (size_t)row * ni;
+                v = r[col];
+                if (halo) h = r[hcol];
+                return;
+            }
+            // own row: own columns from the field, the rest from the saved
+            // boundary columns (left halo: this tile's boundary; right halo
+            // and lanes past the row end: the next boundary, wrapped)
+            const int tx = tile % ntx;
+            const T *xr = a.xb + ((size_t)k * nj + j) * ntx * 4;
+            const T *xl = xr + (size_t)tx * 4, *xn = xr + (size_t)((tx + 1) % ntx) * 4;
+            const int w = i0 + t - ni;      // >= 0: past the row end, wrapped to column w
+            v = w < 0 ? plane[(size_t)j * ni + i0 + t] : xn[2 + (w < 2 ? w : 1)];
+            if (halo) h = t < 2 ? xl[t] : xn[2 + (t - 2)];
+            return;
+        }
         const T *r = plane + (size_t)pwrap(j, nj) * ni;
         v = r[col];
         if (halo) h = r[hcol];
@@ -226,6 +299,18 @@ __global__ __launch_bounds__(B) void hdiff_dpp_kernel(HArgs<T> a) {
     }
 }
 
+static int hdiff_block(const hfav_config &c) {
+    return (c.block == 64 || c.block == 128 || c.block == 256 || c.block == 512) ? c.block : 256;
+}
+
+size_t hdiff_inplace_bytes(int ni, int nj, int nk, int dtype, const hfav_config &cfg) {
+    const int B = hdiff_block(cfg), seg = cfg.seg > 0 ? cfg.seg : 32;
+    const size_t ntx = (ni + B - 1) / B, nsg = (nj + seg - 1) / seg;
+    const size_t es = dtype == HFAV_F64 ? 8 : 4;
+    const size_t xbytes = ((size_t)nk * nj * ntx * 4 * es + 255) / 256 * 256;
+    return xbytes + (size_t)nk * nsg * 4 * ni * es;
+}
+
 template <class T>
 static hipError_t hdiff_dispatch(const HdiffLaunch &L, hipStream_t s) {
     HArgs<T> a;
@@ -235,8 +320,41 @@ static hipError_t hdiff_dispatch(const HdiffLaunch &L, hipStream_t s) {
     a.seg = L.cfg.seg > 0 ? L.cfg.seg : 32;
     a.coeff = (T)L.coeff;
     a.xcd = L.cfg.xcd;
-    int B = L.cfg.block;
-    if (B != 64 && B != 128 && B != 256 && B != 512) B = 256;
+    a.xb = a.yb = nullptr;
+    const int B = hdiff_block(L.cfg);
+    if (L.halo) {
+        // in place: save the at-risk halo columns and rows, then run the
+        // fused kernel reading them from the copies (the plain LDS-ring
+        // kernel; the DPP variant and the store hint are not used here)
+        const int ntx = (L.ni + B - 1) / B;
+        a.xb = (const T *)L.halo;
+        const size_t xbytes = ((size_t)L.nk * L.nj * ntx * 4 * sizeof(T) + 255) / 256 * 256;
+        a.yb = (const T *)((const char *)L.halo + xbytes);
+        const int nsg = (L.nj + a.seg - 1) / a.seg;
+        const size_t n = (size_t)L.nk * L.nj * ntx * 4 + (size_t)L.nk * nsg * 4 * L.ni;
+        const unsigned nb = (unsigned)std::min<size_t>((n + 255) / 256, 8192);
+        hipLaunchKernelGGL((hdiff_halo_copy_kernel<T>), dim3(nb), dim3(256), 0, s, a, B);
+        const int pv = L.cfg.variant & 7;
+        const int P = pv == 1 ? 1 : pv == 2 ? 2 : pv == 4 ? 8 : 4;
+        dim3 grid(((L.ni + B - 1) / B) * nsg * L.nk);
+#define HI_LAUNCH(BB, PP) hipLaunchKernelGGL((hdiff_kernel<T, BB, PP, false, true>), grid, dim3(BB), 0, s, a)
+#define HI_P(BB)                               \
+    switch (P) {                               \
+    case 1: HI_LAUNCH(BB, 1); break;           \
+    case 2: HI_LAUNCH(BB, 2); break;           \
+    case 8: HI_LAUNCH(BB, 8); break;           \
+    default: HI_LAUNCH(BB, 4); break;          \
+    }
+        switch (B) {
+        case 64: HI_P(64); break;
+        case 128: HI_P(128); break;
+        case 512: HI_P(512); break;
+        default: HI_P(256); break;
+        }
+#undef HI_P
+#undef HI_LAUNCH
+        return hipGetLastError();
+    }
     // variant: bit 4 makes the output stores non-temporal, bit 3 selects
     // the DPP kernel; the low bits give the prefetch depth (rows in flight
     // per workgroup) 1 -> 1, 2 -> 2, 4 -> 8, else 4

@@ -60,8 +60,15 @@ struct HdiffLaunch {
     double coeff;
     int dtype;
     hfav_config cfg;
+    // in-place execution (out == in): device scratch for the copies of the
+    // at-risk halo columns and rows, hdiff_inplace_bytes() long; null
+    // otherwise
+    void *halo;
 };
 hipError_t launch_hdiff(const HdiffLaunch &L, hipStream_t s);
+// bytes of the halo copies an in-place hdiff launch needs at this
+// configuration (4 columns per x-tile boundary, 4 rows per row segment)
+size_t hdiff_inplace_bytes(int ni, int nj, int nk, int dtype, const hfav_config &cfg);
 
 struct Lap7ChainLaunch {
     const void *in;

@@ -817,6 +817,39 @@ int hfav_plan_impl(hfav_chain *c, const hfav_plan_opts *o, hfav_plan_info *info)
         }
     }
 
+    // ---- in/out chaining (Design, "In/out chaining"): for each declared
+    // alias, the axiom's values that a goal reads after the goal may have
+    // overwritten them are saved first.  The axiom's Minkowski extent holds
+    // the offsets every goal reads it at.
+    //  * NORM: a workgroup holds its whole row on chip before writing it:
+    //    nothing to save (the two-pass streamed variant would re-read u);
+    //  * HDIFF: only the 2-wide halo columns and rows at tile and segment
+    //    boundaries are at risk (the LDS ring is the rolling input buffer):
+    //    saved by a copy kernel;
+    //  * other fused families: not built; AUTO falls back to unfused;
+    //  * unfused: safe when the goal's producer is the last rule to read the
+    //    axiom and reads it at offset 0 only; otherwise the whole axiom is
+    //    copied and every rule reads the copy.
+    p.alias_handling.assign(c->alias.size(), HPlan::ALIAS_SAFE);
+    p.alias_ws.assign(c->alias.size(), -1);
+    if (!c->alias.empty() && fused) {
+        const bool norm_ok = p.family == HFAV_FAMILY_NORM && cfg.variant != 1;
+        const bool hdiff_ok = p.family == HFAV_FAMILY_HDIFF;
+        if (!norm_ok && !hdiff_ok) {
+            if (o->mode == HFAV_MODE_FUSED)
+                return hfav_fail(HFAV_EUNSUP, "in-place execution of this fused kernel family is not built "
+                                              "(normalisation with the row on chip, horizontal diffusion)");
+            fused = false;
+        }
+        // in place, wider tiles and longer segments mean fewer boundaries
+        // whose halos must be saved (measured at 64 x 2048^2 FP64: 512-wide
+        // tiles and 128-row segments halve the saved bytes and the copy time)
+        if (hdiff_ok && src == HFAV_CONFIG_DEFAULT) {
+            if (o->dims[0] >= 2048) cfg.block = 512;
+            if (o->dims[1] >= 1024 && cfg.seg < 128) cfg.seg = 128;
+        }
+    }
+
     // ---- workspace layout
     p.ws_off.assign(nt, -1);
     p.ws_bytes = 0;
@@ -841,6 +874,38 @@ int hfav_plan_impl(hfav_chain *c, const hfav_plan_opts *o, hfav_plan_info *info)
         }
     }
     p.exec_order = c->topo;
+    for (size_t q = 0; q < c->alias.size(); ++q) {
+        const int g = c->alias[q].first, a = c->alias[q].second;
+        if (fused) {
+            if (p.family == HFAV_FAMILY_NORM) {
+                p.alias_handling[q] = HPlan::ALIAS_ROWS_ON_CHIP;
+            } else {                    // HDIFF: one halo-copy area serves the pair
+                p.alias_handling[q] = HPlan::ALIAS_TILE_HALOS;
+                p.alias_ws[q] = (int64_t)p.ws_bytes;
+                p.ws_bytes += (hfav::hdiff_inplace_bytes(o->dims[0], o->dims[1], o->dims[2], c->dtype, cfg) + 255) /
+                              256 * 256;
+            }
+            continue;
+        }
+        const int pg = c->terms[g].producer;
+        int last = -1;
+        bool off0 = true;
+        for (size_t pos = 0; pos < p.exec_order.size(); ++pos) {
+            const HRule &R = c->rules[p.exec_order[pos]];
+            for (const HRef &ref : R.in)
+                if (ref.term == a) {
+                    last = (int)pos;
+                    if (p.exec_order[pos] == pg && (ref.off[0] || ref.off[1] || ref.off[2])) off0 = false;
+                }
+        }
+        const bool safe = last < 0 || (p.exec_order[last] == pg && off0);
+        if (!safe) {
+            p.alias_handling[q] = HPlan::ALIAS_FULL_COPY;
+            p.alias_ws[q] = (int64_t)p.ws_bytes;
+            const size_t b = c->terms[a].rank == nd - 1 ? (size_t)nrows * es : (size_t)ncell * es;
+            p.ws_bytes += (b + 255) / 256 * 256;
+        }
+    }
 
     // ---- info
     hfav_plan_info &I = p.info;
@@ -933,6 +998,17 @@ int hfav_plan_impl(hfav_chain *c, const hfav_plan_opts *o, hfav_plan_info *info)
         if (r < c->origin.size())
             js << ",\"pattern\":" << c->origin[r].first << ",\"binding\":" << jstr(c->origin[r].second);
         js << "}";
+    }
+    js << "],\"aliases\":[";
+    for (size_t q = 0; q < c->alias.size(); ++q) {
+        static const char *hname[] = {"safe", "tile_halo_copies", "full_copy", "rows_on_chip"};
+        const HTermPlan &tp = p.terms[c->alias[q].second];
+        js << (q ? "," : "") << "{\"goal\":" << jstr(c->terms[c->alias[q].first].name)
+           << ",\"axiom\":" << jstr(c->terms[c->alias[q].second].name) << ",\"extent_lo\":";
+        json_int3(js, tp.lo);
+        js << ",\"extent_hi\":";
+        json_int3(js, tp.hi);
+        js << ",\"handling\":\"" << hname[p.alias_handling[q]] << "\"}";
     }
     js << "],\"footprint_unfused\":" << fp_un << ",\"footprint_contracted\":" << fp_con
        << ",\"max_window\":" << maxw << ",\"bytes_per_cell_fused\":" << bf

@@ -95,7 +95,7 @@ class hfav_term_info(C.Structure):
 
 # ----------------------------------------------------------------- library
 _lib = None
-EXPORTS = ["hfav_chain_create", "hfav_chain_infer", "hfav_plan", "hfav_execute", "hfav_chain_destroy", "hfav_last_error",
+EXPORTS = ["hfav_chain_create", "hfav_chain_infer", "hfav_chain_alias", "hfav_plan", "hfav_execute", "hfav_chain_destroy", "hfav_last_error",
            "hfav_version", "hfav_num_terms", "hfav_plan_term", "hfav_plan_json",
            "hfav_tuning_clear", "hfav_tuning_add", "hfav_tuning_size"]
 
@@ -111,6 +111,7 @@ def lib():
     L = C.CDLL(LIB_PATH)
     L.hfav_chain_create.argtypes = [C.POINTER(hfav_chain_desc), C.POINTER(C.c_void_p)]
     L.hfav_chain_infer.argtypes = [C.POINTER(hfav_chain_desc), C.POINTER(C.c_void_p)]
+    L.hfav_chain_alias.argtypes = [C.c_void_p, C.c_char_p, C.c_char_p]
     L.hfav_plan.argtypes = [C.c_void_p, C.POINTER(hfav_plan_opts), C.POINTER(hfav_plan_info)]
     L.hfav_execute.argtypes = [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_void_p,
                                C.c_void_p]
@@ -234,6 +235,10 @@ class Chain:
         if h is not None and h.value and _lib is not None:
             _lib.hfav_chain_destroy(h)
             self._h = None
+
+    def alias(self, goal: str, axiom: str):
+        """Declare an in-place pair: `goal` is written over `axiom`."""
+        _check(lib().hfav_chain_alias(self._h, goal.encode(), axiom.encode()))
 
     def plan(self, dims, boundary=(BC_PERIODIC,) * 3, mode=MODE_AUTO, precision=PREC_NATIVE,
              config_source=CONFIG_DEFAULT, forced=None) -> hfav_plan_info:

@@ -1,0 +1,103 @@
+"""In/out chaining for aliased terminals (Design, "In/out chaining"):
+declared in-place pairs, the plan's analysis of which input values are at
+risk, and the execute-time aliasing rules (host only)."""
+import pytest
+
+from paper_1710_08774_amd import hfav as H
+
+Z = (0, 0, 0)
+
+
+def _aliases(c):
+    return {(a["goal"], a["axiom"]): a for a in c.plan_json()["aliases"]}
+
+
+def test_hdiff_in_place_saves_tile_halos():
+    c = H.Chain(H.hdiff_spec())
+    c.alias("out", "u")
+    info = c.plan((200, 70, 3))
+    a = _aliases(c)[("out", "u")]
+    assert info.fused and a["handling"] == "tile_halo_copies"
+    assert a["extent_lo"] == [-2, -2, 0] and a["extent_hi"] == [2, 2, 0]
+    cfg = info.config
+    ntx, nsg = -(-200 // cfg.block), -(-70 // cfg.seg)
+    rnd = lambda b: (b + 255) // 256 * 256
+    xbytes = rnd(3 * 70 * ntx * 4 * 8)
+    assert info.workspace_bytes == rnd(xbytes + 3 * nsg * 4 * 200 * 8)
+    # the same chain without the alias needs no workspace
+    assert H.Chain(H.hdiff_spec()).plan((200, 70, 3)).workspace_bytes == 0
+
+
+def test_norm_in_place_keeps_rows_on_chip():
+    c = H.Chain(H.norm_spec(3))
+    for q in range(3):
+        c.alias(f"out{q}", f"u{q}")
+    info = c.plan((4096, 64))
+    assert info.fused and info.workspace_bytes == 0
+    assert all(a["handling"] == "rows_on_chip" for a in _aliases(c).values())
+    # rows too long for registers: the streamed variant re-reads u, so AUTO
+    # runs the unfused path, where the update is the last reader of u
+    info = c.plan((20000, 8))
+    assert not info.fused
+    assert all(a["handling"] == "safe" for a in _aliases(c).values())
+    with pytest.raises(H.HfavError) as e:
+        c.plan((20000, 8), mode=H.MODE_FUSED)
+    assert e.value.code == H.EUNSUP
+
+
+def test_families_without_in_place_fall_back_to_unfused():
+    c = H.Chain(H.biharm_spec())
+    c.alias("out", "u")
+    info = c.plan((40, 30, 20))
+    assert not info.fused
+    assert _aliases(c)[("out", "u")]["handling"] == "safe"      # AXPY(u, lap2) reads u last, at 0
+    with pytest.raises(H.HfavError) as e:
+        c.plan((40, 30, 20), mode=H.MODE_FUSED)
+    assert e.value.code == H.EUNSUP
+    cu = H.Chain(H.hdiff_spec())
+    cu.alias("out", "u")
+    assert not cu.plan((64, 32, 2), mode=H.MODE_UNFUSED).fused
+    assert _aliases(cu)[("out", "u")]["handling"] == "safe"
+
+
+def test_goal_reading_neighbours_of_its_own_axiom_needs_a_copy():
+    """out(x) = u(x+1) - u(x-1) in place: a rule that reads u at offsets
+    while writing over it gets a full copy of u in the workspace."""
+    spec = H.ChainSpec(ndim=2, axioms=[("u", 2)], goals=["out"],
+                       rules=[H.Rule("STAR", [("u", (1, 0, 0)), ("u", (-1, 0, 0))], ["out"], [1.0, -1.0])])
+    c = H.Chain(spec)
+    c.alias("out", "u")
+    info = c.plan((100, 10))
+    assert _aliases(c)[("out", "u")]["handling"] == "full_copy"
+    assert info.workspace_bytes == (100 * 10 * 8 + 255) // 256 * 256
+    # a later rule reading the axiom also forces the copy
+    spec2 = H.ChainSpec(ndim=2, axioms=[("u", 2)], goals=["a", "b"], rules=[
+        H.Rule("STAR", [("u", Z)], ["a"], [2.0]),
+        H.Rule("STAR", [("a", Z), ("u", (0, 1, 0))], ["b"], [1.0, 1.0])])
+    c2 = H.Chain(spec2)
+    c2.alias("a", "u")
+    c2.plan((16, 16))
+    assert _aliases(c2)[("a", "u")]["handling"] == "full_copy"
+
+
+def test_alias_declaration_errors_and_execute_rules():
+    c = H.Chain(H.hdiff_spec())
+    for goal, axiom, code in [("u", "u", H.EINVAL), ("out", "out", H.EINVAL), ("lap", "u", H.EINVAL)]:
+        with pytest.raises(H.HfavError) as e:
+            c.alias(goal, axiom)
+        assert e.value.code == code
+    c.alias("out", "u")
+    with pytest.raises(H.HfavError) as e:
+        c.alias("out", "u")
+    assert e.value.code == H.EDUP
+    c.plan((64, 32, 2))
+    # a partial overlap is still rejected (before anything is launched)
+    assert c.execute_status([0x100000], [0x100000 + 64], 0x900000) == H.EALIAS
+    # an undeclared chain rejects even the exact in-place call
+    d = H.Chain(H.hdiff_spec())
+    d.plan((64, 32, 2))
+    assert d.execute_status([0x100000], [0x100000]) == H.EALIAS
+    rank = H.ChainSpec(ndim=2, axioms=[("u", 2), ("r", 1)], goals=["y"],
+                       rules=[H.Rule("DIV0", [("u", Z), ("r", Z)], ["y"])])
+    with pytest.raises(H.HfavError):
+        H.Chain(rank).alias("y", "r")
