@@ -96,6 +96,32 @@ def run_gpu(mode, steps, warmup, U0, timing=True, dtype=None):
     return out
 
 
+def run_xy(steps, warmup, U0, seg=None):
+    """The hydro workload with both sweeps of a step in one kernel (the
+    x-swept state on chip; 64 compulsory bytes per cell-step instead of 128),
+    timed like the split path: host clock around `steps` steps."""
+    import torch
+    from paper_1710_08774_amd import hfav as H
+    from paper_1710_08774_amd.euler import EulerStepper
+
+    forced = (64, 1, seg, 0, 0) if seg else None
+    st = EulerStepper(NX, NY, fused_step=True, forced_xy=forced)
+    st.load(U0)
+    st.step(warmup)
+    st.load(U0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / steps
+    cells = NX * NY
+    return {"ms_per_step": ms, "cell_updates_per_s": cells / (ms * 1e-3),
+            # one read and one write of the state per step: a sweep's 64 B per cell
+            "compulsory_GBs": COMPULSORY_BYTES_PER_CELL_SWEEP * cells / (ms * 1e-3) / 1e9,
+            "config": [st.ixy.config.block, st.ixy.config.seg], "state_finite": bool(torch.isfinite(st.state()).all())}
+
+
 def time_chain(spec, dims, mode, reps, inputs_fn):
     """Average ms per hfav_execute of a single-axiom, single-goal chain, timed
     with HIP events on the stream the chain is launched on."""
@@ -376,10 +402,12 @@ def main(argv=None):
     ap.add_argument("--no-timing-events", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--xy-seg", type=int, default=0,
+                    help="with --only euler_xy: one segment length instead of the sweep over 8..64")
     ap.add_argument("--no-aux", action="store_true",
                     help="skip the bandwidth-bound chains and the FP32 hydro variant")
     ap.add_argument("--only", choices=["hdiff", "biharm64", "biharm32", "batch", "hdiff_small", "norm",
-                                       "hdiff_in_place"],
+                                       "hdiff_in_place", "euler_xy"],
                     default=None,
                     help="only time one bandwidth-bound chain, or the batched grids (for profiling)")
     a = ap.parse_args(argv)
@@ -407,6 +435,12 @@ def main(argv=None):
         return 0
     if a.only == "hdiff_small":
         print(json.dumps({"workload": "hdiff_256x256x8", **hdiff_config_shape()}), flush=True)
+        return 0
+    if a.only == "euler_xy":
+        U0 = inputs.euler_ic(NX, NY)
+        segs = (a.xy_seg,) if a.xy_seg else (8, 16, 32, 64)
+        res = {str(sg): run_xy(a.steps, a.warmup, U0, sg) for sg in segs}
+        print(json.dumps({"workload": "euler2d_xy_2048x2048", "by_segment": res}), flush=True)
         return 0
     if a.only == "hdiff_in_place":
         print(json.dumps({"workload": "hdiff_in_place_64x2048x2048", **hdiff_in_place(reps=a.steps)}), flush=True)
@@ -469,6 +503,7 @@ def main(argv=None):
         aux["hdiff_256x256x8"] = hdiff_config_shape()
         aux["norm_4x4096x4096"] = norm_chain()
         aux["hdiff_in_place_64x2048x2048"] = hdiff_in_place()
+        aux["euler_xy_one_kernel_per_step"] = run_xy(a.steps, a.warmup, U0)
         line["aux"] = aux
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(U0)

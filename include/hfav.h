@@ -153,6 +153,9 @@ typedef enum {
     HFAV_FAMILY_EULER_Y_BATCH = 7, /* tuning-table key only: the segment length
                                      (config.seg) of one grid's batched y
                                      sweep, by that grid's (nx, ny) */
+    HFAV_FAMILY_EULER_XY = 9, /* both sweeps of a time step (x then y, same dt)
+                                 in one kernel: the x-swept state stays on
+                                 chip (config.seg = rows per segment) */
     HFAV_FAMILY_NORM = 8      /* flux differences along i (STAR, two refs at
                                  di = 0 and +1) of nq <= 8 fields, SUMSQ of the
                                  fluxes, SUM_I, SQRT, one DIV0 and one AXPY per

@@ -195,6 +195,27 @@ int run_fused(const hfav_chain *c, const Bind &B, hipStream_t s) {
         return dev_err(hfav::launch_euler_smax(U, d[0] * d[1] * d[2], p.fam_param[0], out, c->dtype, s),
                        "smax launch");
     }
+    case HFAV_FAMILY_EULER_XY: {
+        hfav::EulerLaunch L;
+        for (int q = 0; q < 4; ++q) { L.in[q] = B.ptr(p.fam_in[q]); L.out[q] = B.wptr(p.fam_out[q]); }
+        L.nx = d[0]; L.ny = d[1];
+        L.bc = p.opts.boundary[0];
+        L.bcy = p.opts.boundary[1];
+        L.gamma = p.fam_param[0];
+        L.niter = (int)p.fam_param[1];
+        L.dt_src = (const double *)B.ptr(p.fam_dt_term);
+        L.dt_mode = p.fam_dt_mode == 1 ? hfav::DT_FROM_SMAX : hfav::DT_VALUE;
+        L.cfl = p.fam_cfl;
+        L.smax_out = p.fam_smax_goal >= 0 ? (double *)B.wptr(p.fam_smax_goal) : nullptr;
+        L.dtype = c->dtype;
+        L.precision = p.opts.precision;
+        L.cfg = p.info.config;
+        if (L.smax_out) {
+            int rc = dev_err(hfav::launch_fill_scalar(L.smax_out, 0.0, s), "reduction init");
+            if (rc) return rc;
+        }
+        return dev_err(hfav::launch_euler_xy(L, s), "two-sweep kernel launch");
+    }
     case HFAV_FAMILY_NORM: {
         hfav::NormLaunch L;
         memset(&L, 0, sizeof(L));

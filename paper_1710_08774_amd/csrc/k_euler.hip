@@ -19,49 +19,11 @@
 // then one atomic max per workgroup).
 #include <hip/hip_runtime.h>
 #include "kernels.h"
+#include "euler_common.h"
 #include "ops.h"
 #include "xcd.h"
 
 namespace hfav {
-
-template <class T>
-struct EArgs {
-    const T *rho, *mn, *mt, *E;
-    T *orho, *omn, *omt, *oE;
-    int nx, ny, bc;
-    double g;
-    int niter;
-    const double *dt_src;
-    int dt_mode;
-    double cfl;
-    double *smax_out;
-    int seg;
-    int xcd;
-};
-
-__device__ __forceinline__ int bwrap(int i, int n, int bc) {
-    if (bc == HFAV_BC_PERIODIC) {
-        i %= n;
-        return i < 0 ? i + n : i;
-    }
-    return i < 0 ? 0 : (i >= n ? n - 1 : i);
-}
-
-__device__ __forceinline__ double read_dt(const double *src, int mode, double cfl) {
-    double v = *src;
-    return mode == DT_VALUE ? v : cfl / v;
-}
-
-// Slopes and trace for one cell from its primitive window (m-1, m, m+1).
-template <class T>
-__device__ __forceinline__ void slope_trace(const Prim<T> &wm, const Prim<T> &w0, const Prim<T> &wp,
-                                            T nu, T *plus, T *minus) {
-    T dr = vanleer(wm.r, w0.r, wp.r);
-    T du = vanleer(wm.un, w0.un, wp.un);
-    T dv = vanleer(wm.ut, w0.ut, wp.ut);
-    T dp = vanleer(wm.p, w0.p, wp.p);
-    euler_trace(w0, dr, du, dv, dp, nu, plus, minus);
-}
 
 // One grid (or one grid of a batch) as seen by a sweep body.
 template <class T>
@@ -211,23 +173,6 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(WPE))) void e
 }
 
 // ------------------------------------------------------------------ y pass
-template <int B>
-__device__ __forceinline__ void block_max_to(double v, double *out) {
-    __shared__ double red[B / 64];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    __syncthreads();            // red[] may still be read by a previous call
-    if (lane == 0) red[w] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double m = red[0];
-#pragma unroll
-        for (int q = 1; q < B / 64; ++q) m = fmax(m, red[q]);
-        atomic_max_nonneg(out, m);
-    }
-}
-
 // Sweep one tile (columns i0 .. i0+B-1, rows j0 .. j1-1) along y.  Each lane
 // keeps the conserved state of its last three cells in its own LDS slots
 // (read back two rows later by the update).  Returns the lane's largest

@@ -26,8 +26,13 @@ struct EulerLaunch {
     int dtype;             // hfav_dtype
     int precision;         // hfav_precision
     hfav_config cfg;
+    int bcy;               // boundary along y (both sweeps in one kernel)
 };
 hipError_t launch_euler_x(const EulerLaunch &L, hipStream_t s);
+// x sweep then y sweep of one time step in one kernel; in/out in the
+// physical frame (rho, mx, my, E), bc along x, bcy along y, cfg.seg rows per
+// segment
+hipError_t launch_euler_xy(const EulerLaunch &L, hipStream_t s);
 hipError_t launch_euler_y(const EulerLaunch &L, hipStream_t s);
 
 // Batched sweeps over many grids in packed buffers (grid g at element offset

@@ -174,29 +174,21 @@ bool match_hdiff(const hfav_chain *c, HPlan &p) {
     return true;
 }
 
-// Directionally split Godunov sweep along axis d.
-bool match_euler(const hfav_chain *c, HPlan &p, int &dir) {
-    if (c->ndim != 2) return false;
-    int rp = find_op(c, HFAV_OP_EULER_PRIM), rs = find_op(c, HFAV_OP_EULER_SLOPE);
-    int rt = find_op(c, HFAV_OP_EULER_TRACE), rr = find_op(c, HFAV_OP_EULER_RIEMANN);
-    int rf = find_op(c, HFAV_OP_EULER_FLUX), ru = find_op(c, HFAV_OP_EULER_UPDATE);
-    int rm = find_op(c, HFAV_OP_EULER_SMAX), rd = find_op(c, HFAV_OP_EULER_DT);
-    if (rp < 0 || rs < 0 || rt < 0 || rr < 0 || rf < 0 || ru < 0 || rm == -2 || rd == -2) return false;
-    size_t expect = 6 + (rm >= 0) + (rd >= 0);
-    if (c->topo.size() != expect) return false;
+// The rules of one directional Godunov sweep (prim, slope, trace, Riemann,
+// flux, update) wired as the sweep computes: the direction d from the slope
+// stencil, dt the 0-D term the trace and the update read.  The prim inputs
+// are grid terms at offset 0 (axioms or another sweep's outputs).
+bool sweep_ok(const hfav_chain *c, int rp, int rs, int rt, int rr, int rf, int ru, int &d, int &dt) {
     const HRule &P = c->rules[rp], &S = c->rules[rs], &T = c->rules[rt], &R = c->rules[rr];
     const HRule &F = c->rules[rf], &U = c->rules[ru];
-    // direction from the slope stencil
-    int d = -1;
+    d = -1;
     for (int ax = 0; ax < 2; ++ax)
         if (S.in[2].off[ax] == 1) d = ax;
     if (d < 0) return false;
     int e[3] = {0, 0, 0};
     e[d] = 1;
     for (int q = 0; q < 4; ++q)
-        if (c->terms[P.in[q].term].kind != TK_AXIOM || c->terms[P.in[q].term].rank != 2 ||
-            !ref_is(c, P.in[q], P.in[q].term, 0, 0, 0))
-            return false;
+        if (c->terms[P.in[q].term].rank != 2 || !ref_is(c, P.in[q], P.in[q].term, 0, 0, 0)) return false;
     for (int q = 0; q < 4; ++q) {
         int w = P.out[q];
         if (!(ref_is(c, S.in[3 * q], w, -e[0], -e[1], 0) && ref_is(c, S.in[3 * q + 1], w, 0, 0, 0) &&
@@ -207,7 +199,7 @@ bool match_euler(const hfav_chain *c, HPlan &p, int &dir) {
         if (!ref_is(c, T.in[q], P.out[q], 0, 0, 0)) return false;
     for (int q = 0; q < 4; ++q)
         if (!ref_is(c, T.in[5 + q], S.out[q], 0, 0, 0)) return false;
-    const int dt = T.in[9].term;
+    dt = T.in[9].term;
     for (int q = 0; q < 4; ++q) {
         if (!ref_is(c, R.in[q], T.out[q], 0, 0, 0)) return false;
         if (!ref_is(c, R.in[4 + q], T.out[4 + q], e[0], e[1], 0)) return false;
@@ -220,22 +212,47 @@ bool match_euler(const hfav_chain *c, HPlan &p, int &dir) {
     const double g = P.param[0];
     if (R.param[0] != g || F.param[0] != g) return false;
     if (R.param[1] < 0 || R.param[1] > 64 || R.param[1] != (double)(int)R.param[1]) return false;
-    // dt: an axiom, or a 0-D rule from an smax axiom
+    for (int r : {rp, rs, rt, rr, rf})
+        for (int t : c->rules[r].out)
+            if (!is_inter(c, t)) return false;
+    return true;
+}
+
+// dt of a sweep family: a 0-D axiom, or a 0-D rule cfl/smax of an axiom
+bool sweep_dt(const hfav_chain *c, HPlan &p, int dt, int rd) {
     if (rd >= 0) {
         const HRule &Dr = c->rules[rd];
         if (Dr.out[0] != dt || c->terms[Dr.in[0].term].kind != TK_AXIOM) return false;
         p.fam_dt_term = Dr.in[0].term;
         p.fam_dt_mode = 1;
         p.fam_cfl = Dr.param[0];
-    } else {
-        if (c->terms[dt].kind != TK_AXIOM) return false;
-        p.fam_dt_term = dt;
-        p.fam_dt_mode = 0;
+        return true;
     }
-    // the intermediates stay intermediates; goals are the 4 updated fields
-    for (int r : {rp, rs, rt, rr, rf})
-        for (int t : c->rules[r].out)
-            if (!is_inter(c, t)) return false;
+    if (c->terms[dt].kind != TK_AXIOM) return false;
+    p.fam_dt_term = dt;
+    p.fam_dt_mode = 0;
+    return true;
+}
+
+// Directionally split Godunov sweep along axis d.
+bool match_euler(const hfav_chain *c, HPlan &p, int &dir) {
+    if (c->ndim != 2) return false;
+    int rp = find_op(c, HFAV_OP_EULER_PRIM), rs = find_op(c, HFAV_OP_EULER_SLOPE);
+    int rt = find_op(c, HFAV_OP_EULER_TRACE), rr = find_op(c, HFAV_OP_EULER_RIEMANN);
+    int rf = find_op(c, HFAV_OP_EULER_FLUX), ru = find_op(c, HFAV_OP_EULER_UPDATE);
+    int rm = find_op(c, HFAV_OP_EULER_SMAX), rd = find_op(c, HFAV_OP_EULER_DT);
+    if (rp < 0 || rs < 0 || rt < 0 || rr < 0 || rf < 0 || ru < 0 || rm == -2 || rd == -2) return false;
+    size_t expect = 6 + (rm >= 0) + (rd >= 0);
+    if (c->topo.size() != expect) return false;
+    const HRule &P = c->rules[rp], &R = c->rules[rr], &U = c->rules[ru];
+    int d = -1, dt = -1;
+    if (!sweep_ok(c, rp, rs, rt, rr, rf, ru, d, dt)) return false;
+    for (int q = 0; q < 4; ++q)
+        if (c->terms[P.in[q].term].kind != TK_AXIOM) return false;
+    const double g = P.param[0];
+    // dt: an axiom, or a 0-D rule from an smax axiom
+    if (!sweep_dt(c, p, dt, rd)) return false;
+    // goals are the 4 updated fields
     for (int q = 0; q < 4; ++q)
         if (c->terms[U.out[q]].kind != TK_GOAL) return false;
     p.fam_smax_goal = -1;
@@ -253,6 +270,86 @@ bool match_euler(const hfav_chain *c, HPlan &p, int &dir) {
     p.fam_out = {U.out[0], U.out[1], U.out[2], U.out[3]};
     p.fam_param = {g, R.param[1]};
     dir = d;
+    return true;
+}
+
+// Both sweeps of a time step: an x sweep of the axioms (rho, mx, my, E)
+// whose updated state, in the y frame (rho, my, mx, E), feeds a y sweep with
+// the same dt, gamma and Newton count; the x-swept state stays an
+// intermediate.  Optional CFL reduction of the new state as a 0-D goal.
+bool match_euler_xy(const hfav_chain *c, HPlan &p) {
+    if (c->ndim != 2) return false;
+    static const int ops[6] = {HFAV_OP_EULER_PRIM, HFAV_OP_EULER_SLOPE, HFAV_OP_EULER_TRACE,
+                               HFAV_OP_EULER_RIEMANN, HFAV_OP_EULER_FLUX, HFAV_OP_EULER_UPDATE};
+    std::vector<int> by[6];
+    int rd = -1, rm = -1, other = 0;
+    for (int r : c->topo) {
+        const int op = c->rules[r].op;
+        int k = -1;
+        for (int q = 0; q < 6; ++q)
+            if (ops[q] == op) k = q;
+        if (k >= 0) by[k].push_back(r);
+        else if (op == HFAV_OP_EULER_DT && rd < 0) rd = r;
+        else if (op == HFAV_OP_EULER_SMAX && rm < 0) rm = r;
+        else ++other;
+    }
+    if (other) return false;
+    for (int q = 0; q < 6; ++q)
+        if (by[q].size() != 2) return false;
+    // chain each sweep's rules from its prim rule by dataflow
+    auto chain_from = [&](int rp, int *id) {
+        id[0] = rp;
+        auto find = [&](int k, int pos, int term) {
+            for (int r : by[k])
+                if (c->rules[r].in[pos].term == term) return r;
+            return -1;
+        };
+        id[1] = find(1, 1, c->rules[rp].out[0]);
+        id[2] = find(2, 0, c->rules[rp].out[0]);
+        if (id[2] < 0) return false;
+        id[3] = find(3, 0, c->rules[id[2]].out[0]);
+        if (id[3] < 0) return false;
+        id[4] = find(4, 0, c->rules[id[3]].out[0]);
+        if (id[4] < 0) return false;
+        id[5] = find(5, 4, c->rules[id[4]].out[0]);
+        return id[1] >= 0 && id[5] >= 0;
+    };
+    int X[6], Y[6];
+    int px = by[0][0], py = by[0][1];
+    if (c->terms[c->rules[px].in[0].term].kind != TK_AXIOM) std::swap(px, py);
+    if (!chain_from(px, X) || !chain_from(py, Y)) return false;
+    int dx, dy, dtx, dty;
+    if (!sweep_ok(c, X[0], X[1], X[2], X[3], X[4], X[5], dx, dtx) ||
+        !sweep_ok(c, Y[0], Y[1], Y[2], Y[3], Y[4], Y[5], dy, dty))
+        return false;
+    if (dx != 0 || dy != 1 || dtx != dty) return false;
+    const HRule &Px = c->rules[X[0]], &Ux = c->rules[X[5]], &Py = c->rules[Y[0]], &Uy = c->rules[Y[5]];
+    for (int q = 0; q < 4; ++q)
+        if (c->terms[Px.in[q].term].kind != TK_AXIOM || !is_inter(c, Ux.out[q])) return false;
+    static const int yframe[4] = {0, 2, 1, 3};
+    for (int q = 0; q < 4; ++q)
+        if (Py.in[q].term != Ux.out[yframe[q]]) return false;
+    const double g = Px.param[0];
+    if (Py.param[0] != g || c->rules[X[3]].param[1] != c->rules[Y[3]].param[1]) return false;
+    if (!sweep_dt(c, p, dtx, rd)) return false;
+    for (int q = 0; q < 4; ++q)
+        if (c->terms[Uy.out[q]].kind != TK_GOAL) return false;
+    p.fam_smax_goal = -1;
+    if (rm >= 0) {
+        const HRule &M = c->rules[rm];
+        if (M.param[0] != g || c->terms[M.out[0]].kind != TK_GOAL) return false;
+        // physical order: rho, mx, my, E
+        if (!(ref_is(c, M.in[0], Uy.out[0], 0, 0, 0) && ref_is(c, M.in[1], Uy.out[2], 0, 0, 0) &&
+              ref_is(c, M.in[2], Uy.out[1], 0, 0, 0) && ref_is(c, M.in[3], Uy.out[3], 0, 0, 0)))
+            return false;
+        p.fam_smax_goal = M.out[0];
+    }
+    if (c->goals.size() != 4u + (rm >= 0)) return false;
+    for (int ax = 0; ax < 2; ++ax)
+        if (p.opts.boundary[ax] != HFAV_BC_PERIODIC && p.opts.boundary[ax] != HFAV_BC_TRANSMISSIVE) return false;
+    p.fam_in = {Px.in[0].term, Px.in[1].term, Px.in[2].term, Px.in[3].term};
+    p.fam_out = {Uy.out[0], Uy.out[2], Uy.out[1], Uy.out[3]};
+    p.fam_param = {g, c->rules[Y[3]].param[1]};
     return true;
 }
 
@@ -754,9 +851,10 @@ int hfav_plan_impl(hfav_chain *c, const hfav_plan_opts *o, hfav_plan_info *info)
     else if (match_smax(c, p)) p.family = HFAV_FAMILY_SMAX;
     else if (match_star_chain(c, p)) p.family = HFAV_FAMILY_STAR_CHAIN;
     else if (match_norm(c, p)) p.family = HFAV_FAMILY_NORM;
+    else if (match_euler_xy(c, p)) p.family = HFAV_FAMILY_EULER_XY;
     else p.family = HFAV_FAMILY_NONE;
     if (o->precision == HFAV_PREC_F32_F64ACC && p.family != HFAV_FAMILY_EULER_X &&
-        p.family != HFAV_FAMILY_EULER_Y && o->mode == HFAV_MODE_FUSED)
+        p.family != HFAV_FAMILY_EULER_Y && p.family != HFAV_FAMILY_EULER_XY && o->mode == HFAV_MODE_FUSED)
         return hfav_fail(HFAV_EUNSUP, "F32_F64ACC is implemented for the Euler sweeps only");
 
     bool fused = false;

@@ -54,6 +54,10 @@ hfav_config hfav_default_config(int family, int dtype, const int dims[3]) {
         c.variant = 3;
         break;
     }
+    case HFAV_FAMILY_EULER_XY:  // one wave per 60 columns x 16 rows
+        c.block = 64;
+        c.seg = 16;
+        break;
     case HFAV_FAMILY_LAP7_CHAIN:
         if (cells >= 64.0 * 1024 * 1024) {      // 64 x 16 tiles, 4 planes in flight
             c.block = 1024; c.seg = 128; c.variant = 5; c.tile_y = 4;

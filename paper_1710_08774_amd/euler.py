@@ -15,9 +15,14 @@ from . import hfav as H
 
 
 class EulerStepper:
+    """fused_step=True runs each step as ONE chain (both sweeps; the
+    two-sweep kernel keeps the x-swept state on chip); otherwise one chain
+    per sweep."""
+
     def __init__(self, nx, ny, dtype=torch.float64, gamma=1.4, cfl=0.5, niter=10,
                  bc=H.BC_PERIODIC, mode=H.MODE_FUSED, precision=H.PREC_NATIVE,
-                 config_source=H.CONFIG_DEFAULT, forced_x=None, forced_y=None, device="cuda"):
+                 config_source=H.CONFIG_DEFAULT, forced_x=None, forced_y=None, device="cuda",
+                 fused_step=False, forced_xy=None):
         self.nx, self.ny = nx, ny
         self.dtype = dtype
         cd = H.F64 if dtype == torch.float64 else H.F32
@@ -34,9 +39,16 @@ class EulerStepper:
                                forced=forced_x)
         self.iy = self.cy.plan((nx, ny), (bc, bc), mode=mode, precision=precision, config_source=fy,
                                forced=forced_y)
+        self.cxy = self.ixy = None
+        if fused_step:
+            self.cxy = H.Chain(H.euler_step_spec(gamma, niter, cfl, "smax", True, cd))
+            fxy = H.CONFIG_FORCED if forced_xy is not None else config_source
+            self.ixy = self.cxy.plan((nx, ny), (bc, bc), mode=mode, precision=precision, config_source=fxy,
+                                     forced=forced_xy)
         self.U = [torch.empty((4, ny, nx), dtype=dtype, device=device) for _ in range(2)]
         self.smax = torch.zeros(2, dtype=torch.float64, device=device)
-        ws = max(self.ix.workspace_bytes, self.iy.workspace_bytes)
+        ws = max(self.ix.workspace_bytes, self.iy.workspace_bytes,
+                 self.ixy.workspace_bytes if self.ixy is not None else 0)
         self.ws = torch.empty(ws, dtype=torch.uint8, device=device) if ws else None
         self.cur = 0
         self.slot = 0
@@ -51,8 +63,12 @@ class EulerStepper:
         for _ in range(n):
             a, b = self.U[self.cur], self.U[1 - self.cur]
             s0, s1 = self.smax[self.slot], self.smax[1 - self.slot]
-            self.cx.execute([a[0], a[1], a[2], a[3], s0], [b[0], b[1], b[2], b[3]], self.ws)
-            self.cy.execute([b[0], b[1], b[2], b[3], s0], [a[0], a[1], a[2], a[3], s1], self.ws)
+            if self.cxy is not None:
+                self.cxy.execute([a[0], a[1], a[2], a[3], s0], [b[0], b[1], b[2], b[3], s1], self.ws)
+                self.cur = 1 - self.cur
+            else:
+                self.cx.execute([a[0], a[1], a[2], a[3], s0], [b[0], b[1], b[2], b[3]], self.ws)
+                self.cy.execute([b[0], b[1], b[2], b[3], s0], [a[0], a[1], a[2], a[3], s1], self.ws)
             self.slot = 1 - self.slot
 
     def sweep_x(self):

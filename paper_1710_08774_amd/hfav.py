@@ -37,7 +37,7 @@ MODE_AUTO, MODE_FUSED, MODE_UNFUSED = 0, 1, 2
 PREC_NATIVE, PREC_F32_F64ACC = 0, 1
 CONFIG_DEFAULT, CONFIG_TUNED, CONFIG_MODEL, CONFIG_FORCED = 0, 1, 2, 3
 FAMILY = {0: "none", 1: "hdiff", 2: "euler_x", 3: "euler_y", 4: "lap7_chain", 5: "star_chain", 6: "smax",
-          7: "euler_y_batch", 8: "norm"}
+          7: "euler_y_batch", 8: "norm", 9: "euler_xy"}
 STORAGE = {0: "full", 1: "register", 2: "inner", 3: "outer", 4: "scalar"}
 MAX_RULES = 64
 MAX_NESTS = 8
@@ -457,6 +457,32 @@ def euler_sweep_spec(direction, gamma=1.4, niter=10, cfl=0.5, dt_source="smax", 
                           [gamma], REDUCE_MAX))
         goals.append("smax_n")
     return ChainSpec(ndim=2, dtype=dtype, axioms=axioms, goals=goals, rules=rules)
+
+
+def euler_step_spec(gamma=1.4, niter=10, cfl=0.5, dt_source="smax", with_smax=False, dtype=F64) -> ChainSpec:
+    """One time step as ONE chain: the x sweep of (rho, mx, my, E) and the y
+    sweep of its result with the same dt; the x-swept state is an
+    intermediate (names suffixed _x), the goals are the new state.  The
+    planner fuses the two equal-rank nests (Design, "Fusing iteration
+    nests")."""
+    xs = euler_sweep_spec(0, gamma, niter, cfl, dt_source, False, dtype)
+    ys = euler_sweep_spec(1, gamma, niter, cfl, dt_source, with_smax, dtype)
+    ren_x = {g: g.replace("_n", "_x") for g in EULER_GOALS}
+    rules = []
+    for r in xs.rules:
+        outs = [ren_x.get(o, o if o == "dt" else o + "_x") for o in r.outputs]
+        ins = [(t if t in EULER_AXIOMS or t in ("dt", "smax") else ren_x.get(t, t + "_x"), off)
+               for t, off in r.inputs]
+        rules.append(Rule(r.op, ins, outs, r.params, r.reduce))
+    src = {a: ren_x[g] for a, g in zip(EULER_AXIOMS, EULER_GOALS)}      # rho -> rho_x, ...
+    for r in ys.rules:
+        if r.op == "EULER_DT":
+            continue                                                     # dt is shared
+        outs = [o if o in EULER_GOALS or o == "smax_n" else o + "_y" for o in r.outputs]
+        ins = [(src[t] if t in EULER_AXIOMS else t if t in ("dt",) or t in EULER_GOALS else t + "_y", off)
+               for t, off in r.inputs]
+        rules.append(Rule(r.op, ins, outs, r.params, r.reduce))
+    return ChainSpec(ndim=2, dtype=dtype, axioms=xs.axioms, goals=list(ys.goals), rules=rules)
 
 
 def smax_spec(gamma=1.4, dtype=F64) -> ChainSpec:

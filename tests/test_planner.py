@@ -322,3 +322,25 @@ def test_batch_segments_from_tuning_buckets():
         assert c.plan_json()["batch"]["y_seg"] == [5]
     finally:
         H.tuning_clear()
+
+
+def test_two_sweep_step_chain_fuses_into_one_nest():
+    """x sweep then y sweep as one chain: equal-rank nests fuse (Design,
+    "Fusing iteration nests"); the x-swept state is needed at rows j-2 ..
+    j+2 of the y sweep (a 5-row window), and the step's compulsory traffic
+    halves from 128 to 64 bytes per cell."""
+    c = H.Chain(H.euler_step_spec(with_smax=True))
+    info = c.plan((256, 128))
+    assert H.FAMILY[info.family] == "euler_xy" and info.fused and info.n_nests == 1
+    assert info.bytes_per_cell_fused == 64.0
+    t = c.terms()
+    for f in ("rho_x", "mx_x", "my_x", "E_x"):
+        assert (t[f]["storage"], t[f]["window_axis"], t[f]["window"]) == ("outer", 1, 5)
+    assert (info.config.block, info.config.seg) == (64, 16)
+    i32 = H.Chain(H.euler_step_spec(dtype=H.F32)).plan((64, 64), precision=H.PREC_F32_F64ACC, mode=H.MODE_FUSED)
+    assert i32.family == 9
+    # the y sweep reading another dt than the x sweep is not the fused family
+    bad = H.euler_step_spec(dt_source="dt")
+    bad.rules[-1].inputs[-1] = ("dt2", (0, 0, 0))
+    bad.axioms.append(("dt2", 0))
+    assert H.Chain(bad).plan((64, 64)).family == 0
