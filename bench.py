@@ -35,7 +35,7 @@ COMPULSORY_BYTES_PER_CELL_SWEEP = 64      # 4 FP64 fields read once, written onc
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("k_euler.hip", "ops.h"):
+    for f in ("k_euler.hip", "euler_common.h", "ops.h"):
         with open(os.path.join(ROOT, "paper_1710_08774_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
