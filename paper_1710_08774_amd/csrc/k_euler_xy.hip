@@ -21,6 +21,7 @@
 // FP64-ALU bound, not HBM bound, so this kernel trades bytes that were not
 // the bottleneck for arithmetic that is.
 #include <hip/hip_runtime.h>
+#include "dpp.h"
 #include "euler_common.h"
 #include "kernels.h"
 #include "ops.h"
@@ -31,27 +32,11 @@ namespace {
 
 constexpr int XY_W = 60;      // output columns per wave
 
-// DPP wave shifts: value of lane l - 1 (lane 0 receives 0) and of lane l + 1
-// (lane 63 receives 0)
-__device__ __forceinline__ int from_prev_i32(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false); }
-__device__ __forceinline__ int from_next_i32(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false); }
-template <bool PREV>
-__device__ __forceinline__ double shift(double v) {
-    const long long b = __double_as_longlong(v);
-    const int lo = (int)(b & 0xffffffffLL), hi = (int)(b >> 32);
-    const int rlo = PREV ? from_prev_i32(lo) : from_next_i32(lo);
-    const int rhi = PREV ? from_prev_i32(hi) : from_next_i32(hi);
-    return __longlong_as_double(((long long)rhi << 32) | (unsigned int)rlo);
-}
-template <bool PREV>
-__device__ __forceinline__ float shift(float v) {
-    return __int_as_float(PREV ? from_prev_i32(__float_as_int(v)) : from_next_i32(__float_as_int(v)));
-}
 // neighbour's value, or the lane's own at the wave edge (keeps the halo
 // lanes' arithmetic on physical states)
 template <bool PREV, class T>
 __device__ __forceinline__ T nb(T v, bool edge) {
-    const T s = shift<PREV>(v);
+    const T s = lane_shift<PREV>(v);
     return edge ? v : s;
 }
 template <bool PREV, class T>

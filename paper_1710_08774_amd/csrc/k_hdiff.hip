@@ -14,6 +14,7 @@
 // HBM latency.
 #include <algorithm>
 #include <hip/hip_runtime.h>
+#include "dpp.h"
 #include "kernels.h"
 #include "ops.h"
 #include "store.h"
@@ -176,26 +177,6 @@ __global__ __launch_bounds__(B) void hdiff_kernel(HArgs<T> a) {
 // the edges of each wave read their missing neighbour from the LDS row ring
 // (filled as in the kernel above).  The column's rows j .. j+2 stay in
 // registers.  Arithmetic is unchanged, so results are bit-identical.
-__device__ __forceinline__ int dpp_from_left(int v) {
-    return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false);    // wave_shr:1
-}
-__device__ __forceinline__ int dpp_from_right(int v) {
-    return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false);    // wave_shl:1
-}
-template <bool LEFT>
-__device__ __forceinline__ double lane_shift(double v) {
-    const long long b = __double_as_longlong(v);
-    const int lo = (int)(b & 0xffffffffLL), hi = (int)(b >> 32);
-    const int rlo = LEFT ? dpp_from_left(lo) : dpp_from_right(lo);
-    const int rhi = LEFT ? dpp_from_left(hi) : dpp_from_right(hi);
-    return __longlong_as_double(((long long)rhi << 32) | (unsigned int)rlo);
-}
-template <bool LEFT>
-__device__ __forceinline__ float lane_shift(float v) {
-    const int b = __float_as_int(v);
-    return __int_as_float(LEFT ? dpp_from_left(b) : dpp_from_right(b));
-}
-
 template <class T, int B, int P, bool NT, bool IP = false>
 __global__ __launch_bounds__(B) void hdiff_dpp_kernel(HArgs<T> a) {
     constexpr int W = B + 4;

@@ -25,6 +25,7 @@
 // The division runs as a multiply by 1/n, one reciprocal per row: at most
 // one rounding more than the quotient.
 #include <hip/hip_runtime.h>
+#include "dpp.h"
 #include "kernels.h"
 #include "ops.h"
 
@@ -40,17 +41,6 @@ struct NArgs {
     int ni;
     int periodic;
 };
-
-// value of lane l + 1 (lane 63 receives 0): DPP wave_shl by one lane
-__device__ __forceinline__ int next_lane_i32(int v) {
-    return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false);
-}
-__device__ __forceinline__ double next_lane(double v) {
-    const long long b = __double_as_longlong(v);
-    const int lo = next_lane_i32((int)(b & 0xffffffffLL)), hi = next_lane_i32((int)(b >> 32));
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-__device__ __forceinline__ float next_lane(float v) { return __int_as_float(next_lane_i32(__float_as_int(v))); }
 
 template <class T>
 __device__ __forceinline__ T wave_sum(T v) {
@@ -136,7 +126,7 @@ __global__ __launch_bounds__(1024) void norm_reg_kernel(NArgs<T> a) {
         // into a branch of its own, which splits the sweep into blocks and
         // keeps every slot's neighbour live at once
         asm volatile("" : "+v"(e), "+v"(w0));
-        const T v = next_lane(u[q][m]);
+        const T v = lane_shift<false>(u[q][m]);
         const T wrapv = a.periodic ? w0 : u[q][m];
         const int i = t + m * B;
         return i == ni - 1 ? wrapv : (lane == 63 ? e : v);

@@ -54,10 +54,18 @@ hfav_config hfav_default_config(int family, int dtype, const int dims[3]) {
         c.variant = 3;
         break;
     }
-    case HFAV_FAMILY_EULER_XY:  // one wave per 60 columns x 16 rows
+    case HFAV_FAMILY_EULER_XY: {
+        // one wave per 60 columns x seg rows: the longest segment (fewest
+        // halo rows) that still gives about 5000 waves, each XCD a
+        // contiguous range of tiles (measured at 2048^2 and 512^2)
+        const long long strips = (dims[0] + 59) / 60;
         c.block = 64;
-        c.seg = 16;
+        c.xcd = -1;
+        c.seg = 4;
+        for (int s : {16, 12, 8})
+            if (strips * ((dims[1] + s - 1) / s) >= 5000) { c.seg = s; break; }
         break;
+    }
     case HFAV_FAMILY_LAP7_CHAIN:
         if (cells >= 64.0 * 1024 * 1024) {      // 64 x 16 tiles, 4 planes in flight
             c.block = 1024; c.seg = 128; c.variant = 5; c.tile_y = 4;

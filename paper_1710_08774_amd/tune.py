@@ -42,7 +42,9 @@ def chain_dims(ch):
 
 
 # ------------------------------------------------------------------ families
-FAMILY_ID = {"hdiff": 1, "euler_x": 2, "euler_y": 3, "lap7_chain": 4, "euler_y_batch": 7}
+FAMILY_ID = {"hdiff": 1, "euler_x": 2, "euler_y": 3, "lap7_chain": 4, "euler_y_batch": 7, "norm": 8,
+             "euler_xy": 9}
+NORM_FIELDS = 4      # the normalisation family is tuned with 4 fields (the tuning key has no field count)
 DTYPE_NAME = {H.F64: "f64", H.F32: "f32"}
 
 
@@ -73,6 +75,19 @@ def family_space(family):
         for blk in (256, 512):
             for seg in (32, 64, 128):
                 out.append((blk, 1, seg, 3, 0))
+    elif family == "norm":
+        # only the configurations covering the row are feasible; the tuner
+        # skips the others
+        for blk in (64, 128, 256, 512, 1024):
+            for seg in (1, 2, 4, 8, 16):
+                for var in (0, 2, 3):
+                    out.append((blk, 1, seg, var, 0))
+        for blk in (64, 128, 256):
+            out.append((blk, 1, 0, 1, 0))
+    elif family == "euler_xy":
+        for seg in (4, 8, 12, 16, 24, 32):
+            for xcd in (0, -1):
+                out.append((64, 1, seg, 0, xcd))
     else:
         raise ValueError(f"no search space for family {family!r}")
     return out
@@ -123,6 +138,32 @@ def tune_family(family, dims, dtype=H.F64, reps=5, space=None):
         st = EulerStepper(nx, ny, dtype=tdt)
         st.load(U)
         default_ms = _event_ms(st.sweep_x if x else st.sweep_y, reps)
+    elif family == "norm":
+        ni, nrows = dims[0], dims[1]
+        g = torch.Generator(device="cuda").manual_seed(0)
+        u = torch.rand((NORM_FIELDS, nrows, ni), dtype=tdt, device="cuda", generator=g)
+        o = torch.empty_like(u)
+        c = H.Chain(H.norm_spec(NORM_FIELDS, dtype=dtype))
+        args = ([u[q] for q in range(NORM_FIELDS)], [o[q] for q in range(NORM_FIELDS)])
+        for cfg in space:
+            try:
+                c.plan((ni, nrows), mode=H.MODE_FUSED, config_source=H.CONFIG_FORCED, forced=cfg)
+            except H.HfavError:
+                continue                                  # does not cover the row
+            res.append((_event_ms(lambda: c.execute(*args), reps), tuple(cfg)))
+        c.plan((ni, nrows), mode=H.MODE_FUSED)
+        default_ms = _event_ms(lambda: c.execute(*args), reps)
+    elif family == "euler_xy":
+        from .euler import EulerStepper
+        nx, ny = dims[0], dims[1]
+        U = inputs.euler_ic(nx, ny)
+        for cfg in space:
+            st = EulerStepper(nx, ny, dtype=tdt, fused_step=True, forced_xy=cfg)
+            st.load(U)
+            res.append((_event_ms(st.step, reps), tuple(cfg)))
+        st = EulerStepper(nx, ny, dtype=tdt, fused_step=True)
+        st.load(U)
+        default_ms = _event_ms(st.step, reps)
     else:
         raise ValueError(f"no autotuner for family {family!r}")
     res.sort(key=lambda r: r[0])
@@ -137,6 +178,8 @@ DB_BUCKETS = [
     ("euler_x", H.F64, (2048, 2048, 1)), ("euler_x", H.F64, (512, 512, 1)),
     ("euler_y", H.F64, (2048, 2048, 1)), ("euler_y", H.F64, (512, 512, 1)),
     ("euler_y", H.F64, (128, 128, 1)),
+    ("norm", H.F64, (4096, 4096, 1)), ("norm", H.F64, (1024, 16384, 1)), ("norm", H.F32, (4096, 4096, 1)),
+    ("euler_xy", H.F64, (2048, 2048, 1)), ("euler_xy", H.F64, (512, 512, 1)),
 ]
 # size buckets of the batched y sweep (centres, log2-nearest assignment)
 BATCH_BUCKETS = ((128, 128, 1), (362, 362, 1), (724, 724, 1))
@@ -445,6 +488,10 @@ def main(argv=None):
     dbp = sub.add_parser("db", help="autotune the kernel families and write the tuning database")
     dbp.add_argument("--reps", type=int, default=5)
     dbp.add_argument("--out", default="gpurun_out/tuning_db.json")
+    dbp.add_argument("--families", nargs="*", default=None,
+                     help="tune only these families (default: all, plus the batch segments)")
+    dbp.add_argument("--merge", default=None,
+                     help="database whose entries of the other families are kept")
     st = sub.add_parser("study", help="train on seeded chains, report regret on held-out chains")
     st.add_argument("--train-chains", type=int, default=60)
     st.add_argument("--test-chains", type=int, default=200)
@@ -454,7 +501,15 @@ def main(argv=None):
     st.add_argument("--out", default="gpurun_out/costmodel_study.json")
     a = ap.parse_args(argv)
     if a.cmd == "db":
-        db = build_db(reps=a.reps, log=lambda m: print(m, flush=True))
+        buckets = None
+        if a.families:
+            buckets = [b for b in DB_BUCKETS if b[0] in a.families]
+        db = build_db(buckets=buckets, reps=a.reps, log=lambda m: print(m, flush=True))
+        if a.merge:
+            with open(a.merge) as f:
+                old = json.load(f)
+            tuned = set(a.families or FAMILY_ID)
+            db["entries"] = [e for e in old["entries"] if e["family"] not in tuned] + db["entries"]
         os.makedirs(os.path.dirname(a.out) or ".", exist_ok=True)
         with open(a.out, "w") as f:
             json.dump(db, f, indent=1)

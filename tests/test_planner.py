@@ -292,6 +292,23 @@ def test_family_search_spaces_plan():
         for cfg in space:
             info = c.plan(dims, mode=H.MODE_FUSED, config_source=H.CONFIG_FORCED, forced=cfg)
             assert info.fused and H.FAMILY[info.family] == fam
+    # the two-sweep family: every configuration plans
+    c = H.Chain(H.euler_step_spec())
+    for cfg in tune.family_space("euler_xy"):
+        assert c.plan((64, 48), mode=H.MODE_FUSED, config_source=H.CONFIG_FORCED, forced=cfg).family == 9
+    # the normalisation family: exactly the configurations covering the row plan
+    c = H.Chain(H.norm_spec(tune.NORM_FIELDS))
+    ok = 0
+    for cfg in tune.family_space("norm"):
+        blk, _, seg, var, _ = cfg
+        fits = var == 1 or (blk * seg >= 1000 and tune.NORM_FIELDS * seg <= 32)
+        try:
+            info = c.plan((1000, 8), mode=H.MODE_FUSED, config_source=H.CONFIG_FORCED, forced=cfg)
+            assert fits and info.family == 8
+            ok += 1
+        except H.HfavError as e:
+            assert not fits and e.code == H.EUNSUP
+    assert ok >= 9
 
 
 def test_random_star_chain_plans():
@@ -336,7 +353,9 @@ def test_two_sweep_step_chain_fuses_into_one_nest():
     t = c.terms()
     for f in ("rho_x", "mx_x", "my_x", "E_x"):
         assert (t[f]["storage"], t[f]["window_axis"], t[f]["window"]) == ("outer", 1, 5)
-    assert (info.config.block, info.config.seg) == (64, 16)
+    assert (info.config.block, info.config.seg, info.config.xcd) == (64, 4, -1)
+    big = H.Chain(H.euler_step_spec()).plan((2048, 2048))
+    assert (big.config.seg, big.config.xcd) == (12, -1)
     i32 = H.Chain(H.euler_step_spec(dtype=H.F32)).plan((64, 64), precision=H.PREC_F32_F64ACC, mode=H.MODE_FUSED)
     assert i32.family == 9
     # the y sweep reading another dt than the x sweep is not the fused family
