@@ -30,14 +30,17 @@ hfav_config hfav_default_config(int family, int dtype, const int dims[3]) {
         } else {
             c.block = 256; c.seg = 128; c.variant = 0; c.xcd = 0;
         }
-        // small grids: shorter segments, then narrower tiles, until about
-        // 2048 workgroups are in flight
+        // small grids: shorter segments (down to 4 rows), then narrower
+        // tiles, until about 2048 workgroups are in flight; short segments
+        // prefetch one row (at 256x256x8 FP64: 5.4 us per execution against
+        // 8.7 us with 16-row segments)
         auto wgs = [&](const hfav_config &k) {
             return (double)((dims[0] + k.block - 1) / k.block) * ((dims[1] + k.seg - 1) / k.seg) *
                    (dims[2] > 0 ? dims[2] : 1);
         };
-        while (wgs(c) < 2048 && c.seg > 16) c.seg /= 2;
+        while (wgs(c) < 2048 && c.seg > 4) c.seg /= 2;
         while (wgs(c) < 2048 && c.block > 64) c.block /= 2;
+        if (c.seg <= 8) c.variant = 1;
         break;
     }
     case HFAV_FAMILY_EULER_X:   // one workgroup per row, up to 4 waves

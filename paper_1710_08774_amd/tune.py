@@ -53,7 +53,7 @@ def family_space(family):
     out = []
     if family == "hdiff":
         for blk in (64, 128, 256, 512):
-            for seg in (16, 32, 64, 128):
+            for seg in (4, 8, 16, 32, 64, 128):
                 for var in (0, 1, 2, 4, 8, 10, 18):
                     for xcd in (0, -1):
                         out.append((blk, 1, seg, var, xcd))
