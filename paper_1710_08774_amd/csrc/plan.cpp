@@ -396,6 +396,8 @@ bool match_lap7_chain(const hfav_chain *c, HPlan &p) {
 bool match_norm(const hfav_chain *c, HPlan &p) {
     const int nd = c->ndim;
     if (c->order[nd - 1] != 0) return false;
+    // one workgroup per row: the row count must fit a launch
+    if ((int64_t)p.opts.dims[1] * p.opts.dims[2] >= ((int64_t)1 << 31)) return false;
     if (p.opts.boundary[0] != HFAV_BC_PERIODIC && p.opts.boundary[0] != HFAV_BC_TRANSMISSIVE) return false;
     const int rsq = find_op(c, HFAV_OP_SUMSQ), rsu = find_op(c, HFAV_OP_SUM_I), rrt = find_op(c, HFAV_OP_SQRT);
     if (rsq < 0 || rsu < 0 || rrt < 0) return false;
