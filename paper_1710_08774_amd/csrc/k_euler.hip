@@ -104,10 +104,11 @@ __device__ __forceinline__ void x_row(const EArgs<T> &a, const EView<T> &v, int 
         const int p = c0 + t;
         const bool act = p < nx;
         const int sm = slot(t - 1), s0 = slot(t), sp = slot(t + 1);
-        // stage 1: conserved state of the cell entering the window
+        // stage 1: conserved state of the cell entering the window.  The
+        // previous chunk read these primitive slots in its stage 2 (stage 3
+        // for the right end), and two barriers have passed since
         T unew[4];
         if (act) load_cell(p + 1, unew);
-        __syncthreads();      // previous chunk's reads of these slots are done
         if (act) put(sp, unew);
         __syncthreads();
         // stage 2: slopes + trace of cell p; the plus face goes to its right
@@ -317,13 +318,14 @@ __device__ __forceinline__ double strip(const EArgs<T> &a, const EView<T> &v, bo
     for (int c0 = j0; c0 <= j1; c0 += C) {
         const int p = c0 + q;
         const bool act = lact && p <= j1;
-        // stage 1: the cell entering the window
+        // stage 1: the cell entering the window.  The previous chunk read
+        // these primitive slots in its stage 2, and three barriers have
+        // passed since
         T un[4];
         if (act) {
             const size_t o = addr(p + 1);
             un[0] = v.rho[o]; un[1] = v.mn[o]; un[2] = v.mt[o]; un[3] = v.E[o];
         }
-        __syncthreads();        // the previous chunk's reads of these slots are done
         if (act) put(p + 1, euler_prim(un[0], un[1], un[2], un[3], g));
         __syncthreads();
         // stage 2: slopes and trace of cell p; the plus face goes to the

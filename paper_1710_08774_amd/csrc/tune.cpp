@@ -25,8 +25,8 @@ hfav_config hfav_default_config(int family, int dtype, const int dims[3]) {
     const double cells = (double)dims[0] * dims[1] * (dims[2] > 0 ? dims[2] : 1);
     switch (family) {
     case HFAV_FAMILY_HDIFF: {
-        if (dtype == HFAV_F64) {    // 2 rows in flight, one tile range per XCD
-            c.block = 256; c.seg = 64; c.variant = 2; c.xcd = -1;
+        if (dtype == HFAV_F64) {    // 2 rows in flight, non-temporal stores, one tile range per XCD
+            c.block = 256; c.seg = 32; c.variant = 2 + 16; c.xcd = -1;
         } else {
             c.block = 256; c.seg = 128; c.variant = 0; c.xcd = 0;
         }
@@ -49,11 +49,13 @@ hfav_config hfav_default_config(int family, int dtype, const int dims[3]) {
         break;
     case HFAV_FAMILY_EULER_Y: {
         // LDS-ring strips of 64 columns x 8 rows per chunk; segments as long
-        // as keeps about 512 eight-wave workgroups in flight
+        // as keeps about 512 eight-wave workgroups in flight, one row short
+        // of a power of two: a segment of seg rows takes seg + 1 chunk rows,
+        // so no chunk row idles (2048^2 FP64: 3% faster than 128 rows)
         int seg = 32;
         while (seg < 128 && cells / (64.0 * 2 * seg) >= 512) seg *= 2;
         c.block = 512;
-        c.seg = seg;
+        c.seg = seg - 1;
         c.variant = 3;
         break;
     }

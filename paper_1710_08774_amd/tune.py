@@ -72,8 +72,11 @@ def family_space(family):
             for seg in (8, 16, 32):
                 for var in (0, 1):
                     out.append((blk, 1, seg, var, 0))
+        # LDS-ring strips of 64 columns x block/64 rows per chunk; a segment
+        # of seg rows takes seg + 1 chunk rows, so segments of C k - 1 rows
+        # leave no idle chunk row
         for blk in (256, 512):
-            for seg in (32, 64, 128):
+            for seg in (31, 32, 63, 64, 127, 128):
                 out.append((blk, 1, seg, 3, 0))
     elif family == "norm":
         # only the configurations covering the row are feasible; the tuner

@@ -112,7 +112,8 @@ def test_euler_sweep_parity(shape, direction, mode):
 @pytest.mark.parametrize("direction,cfg", [(0, (64, 1, 0, 0)), (0, (256, 1, 0, 0)),
                                            (1, (128, 1, 3, 0)), (1, (256, 1, 64, 0)), (1, (64, 1, 1, 0)),
                                            (0, (64, 1, 0, 3)), (0, (256, 1, 0, 3)), (1, (256, 1, 16, 3)),
-                                           (1, (128, 1, 5, 3)), (1, (512, 1, 64, 3)), (1, (256, 1, 1, 3))])
+                                           (1, (128, 1, 5, 3)), (1, (512, 1, 64, 3)), (1, (256, 1, 1, 3)),
+                                           (1, (512, 1, 127, 3)), (1, (512, 1, 31, 3)), (1, (128, 1, 3, 3))])
 def test_euler_sweep_tile_configs(direction, cfg):
     U = inputs.euler_ic(300, 70, seed=12, amp=0.05)
     dt = 0.5 / oracle.euler_smax(U)
@@ -164,12 +165,13 @@ def test_euler_run_parity(mode):
 
 
 @pytest.mark.parametrize("shape", [(96, 80), (200, 33)])
-def test_euler_run_parity_strip_kernels(shape):
+@pytest.mark.parametrize("ycfg", [(256, 1, 16, 3), (512, 1, 15, 3)])
+def test_euler_run_parity_strip_kernels(shape, ycfg):
     # both sweeps as LDS-ring strips, the CFL reduction fused into the y strip
     nx, ny = shape
     U = inputs.euler_ic(nx, ny, seed=102)
     ref, _ = oracle.euler_run(U, 30)
-    st = EulerStepper(nx, ny, forced_x=(256, 1, 0, 3), forced_y=(256, 1, 16, 3))
+    st = EulerStepper(nx, ny, forced_x=(256, 1, 0, 3), forced_y=ycfg)
     st.load(U)
     st.step(30)
     assert max(hydro_errs(host(st.state()), ref)) <= TOL64
