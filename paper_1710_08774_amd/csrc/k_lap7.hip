@@ -10,7 +10,9 @@
 // 2-plane LDS ring over the tile plus a 1-cell halo (the planes k and k+1 its
 // consumer needs), and its centre value at plane k-1 stays in a register.
 // Two barriers per plane; plane loads are software-pipelined P planes ahead
-// through registers.
+// through registers.  A workgroup of NT lanes may own a tile of R = TX*TY/NT
+// output points per lane (lane t owns points t, t + NT, ...): larger tiles
+// re-read less of their 2-cell halo from HBM.
 #include <hip/hip_runtime.h>
 #include "kernels.h"
 #include "ops.h"
@@ -32,16 +34,16 @@ __device__ __forceinline__ int w3(int i, int n) {
     return i < 0 ? i + n : i;
 }
 
-template <class T, int TX, int TY, int P, bool NTS>
-__global__ __launch_bounds__(TX * TY) void lap7_chain_kernel(BArgs<T> a) {
-    constexpr int NT = TX * TY;
+template <class T, int TX, int TY, int P, bool NTS, int NT = TX * TY>
+__global__ __launch_bounds__(NT) void lap7_chain_kernel(BArgs<T> a) {
+    constexpr int R = TX * TY / NT;             // output points per lane
+    static_assert(R * NT == TX * TY, "the tile must be a multiple of the workgroup");
     constexpr int UX = TX + 4, UY = TY + 4;     // u tile with halo 2
     constexpr int LX = TX + 2, LY = TY + 2;     // lap1 tile with halo 1
     constexpr int M = (UX * UY + NT - 1) / NT;  // u points loaded per lane per plane
     __shared__ T su[4][UY][UX];
     __shared__ T sl[2][LY][LX];
     const int tid = threadIdx.x;
-    const int tx = tid % TX, ty = tid / TX;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     // logical tile: x tile fastest, then y tile, then z segment
     const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY, nsg = (nz + a.seg - 1) / a.seg;
@@ -101,12 +103,21 @@ __global__ __launch_bounds__(TX * TY) void lap7_chain_kernel(BArgs<T> a) {
         commit(k0 + r, v);
     }
     __syncthreads();
-    T lm = lap1_at(k0 - 1, tx + 1, ty + 1);
+    // owned output points: tile coordinates, and lap1 at plane k-1 (the
+    // point's own centre, kept in a register)
+    int tx[R], ty[R];
+    bool own[R];
+    T lm[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        tx[r] = (tid + r * NT) % TX;
+        ty[r] = (tid + r * NT) / TX;
+        own[r] = x0 + tx[r] < nx && y0 + ty[r] < ny;
+        lm[r] = lap1_at(k0 - 1, tx[r] + 1, ty[r] + 1);
+    }
     lap1_plane(k0);
     __syncthreads();
 
-    const int gx = x0 + tx, gy = y0 + ty;
-    const bool own = gx < nx && gy < ny;
     for (int kb = k0; kb < k1; kb += P) {
 #pragma unroll
         for (int q = 0; q < P; ++q) {
@@ -118,12 +129,18 @@ __global__ __launch_bounds__(TX * TY) void lap7_chain_kernel(BArgs<T> a) {
             lap1_plane(k + 1);                 // replaces lap1 plane k-1
             __syncthreads();
             T(*l0)[LX] = sl[k & 1];
-            const int hx = tx + 1, hy = ty + 1;
-            const T lc = l0[hy][hx];
-            const T lap2 = lap7(lc, l0[hy][hx + 1], l0[hy][hx - 1], l0[hy + 1][hx], l0[hy - 1][hx],
-                                sl[(k + 1) & 1][hy][hx], lm);
-            if (own) store_out<NTS>(a.out + (size_t)k * plane + (size_t)gy * nx + gx, axpy(su[k & 3][ty + 2][tx + 2], lap2, a.alpha));
-            lm = lc;
+            T *out = a.out + (size_t)k * plane;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int hx = tx[r] + 1, hy = ty[r] + 1;
+                const T lc = l0[hy][hx];
+                const T lap2 = lap7(lc, l0[hy][hx + 1], l0[hy][hx - 1], l0[hy + 1][hx], l0[hy - 1][hx],
+                                    sl[(k + 1) & 1][hy][hx], lm[r]);
+                if (own[r])
+                    store_out<NTS>(out + (size_t)(y0 + ty[r]) * nx + (x0 + tx[r]),
+                                   axpy(su[k & 3][ty[r] + 2][tx[r] + 2], lap2, a.alpha));
+                lm[r] = lc;
+            }
         }
     }
 }
@@ -284,6 +301,12 @@ static hipError_t lap7_dispatch(const Lap7ChainLaunch &L, hipStream_t s) {
     case 3: tx = 128; ty = 2; break;
     case 4: tx = 32; ty = 4; break;
     case 5: case 10: tx = 64; ty = 16; break;
+    case 6: tx = 64; ty = 32; break;
+    case 7: tx = 128; ty = 16; break;
+    // the 4-point tiles need more LDS than a workgroup has in FP64: there
+    // they run as 64 x 32
+    case 8: tx = sizeof(T) == 4 ? 128 : 64; ty = 32; break;
+    case 9: tx = sizeof(T) == 4 ? 256 : 64; ty = sizeof(T) == 4 ? 16 : 32; break;
     case 11: tx = 64; ty = 8; break;
     case 12: tx = 32; ty = 8; break;
     case 13: tx = 128; ty = 8; break;
@@ -293,16 +316,24 @@ static hipError_t lap7_dispatch(const Lap7ChainLaunch &L, hipStream_t s) {
     // tile_y selects the prefetch depth (planes in flight): 1, 2 or 4
     const int P = L.cfg.tile_y == 1 ? 1 : L.cfg.tile_y == 4 ? 4 : 2;
     dim3 grid(((L.nx + tx - 1) / tx) * ((L.ny + ty - 1) / ty) * ((L.nz + a.seg - 1) / a.seg));
-#define B7(TX_, TY_, PP)                                                                                   \
-    do {                                                                                                   \
-        if (nt) hipLaunchKernelGGL((lap7_chain_kernel<T, TX_, TY_, PP, true>), grid, dim3(TX_ * TY_), 0, s, a); \
-        else hipLaunchKernelGGL((lap7_chain_kernel<T, TX_, TY_, PP, false>), grid, dim3(TX_ * TY_), 0, s, a);   \
+#define B7N(TX_, TY_, PP, NN)                                                                                      \
+    do {                                                                                                           \
+        if (nt) hipLaunchKernelGGL((lap7_chain_kernel<T, TX_, TY_, PP, true, NN>), grid, dim3(NN), 0, s, a);       \
+        else hipLaunchKernelGGL((lap7_chain_kernel<T, TX_, TY_, PP, false, NN>), grid, dim3(NN), 0, s, a);         \
     } while (0)
+#define B7(TX_, TY_, PP) B7N(TX_, TY_, PP, TX_ * TY_)
 #define B7P(TX_, TY_)                 \
     switch (P) {                      \
     case 1: B7(TX_, TY_, 1); break;   \
     case 4: B7(TX_, TY_, 4); break;   \
     default: B7(TX_, TY_, 2); break;  \
+    }
+    // tiles larger than a workgroup: 1024 lanes, 2 or 4 points per lane
+#define B7L(TX_, TY_)                          \
+    switch (P) {                               \
+    case 1: B7N(TX_, TY_, 1, 1024); break;     \
+    case 4: B7N(TX_, TY_, 4, 1024); break;     \
+    default: B7N(TX_, TY_, 2, 1024); break;    \
     }
 #define R7(TX_, TY_, PP)                                                                                   \
     do {                                                                                                   \
@@ -321,6 +352,14 @@ static hipError_t lap7_dispatch(const Lap7ChainLaunch &L, hipStream_t s) {
     case 3: B7P(128, 2); break;
     case 4: B7P(32, 4); break;
     case 5: B7P(64, 16); break;
+    case 6: B7L(64, 32); break;
+    case 7: B7L(128, 16); break;
+    case 8:
+        if constexpr (sizeof(T) == 4) { B7L(128, 32); } else { B7L(64, 32); }
+        break;
+    case 9:
+        if constexpr (sizeof(T) == 4) { B7L(256, 16); } else { B7L(64, 32); }
+        break;
     case 10: R7P(64, 16); break;
     case 11: R7P(64, 8); break;
     case 12: R7P(32, 8); break;
@@ -330,8 +369,10 @@ static hipError_t lap7_dispatch(const Lap7ChainLaunch &L, hipStream_t s) {
     }
 #undef R7P
 #undef R7
+#undef B7L
 #undef B7P
 #undef B7
+#undef B7N
     return hipGetLastError();
 }
 

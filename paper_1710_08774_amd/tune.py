@@ -58,7 +58,7 @@ def family_space(family):
                     for xcd in (0, -1):
                         out.append((blk, 1, seg, var, xcd))
     elif family == "lap7_chain":
-        for var in (1, 2, 5, 10, 13, 37):
+        for var in (1, 2, 5, 6, 7, 8, 9, 10, 13, 37, 38):
             for seg in (64, 128):
                 for depth in (2, 4):
                     for xcd in (0, 8):

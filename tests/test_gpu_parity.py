@@ -295,11 +295,12 @@ def test_biharm_parity(shape, mode):
     assert np.array_equal(got, ref)
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 10, 11, 12, 13, 14, 37, 42])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 37, 38, 42])
 @pytest.mark.parametrize("depth,seg", [(1, 5), (4, 6), (2, 17)])
 def test_biharm_tile_variants(variant, depth, seg):
     # ragged tiles in x and y, segments that do not divide nz, every
-    # prefetch depth; variants 10-14 keep the z windows in registers
+    # prefetch depth; variants 6-9 own 2 or 4 points per lane, variants
+    # 10-14 keep the z windows in registers
     shape = (17, 40, 150)
     u = inputs.biharm_input(shape=shape, seed=5)
     ref = oracle.biharm(u)
@@ -309,6 +310,25 @@ def test_biharm_tile_variants(variant, depth, seg):
     o = torch.empty_like(d)
     c.execute([d], [o])
     assert np.array_equal(host(o), ref)
+
+
+@pytest.mark.parametrize("variant", [6, 7, 8, 9, 13])
+def test_biharm_f32_tile_variants_equal_default(variant):
+    """Every tile shape evaluates the same expression per point in the same
+    order, so FP32 results equal the default tiles' bit for bit (here with
+    ragged 128- and 256-wide tiles)."""
+    shape = (9, 50, 300)
+    u = inputs.biharm_input(shape=shape, seed=6)
+    d = dev(u, torch.float32)
+    outs = []
+    for cfg in ((1024, 2, 7, 5), (1024, 2, 7, variant)):
+        c = H.Chain(H.biharm_spec(dtype=H.F32))
+        c.plan((300, 50, 9), mode=H.MODE_FUSED, config_source=H.CONFIG_FORCED, forced=cfg)
+        o = torch.empty_like(d)
+        c.execute([d], [o])
+        outs.append(host(o))
+    assert np.array_equal(outs[0], outs[1])
+    assert relerr(outs[1], oracle.biharm(u.astype(np.float32).astype(np.float64))) <= 1e-6
 
 
 def test_biharm_f32_error_bound():
