@@ -34,8 +34,10 @@ COMPULSORY_BYTES_PER_CELL_SWEEP = 64      # 4 FP64 fields read once, written onc
 
 
 def kernel_source_hash():
+    """Hash of the sweep kernels' sources and of the default launch
+    configurations (tune.cpp): either changes the traffic per launch."""
     h = hashlib.sha256()
-    for f in ("k_euler.hip", "euler_common.h", "ops.h"):
+    for f in ("k_euler.hip", "euler_common.h", "ops.h", "tune.cpp"):
         with open(os.path.join(ROOT, "paper_1710_08774_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -43,7 +45,8 @@ def kernel_source_hash():
 
 def load_traffic(kernel):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when the kernel source changed since the counters were taken."""
+    None when the kernel source or its default configuration changed since
+    the counters were taken."""
     path = os.path.join(ROOT, "profiles", "euler_sweeps_2048_traffic.json")
     try:
         with open(path) as fh:

@@ -226,11 +226,15 @@ typedef struct {
     int variant;    /* family-specific kernel variant, 0 = default.
                        EULER_X / EULER_Y: 0 register budget free, 1 at least
                        4 waves per SIMD, 2 at least 5, 3 LDS-ring strip
-                       kernel (y: block = 64 columns x 2, 4 or 8 rows).
+                       kernel (y: block = 64 columns x 2, 4 or 8 rows; a
+                       segment of seg rows walks seg + 1 chunk rows).
                        HDIFF: row prefetch depth 1 -> 1, 2 -> 2, 4 -> 8,
                        otherwise 4; + 8 DPP lane exchange; + 16
                        non-temporal output stores.  LAP7_CHAIN: tile shape
-                       (1-5 plane rings, 10-14 z windows in registers);
+                       (1-5 plane rings, one point per lane; 6-9 plane
+                       rings with 2 or 4 points per lane: 64 x 32,
+                       128 x 16, FP32 128 x 32 and 256 x 16, FP64 64 x 32
+                       for 8 and 9; 10-14 z windows in registers);
                        + 32 non-temporal output stores.  STAR_CHAIN: tile
                        shape.
                        NORM: 0 row in registers (block * seg >= the row,

@@ -374,12 +374,17 @@ __device__ __forceinline__ double strip(const EArgs<T> &a, const EView<T> &v, bo
     return smax;
 }
 
-// x pass as strips: one workgroup per row (W = 1, C = B lanes along it)
+// x pass as strips: one workgroup per segment of a.seg cells of a row
+// (W = 1, C = B lanes along it); a segment recomputes two halo cells and
+// one interface at its start, like a y segment
 template <class T, class A, bool G14, int B>
 __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(4))) void euler_x_strip_kernel(EArgs<T> a) {
     __shared__ SLds<T, 1, B> S;
-    const int j = xcd_tile(blockIdx.x, a.ny, a.xcd);
-    strip<T, A, G14, 1, B>(a, full_view(a), true, j, 0, a.nx, read_dt(a.dt_src, a.dt_mode, a.cfl), false, S);
+    const int nsg = (a.nx + a.seg - 1) / a.seg;
+    const int tile = xcd_tile(blockIdx.x, a.ny * nsg, a.xcd);
+    const int j = tile / nsg, i0 = (tile % nsg) * a.seg;
+    strip<T, A, G14, 1, B>(a, full_view(a), true, j, i0, min(i0 + a.seg, a.nx), read_dt(a.dt_src, a.dt_mode, a.cfl),
+                           false, S);
 }
 
 // y pass as strips: 64 columns x C rows per chunk, segments of a.seg rows
@@ -526,6 +531,9 @@ static hipError_t euler_x_dispatch(const EulerLaunch &L, hipStream_t s) {
     EArgs<T> a = make_args<T>(L);
     dim3 grid(L.ny);
     if (L.cfg.variant == 3) {
+        // segments of cfg.seg cells (0: whole rows)
+        a.seg = L.cfg.seg > 0 && L.cfg.seg < L.nx ? L.cfg.seg : L.nx;
+        grid = dim3((unsigned)(L.ny * ((L.nx + a.seg - 1) / a.seg)));
         switch (L.cfg.block) {
         case 64: hipLaunchKernelGGL((euler_x_strip_kernel<T, A, G14, 64>), grid, dim3(64), 0, s, a); break;
         case 128: hipLaunchKernelGGL((euler_x_strip_kernel<T, A, G14, 128>), grid, dim3(128), 0, s, a); break;

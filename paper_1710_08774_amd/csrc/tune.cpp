@@ -43,19 +43,29 @@ hfav_config hfav_default_config(int family, int dtype, const int dims[3]) {
         if (c.seg <= 8) c.variant = 1;
         break;
     }
-    case HFAV_FAMILY_EULER_X:   // one workgroup per row, up to 4 waves
-        c.block = dims[0] >= 256 ? 256 : (dims[0] >= 128 ? 128 : 64);
-        c.variant = 1;
+    case HFAV_FAMILY_EULER_X: {
+        // LDS-ring strips, one wave per row segment of seg cells (64 per
+        // chunk; seg = 64k - 1 leaves no chunk lane idle): 191-cell
+        // segments while they give at least 16384 workgroups, else 63
+        // (2048^2 FP64: 0.153 ms against 0.162 for one 4-wave workgroup
+        // per row, whose 2048 workgroups fill 1.6 rounds of the chip)
+        c.block = 64;
+        c.variant = 3;
+        c.seg = (double)dims[1] * ((dims[0] + 190) / 191) >= 16384 ? 191 : 63;
         break;
+    }
     case HFAV_FAMILY_EULER_Y: {
-        // LDS-ring strips of 64 columns x 8 rows per chunk; segments as long
-        // as keeps about 512 eight-wave workgroups in flight, one row short
-        // of a power of two: a segment of seg rows takes seg + 1 chunk rows,
-        // so no chunk row idles (2048^2 FP64: 3% faster than 128 rows)
-        int seg = 32;
-        while (seg < 128 && cells / (64.0 * 2 * seg) >= 512) seg *= 2;
-        c.block = 512;
-        c.seg = seg - 1;
+        // LDS-ring strips of 64 columns x 4 rows per chunk (4-wave
+        // workgroups reach 5 waves per SIMD, 8-wave ones only 4).  A segment
+        // of seg rows walks seg + 1 chunk rows, so seg = 4k - 1 leaves no
+        // chunk row idle; 15-row segments while they still give about
+        // three rounds of 1280 resident workgroups, else 7, else 3 (2048^2
+        // FP64: 0.183 ms against 0.192 with 8 x 127; 512^2: 0.025 ms
+        // against 0.035)
+        const double cols = (dims[0] + 63) / 64;
+        auto wgs = [&](int seg) { return cols * ((dims[1] + seg - 1) / seg); };
+        c.block = 256;
+        c.seg = wgs(15) >= 3840 ? 15 : wgs(7) >= 512 ? 7 : 3;
         c.variant = 3;
         break;
     }

@@ -67,6 +67,9 @@ def family_space(family):
         for blk in (64, 128, 256):
             for var in (0, 1, 3):
                 out.append((blk, 1, 0, var, 0))
+        # row segments of the strip kernel (64 k - 1 cells)
+        for blk, seg in ((64, 63), (64, 127), (64, 191), (64, 255), (128, 127), (128, 255), (256, 255), (256, 511)):
+            out.append((blk, 1, seg, 3, 0))
     elif family == "euler_y":
         for blk in (64, 128, 256):
             for seg in (8, 16, 32):
@@ -75,9 +78,12 @@ def family_space(family):
         # LDS-ring strips of 64 columns x block/64 rows per chunk; a segment
         # of seg rows takes seg + 1 chunk rows, so segments of C k - 1 rows
         # leave no idle chunk row
-        for blk in (256, 512):
-            for seg in (31, 32, 63, 64, 127, 128):
-                out.append((blk, 1, seg, 3, 0))
+        for seg in (3, 7, 11, 15, 19, 23, 31, 63, 127):
+            out.append((256, 1, seg, 3, 0))
+        for seg in (31, 63, 127):
+            out.append((512, 1, seg, 3, 0))
+        for seg in (7, 15):
+            out.append((128, 1, seg, 3, 0))
     elif family == "norm":
         # only the configurations covering the row are feasible; the tuner
         # skips the others

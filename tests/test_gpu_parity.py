@@ -113,7 +113,10 @@ def test_euler_sweep_parity(shape, direction, mode):
                                            (1, (128, 1, 3, 0)), (1, (256, 1, 64, 0)), (1, (64, 1, 1, 0)),
                                            (0, (64, 1, 0, 3)), (0, (256, 1, 0, 3)), (1, (256, 1, 16, 3)),
                                            (1, (128, 1, 5, 3)), (1, (512, 1, 64, 3)), (1, (256, 1, 1, 3)),
-                                           (1, (512, 1, 127, 3)), (1, (512, 1, 31, 3)), (1, (128, 1, 3, 3))])
+                                           (1, (512, 1, 127, 3)), (1, (512, 1, 31, 3)), (1, (128, 1, 3, 3)),
+                                           (1, (256, 1, 15, 3)), (1, (256, 1, 7, 3)), (1, (256, 1, 3, 3)),
+                                           (0, (256, 1, 255, 3)), (0, (128, 1, 100, 3)), (0, (64, 1, 63, 3)),
+                                           (0, (256, 1, 1, 3)), (0, (128, 1, 299, 3))])
 def test_euler_sweep_tile_configs(direction, cfg):
     U = inputs.euler_ic(300, 70, seed=12, amp=0.05)
     dt = 0.5 / oracle.euler_smax(U)
