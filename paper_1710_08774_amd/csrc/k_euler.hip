@@ -17,6 +17,12 @@
 // recomputes two halo cells and one interface at its top.  The CFL
 // reduction of the updated state is fused into this pass (wave reduction,
 // then one atomic max per workgroup).
+//
+// Strip pass (either direction, the default for both): the LDS rings of the
+// x pass laid along the sweep for W adjacent lines and C cells of each per
+// chunk, over segments of a line, so that short work items (one wave per x
+// segment, 4-row strips for y) fill the chip evenly.  The batched sweeps run
+// the same strip body on (grid, line, segment) items.
 #include <hip/hip_runtime.h>
 #include "kernels.h"
 #include "euler_common.h"
@@ -315,12 +321,15 @@ __device__ __forceinline__ double strip(const EArgs<T> &a, const EView<T> &v, bo
 #pragma unroll
         for (int k = 0; k < 4; ++k) S.fF[k][sl][wl] = plus[k];
     }
+    // the ring holds C + 2 cells: the first chunk's cell j0 + C takes the
+    // slot of cell j0 - 2, which the reads just above must be done with
+    __syncthreads();
     for (int c0 = j0; c0 <= j1; c0 += C) {
         const int p = c0 + q;
         const bool act = lact && p <= j1;
         // stage 1: the cell entering the window.  The previous chunk read
         // these primitive slots in its stage 2, and three barriers have
-        // passed since
+        // passed since (the prologue's reads: the barrier before the loop)
         T un[4];
         if (act) {
             const size_t o = addr(p + 1);
@@ -436,36 +445,44 @@ __device__ __forceinline__ EView<T> grid_view(const EArgs<T> &a, const BatchDims
                     a.orho + c.off, a.omn + c.off, a.omt + c.off, a.oE + c.off, d.nx[c.g], d.ny[c.g]};
 }
 
-template <class T, class A, bool G14, int B>
-__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(4))) void euler_x_batch_kernel(EArgs<T> a, BatchDims d, long long items) {
-    __shared__ XLds<T, B> S;
+// x items: segments of BATCH_XSEG cells of one row, one wave each (the
+// strip body with W = 1, C = 64, as the single-grid x sweep)
+constexpr int BATCH_XSEG = 191;
+
+template <class T, class A, bool G14>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void euler_x_batch_kernel(EArgs<T> a, BatchDims d, long long items) {
+    __shared__ SLds<T, 1, 64> S;
     Cursor c{0, 0, 0};
-    auto rows = [&](int g) { return (long long)d.ny[g]; };
+    auto segs = [&](int g) { return (long long)d.ny[g] * ((d.nx[g] + BATCH_XSEG - 1) / BATCH_XSEG); };
     for (long long it = blockIdx.x; it < items; it += gridDim.x) {
-        advance(c, it, d, rows);
+        advance(c, it, d, segs);
         const EView<T> v = grid_view(a, d, c);
+        const int nsg = (v.nx + BATCH_XSEG - 1) / BATCH_XSEG;
+        const int local = (int)(it - c.base);
+        const int j = local / nsg, i0 = (local % nsg) * BATCH_XSEG;
         const double dt = read_dt(a.dt_src + c.g, a.dt_mode, a.cfl);
-        x_row<T, A, G14, B>(a, v, (int)(it - c.base), dt, S);
+        strip<T, A, G14, 1, 64>(a, v, true, j, i0, min(i0 + BATCH_XSEG, v.nx), dt, false, S);
     }
 }
 
-template <class T, class A, bool G14, int B>
-__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(4))) void euler_y_batch_kernel(EArgs<T> a, BatchDims d, long long items) {
-    __shared__ T s_u[3][4][B];
+// y items: tiles of 64 columns x seg[g] rows, 4-wave strips (C = 4)
+template <class T, class A, bool G14>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void euler_y_batch_kernel(EArgs<T> a, BatchDims d, long long items) {
+    __shared__ SLds<T, 64, 4> S;
     Cursor c{0, 0, 0};
     auto tiles = [&](int g) {
-        return (long long)((d.nx[g] + B - 1) / B) * ((d.ny[g] + d.seg[g] - 1) / d.seg[g]);
+        return (long long)((d.nx[g] + 63) / 64) * ((d.ny[g] + d.seg[g] - 1) / d.seg[g]);
     };
     for (long long it = blockIdx.x; it < items; it += gridDim.x) {
         advance(c, it, d, tiles);
         const EView<T> v = grid_view(a, d, c);
-        const int ntx = (v.nx + B - 1) / B;
+        const int ntx = (v.nx + 63) / 64;
         const int tile = (int)(it - c.base);
-        const int i0 = (tile % ntx) * B, j0 = (tile / ntx) * d.seg[c.g];
+        const int i0 = (tile % ntx) * 64, j0 = (tile / ntx) * d.seg[c.g];
         const int j1 = min(j0 + (int)d.seg[c.g], v.ny);
         const double dt = read_dt(a.dt_src + c.g, a.dt_mode, a.cfl);
-        const double smax = y_tile<T, A, G14, B>(a, v, i0, j0, j1, dt, a.smax_out != nullptr, s_u);
-        if (a.smax_out) block_max_to<B>(smax, a.smax_out + c.g);
+        const double smax = strip<T, A, G14, 64, 4>(a, v, false, i0, j0, j1, dt, a.smax_out != nullptr, S);
+        if (a.smax_out) block_max_to<256>(smax, a.smax_out + c.g);
     }
 }
 
@@ -635,15 +652,18 @@ static hipError_t batch_dispatch(const EulerLaunch &L, const EulerBatch &Bt, boo
     EArgs<T> a = make_args<T>(L);
     const BatchDims d = make_dims(Bt);
     long long items = 0;
-    const int B = 64;
-    for (int g = 0; g < Bt.n; ++g)
-        items += x ? Bt.ny[g] : (long long)((Bt.nx[g] + B - 1) / B) * ((Bt.ny[g] + Bt.seg[g] - 1) / Bt.seg[g]);
-    // one-wave workgroups, four resident per SIMD
-    const long long cap = (long long)(Bt.workgroups > 0 ? Bt.workgroups : 256 * 16);
+    for (int g = 0; g < Bt.n; ++g) {
+        if (Bt.seg[g] < 1) return hipErrorInvalidValue;
+        items += x ? (long long)Bt.ny[g] * ((Bt.nx[g] + BATCH_XSEG - 1) / BATCH_XSEG)
+                   : (long long)((Bt.nx[g] + 63) / 64) * ((Bt.ny[g] + Bt.seg[g] - 1) / Bt.seg[g]);
+    }
+    // resident pool: 5 waves per SIMD on 256 CUs, as one-wave x workgroups
+    // or four-wave y workgroups
+    const long long cap = (long long)(Bt.workgroups > 0 ? Bt.workgroups : (x ? 256 * 20 : 256 * 5));
     const unsigned nwg = (unsigned)(items < cap ? items : cap);
     if (nwg == 0) return hipSuccess;
-    if (x) hipLaunchKernelGGL((euler_x_batch_kernel<T, A, G14, 64>), dim3(nwg), dim3(64), 0, s, a, d, items);
-    else hipLaunchKernelGGL((euler_y_batch_kernel<T, A, G14, 64>), dim3(nwg), dim3(64), 0, s, a, d, items);
+    if (x) hipLaunchKernelGGL((euler_x_batch_kernel<T, A, G14>), dim3(nwg), dim3(64), 0, s, a, d, items);
+    else hipLaunchKernelGGL((euler_y_batch_kernel<T, A, G14>), dim3(nwg), dim3(256), 0, s, a, d, items);
     return hipGetLastError();
 }
 

@@ -1172,14 +1172,14 @@ extern "C" int hfav_plan_batch(hfav_chain *chain, const hfav_plan_opts *opts, in
         p.boff[g] = off;
         off += (int64_t)p.bnx[g] * p.bny[g];
         const int gd[3] = {p.bnx[g], p.bny[g], 1};
-        // the batched y sweep keeps its windows in registers; its segment
-        // length per grid comes from the batch entries of the tuning table
-        // (nearest size bucket), else 16
-        hfav_config cg{64, 1, 16, 1, 0};
+        // the batched y sweep runs 4-row strips; its segment length per
+        // grid comes from the batch entries of the tuning table (nearest
+        // size bucket), else 15 (a segment of s rows walks s + 1 chunk rows)
+        hfav_config cg{256, 1, 15, 3, 0};
         if (o.config_source == HFAV_CONFIG_FORCED) cg = o.forced;
         else if (o.config_source == HFAV_CONFIG_TUNED)
             hfav_tuned_config(HFAV_FAMILY_EULER_Y_BATCH, chain->dtype, gd, &cg);
-        int seg = cg.seg > 0 && cg.variant != 3 ? cg.seg : 16;
+        int seg = cg.seg > 0 ? cg.seg : 15;
         p.bseg[g] = seg > 255 ? 255 : seg;
     }
     p.btotal = off;

@@ -194,11 +194,11 @@ DB_BUCKETS = [
 BATCH_BUCKETS = ((128, 128, 1), (362, 362, 1), (724, 724, 1))
 
 
-def tune_batch(sizes=None, segs=(8, 16, 32, 64), reps=3, dtype=H.F64, log=None):
-    """Segment length of the batched y sweep per size bucket, chosen by timing
-    the whole batch (its load balance depends on the mix): coordinate descent
-    over the buckets from seg 16 everywhere, two rounds.  Returns database
-    entries for HFAV_FAMILY_EULER_Y_BATCH."""
+def tune_batch(sizes=None, segs=(7, 15, 31, 63), reps=3, dtype=H.F64, log=None):
+    """Segment length of the batched y sweep (4-row strips) per size bucket,
+    chosen by timing the whole batch (its load balance depends on the mix):
+    coordinate descent over the buckets from seg 15 everywhere, two rounds.
+    Returns database entries for HFAV_FAMILY_EULER_Y_BATCH."""
     import torch
     from .euler import EulerBatchStepper
     sizes = inputs.batch_sizes(512) if sizes is None else sizes
@@ -210,11 +210,11 @@ def tune_batch(sizes=None, segs=(8, 16, 32, 64), reps=3, dtype=H.F64, log=None):
     def timed(choice):
         H.tuning_clear()
         for centre, seg in zip(BATCH_BUCKETS, choice):
-            H.tuning_add(FAMILY_ID["euler_y_batch"], dtype, centre, (64, 1, seg, 1, 0))
+            H.tuning_add(FAMILY_ID["euler_y_batch"], dtype, centre, (256, 1, seg, 3, 0))
         bt.iy = bt.cy.plan_batch(bt.sizes, config_source=H.CONFIG_TUNED)
         return _event_ms(bt.step, reps)
 
-    choice = [16] * len(BATCH_BUCKETS)
+    choice = [15] * len(BATCH_BUCKETS)
     best = timed(choice)
     base = best
     for _ in range(2):
@@ -230,16 +230,17 @@ def tune_batch(sizes=None, segs=(8, 16, 32, 64), reps=3, dtype=H.F64, log=None):
     H.tuning_clear()
     if log:
         log(f"db: euler_y_batch {len(sizes)} grids: segments {choice} per bucket, {best:.3f} ms per step "
-            f"(16 everywhere: {base:.3f} ms)")
+            f"(15 everywhere: {base:.3f} ms)")
     return [{"family": "euler_y_batch", "family_id": FAMILY_ID["euler_y_batch"], "dtype": DTYPE_NAME[dtype],
-             "dims": list(c), "config": [64, 1, seg, 1, 0], "ms": best, "default_ms": base,
+             "dims": list(c), "config": [256, 1, seg, 3, 0], "ms": best, "default_ms": base,
              "n_configs": len(segs) * len(BATCH_BUCKETS), "search_s": 0.0}
             for c, seg in zip(BATCH_BUCKETS, choice)]
 
 
-def build_db(buckets=None, reps=5, log=None, batch=True):
+def build_db(buckets=None, reps=5, log=None, batch=None):
     """Autotune every (family, dtype, shape) bucket and the batch's segment
-    lengths; returns the database."""
+    lengths (by default only with the full bucket list); returns the
+    database."""
     entries = []
     for family, dtype, dims in (DB_BUCKETS if buckets is None else buckets):
         t0 = time.time()
@@ -251,7 +252,7 @@ def build_db(buckets=None, reps=5, log=None, batch=True):
         if log:
             log(f"db: {family} {DTYPE_NAME[dtype]} {dims}: best {best} {best_ms:.4f} ms "
                 f"(default {default_ms:.4f} ms, {len(res)} configs)")
-    if batch and buckets is None:
+    if batch or (batch is None and buckets is None):
         entries += tune_batch(log=log)
     return {"version": 1, "entries": entries}
 
@@ -510,10 +511,11 @@ def main(argv=None):
     st.add_argument("--out", default="gpurun_out/costmodel_study.json")
     a = ap.parse_args(argv)
     if a.cmd == "db":
-        buckets = None
+        buckets, batch = None, None
         if a.families:
             buckets = [b for b in DB_BUCKETS if b[0] in a.families]
-        db = build_db(buckets=buckets, reps=a.reps, log=lambda m: print(m, flush=True))
+            batch = "euler_y_batch" in a.families
+        db = build_db(buckets=buckets, reps=a.reps, log=lambda m: print(m, flush=True), batch=batch)
         if a.merge:
             with open(a.merge) as f:
                 old = json.load(f)

@@ -19,12 +19,14 @@ def _sizes(n, seed, lo=8, hi=200):
 def test_batch_matches_single_grid_bitwise():
     sizes = _sizes(24, 11) + [(1, 5), (70, 1), (64, 64), (65, 129)]
     states = inputs.batch_ic(sizes=sizes, seed=11)
-    bt = EulerBatchStepper(sizes, forced_y=(64, 1, 16, 0))
+    # the batch runs the single-grid strip bodies: one wave per 191-cell row
+    # segment, 4-row strips over 64 columns x 11-row segments
+    bt = EulerBatchStepper(sizes, forced_y=(256, 1, 11, 3))
     bt.load(states)
     bt.step(4)
     torch.cuda.synchronize()
     for g, (nx, ny) in enumerate(sizes):
-        st = EulerStepper(nx, ny, forced_x=(64, 1, 0, 0), forced_y=(64, 1, 16, 0))
+        st = EulerStepper(nx, ny, forced_x=(64, 1, 191, 3), forced_y=(256, 1, 11, 3))
         st.load(states[g])
         st.step(4)
         assert np.array_equal(host(bt.grid(g)), host(st.state())), (g, nx, ny)

@@ -334,7 +334,7 @@ def test_batch_segments_from_tuning_buckets():
         b = c.plan_json()["batch"]
         assert b["grids"] == 3 and b["y_seg"][:2] == [8, 32]
         c.plan_batch([(100, 120), (700, 800)])
-        assert c.plan_json()["batch"]["y_seg"] == [16, 16]
+        assert c.plan_json()["batch"]["y_seg"] == [15, 15]
         c.plan_batch([(100, 120)], config_source=H.CONFIG_FORCED, forced=(64, 1, 5, 1))
         assert c.plan_json()["batch"]["y_seg"] == [5]
     finally:
