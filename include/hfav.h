@@ -382,8 +382,10 @@ const char *hfav_version(void);
  * grid term is then ONE packed device buffer holding grid g at element
  * offset hfav_batch_offset(chain, g), and every 0-D term is a device array of
  * n_grids doubles (one dt / CFL slot per grid).  The y-sweep segment length
- * of each grid comes from the configuration source (the tuning table is
- * consulted with that grid's own size).  Host only; allocates nothing.
+ * of each grid (rows per work item of 64 columns, 1..255; default 15) comes
+ * from the configuration source (the tuning table is consulted with that
+ * grid's own size; a forced configuration gives every grid its seg).  Host
+ * only; allocates nothing.
  * Errors: EINVAL (bad sizes, n_grids not in [1, HFAV_MAX_BATCH]), EUNSUP
  * (chain not an Euler sweep or CFL reduction, or unfused mode). */
 int hfav_plan_batch(hfav_chain *chain, const hfav_plan_opts *opts, int n_grids, const int *dims,

@@ -180,6 +180,20 @@ def test_euler_run_parity_strip_kernels(shape, ycfg):
     assert max(hydro_errs(host(st.state()), ref)) <= TOL64
 
 
+def test_euler_multiwave_strips_short_segments():
+    """Multi-wave strips (4-wave x blocks, 8-row y strips) over many short
+    segments: each segment's prologue reads the ring slot that its first
+    chunk's last cell takes, so the two must be ordered by a barrier (a
+    race there corrupted the first updated cell of some segments)."""
+    nx, ny = 1024, 768
+    U = inputs.euler_ic(nx, ny, seed=104)
+    ref, _ = oracle.euler_run(U, 3)
+    st = EulerStepper(nx, ny, forced_x=(256, 1, 63, 3), forced_y=(512, 1, 7, 3))
+    st.load(U)
+    st.step(3)
+    assert max(hydro_errs(host(st.state()), ref)) <= TOL64
+
+
 def test_euler_config_workload_two_steps_full_size():
     # the benchmark configuration (2048^2, FP64, periodic), compared in full
     nx = ny = 2048
