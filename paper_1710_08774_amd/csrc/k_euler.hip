@@ -280,7 +280,11 @@ template <class T, class A, bool G14, int W, int C>
 __device__ __forceinline__ double strip(const EArgs<T> &a, const EView<T> &v, bool xdir, int line0, int j0, int j1,
                                         double dt, bool want_smax, SLds<T, W, C> &S) {
     using L = SLds<T, W, C>;
-    const int t = threadIdx.x, wl = t % W, q = t / W;
+    static_assert(L::RW == L::RF, "one slot index serves both rings");
+    // with W = 64 a wave sweeps one cell of each of 64 lines: q is uniform
+    // over the wave, and the slot arithmetic below stays scalar
+    const int t = threadIdx.x, wl = t % W;
+    const int q = W == 64 ? __builtin_amdgcn_readfirstlane(t / W) : t / W;
     const int n = xdir ? v.nx : v.ny;
     const int nlines = xdir ? v.ny : v.nx;
     const bool lact = line0 + wl < nlines;
@@ -291,15 +295,13 @@ __device__ __forceinline__ double strip(const EArgs<T> &a, const EView<T> &v, bo
     const A nuA = (A)dt;
     double smax = 0.0;
     auto addr = [&](int cell) { return lb + (size_t)wrap_cell(cell, n, a.bc) * sa; };
-    auto ws = [&](int cell) { return (cell - j0 + 2) % L::RW; };
+    // ring slot of a cell (both rings: cell - j0 + 2 modulo C + 2)
     auto fs = [&](int cell) { return (cell - j0 + 2) % L::RF; };
-    auto put = [&](int cell, const Prim<T> &w) {
-        const int sl = ws(cell);
+    auto put = [&](int sl, const Prim<T> &w) {
         S.w[0][sl][wl] = w.r; S.w[1][sl][wl] = w.un; S.w[2][sl][wl] = w.ut; S.w[3][sl][wl] = w.p;
         S.w[4][sl][wl] = w.c;
     };
-    auto get = [&](int cell) {
-        const int sl = ws(cell);
+    auto get = [&](int sl) {
         Prim<T> w;
         w.r = S.w[0][sl][wl]; w.un = S.w[1][sl][wl]; w.ut = S.w[2][sl][wl]; w.p = S.w[3][sl][wl];
         w.c = S.w[4][sl][wl];
@@ -311,12 +313,12 @@ __device__ __forceinline__ double strip(const EArgs<T> &a, const EView<T> &v, bo
     // cell j0-1
     for (int k = q; lact && k < 3; k += C) {
         const size_t o = addr(j0 - 2 + k);
-        put(j0 - 2 + k, euler_prim(v.rho[o], v.mn[o], v.mt[o], v.E[o], g));
+        put(fs(j0 - 2 + k), euler_prim(v.rho[o], v.mn[o], v.mt[o], v.E[o], g));
     }
     __syncthreads();
     if (lact && q == 0) {
         T plus[4], minus[4];
-        slope_trace(get(j0 - 2), get(j0 - 1), get(j0), nu, plus, minus);
+        slope_trace(get(fs(j0 - 2)), get(fs(j0 - 1)), get(fs(j0)), nu, plus, minus);
         const int sl = fs(j0 - 1);
 #pragma unroll
         for (int k = 0; k < 4; ++k) S.fF[k][sl][wl] = plus[k];
@@ -327,6 +329,14 @@ __device__ __forceinline__ double strip(const EArgs<T> &a, const EView<T> &v, bo
     for (int c0 = j0; c0 <= j1; c0 += C) {
         const int p = c0 + q;
         const bool act = lact && p <= j1;
+        // slot of cell p + d for d in [-2, 1], from the chunk's base slot
+        // (wave-uniform) with one wrap each way instead of a division
+        const int wb = (c0 - j0 + 2) % L::RW;
+        auto sl = [&](int d) {
+            int s = wb + q + d;
+            s -= s >= L::RW ? L::RW : 0;
+            return s < 0 ? s + L::RW : s;
+        };
         // stage 1: the cell entering the window.  The previous chunk read
         // these primitive slots in its stage 2, and three barriers have
         // passed since (the prologue's reads: the barrier before the loop)
@@ -335,17 +345,17 @@ __device__ __forceinline__ double strip(const EArgs<T> &a, const EView<T> &v, bo
             const size_t o = addr(p + 1);
             un[0] = v.rho[o]; un[1] = v.mn[o]; un[2] = v.mt[o]; un[3] = v.E[o];
         }
-        if (act) put(p + 1, euler_prim(un[0], un[1], un[2], un[3], g));
+        if (act) put(sl(1), euler_prim(un[0], un[1], un[2], un[3], g));
         __syncthreads();
         // stage 2: slopes and trace of cell p; the plus face goes to the
         // lane of cell p+1 through LDS, the minus face stays in registers
         T minus[4];
         if (act) {
             T plus[4];
-            slope_trace(get(p - 1), get(p), get(p + 1), nu, plus, minus);
-            const int sl = fs(p);
+            slope_trace(get(sl(-1)), get(sl(0)), get(sl(1)), nu, plus, minus);
+            const int s0 = sl(0);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) S.fF[k][sl][wl] = plus[k];
+            for (int k = 0; k < 4; ++k) S.fF[k][s0][wl] = plus[k];
         }
         __syncthreads();
         // stage 3: Riemann problem and flux at interface p-1/2; the flux
@@ -353,7 +363,7 @@ __device__ __forceinline__ double strip(const EArgs<T> &a, const EView<T> &v, bo
         // its left state
         T Lf[4];
         if (act) {
-            const int sm = fs(p - 1);
+            const int sm = sl(-1);
 #pragma unroll
             for (int k = 0; k < 4; ++k) Lf[k] = S.fF[k][sm][wl];
         }
@@ -362,7 +372,7 @@ __device__ __forceinline__ double strip(const EArgs<T> &a, const EView<T> &v, bo
             T G[4], F[4];
             riemann_T<T, G14>(Lf, minus, g, a.niter, G);
             euler_flux(G, g, F);
-            const int sm = fs(p - 1);
+            const int sm = sl(-1);
 #pragma unroll
             for (int k = 0; k < 4; ++k) S.fF[k][sm][wl] = F[k];
         }
@@ -371,7 +381,7 @@ __device__ __forceinline__ double strip(const EArgs<T> &a, const EView<T> &v, bo
         // from F(p-1/2) (slot of p-1) and F(p-3/2) (slot of p-2)
         if (act && p > j0) {
             const size_t o = lb + (size_t)(p - 1) * sa;
-            const int s1 = fs(p - 1), s2 = fs(p - 2);
+            const int s1 = sl(-1), s2 = sl(-2);
             const T r = euler_update(v.rho[o], S.fF[0][s1][wl], S.fF[0][s2][wl], nuA);
             const T mn = euler_update(v.mn[o], S.fF[1][s1][wl], S.fF[1][s2][wl], nuA);
             const T mt = euler_update(v.mt[o], S.fF[2][s1][wl], S.fF[2][s2][wl], nuA);
