@@ -378,8 +378,23 @@ def batched_grids(steps=50, loop_steps=4):
             "y_segments_by_bucket": segs}
 
 
-def cpu_baseline(U0, budget_s=12.0):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(U0, budget_s=12.0, single_s=3.0):
+    """The FP64 oracle timed on the host: the full workload on all the
+    threads it uses (bounded to about budget_s), then one thread on a 512^2
+    grid of the same initial-state recipe (bounded to about single_s)."""
     import oracle
+    from paper_1710_08774_amd import inputs
     cores = oracle.num_threads()
     U = U0.copy()
     steps = 0
@@ -390,9 +405,27 @@ def cpu_baseline(U0, budget_s=12.0):
         if time.perf_counter() - t0 >= budget_s or steps >= 50:
             break
     dt = time.perf_counter() - t0
+    # one thread, smaller grid: cell-updates/s of the same chain
+    n1 = 512
+    V = inputs.euler_ic(n1, n1)
+    oracle.set_threads(1)
+    try:
+        s1 = 0
+        t1 = time.perf_counter()
+        while True:
+            V, _ = oracle.euler_run(V, 1)
+            s1 += 1
+            if time.perf_counter() - t1 >= single_s or s1 >= 50:
+                break
+        d1 = time.perf_counter() - t1
+    finally:
+        oracle.set_threads(cores)
     return {"value": NX * NY * steps / dt, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
             "sample": f"FP64 oracle, {NX}x{NY} hydro chain, {steps} full steps from the initial state "
-                      f"({dt:.1f} s on {cores} OpenMP threads)"}
+                      f"({dt:.1f} s on {cores} OpenMP threads)",
+            "cpu": cpu_model(),
+            "single_thread": {"value": n1 * n1 * s1 / d1, "unit": "cell-updates/s",
+                              "sample": f"{n1}x{n1}, {s1} full steps on 1 thread ({d1:.1f} s)"}}
 
 
 def main(argv=None):
