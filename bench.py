@@ -125,9 +125,27 @@ def run_xy(steps, warmup, U0, seg=None):
             "config": [st.ixy.config.block, st.ixy.config.seg], "state_finite": bool(torch.isfinite(st.state()).all())}
 
 
+def event_times(fn, reps, warmup=3):
+    """Median and mean ms of `reps` executions of fn after `warmup` ones,
+    each bracketed by its own pair of HIP events on the current stream."""
+    import torch
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        fn()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1 in ev:
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    t = sorted(e0.elapsed_time(e1) for e0, e1 in ev)
+    return t[len(t) // 2], sum(t) / len(t)
+
+
 def time_chain(spec, dims, mode, reps, inputs_fn):
-    """Average ms per hfav_execute of a single-axiom, single-goal chain, timed
-    with HIP events on the stream the chain is launched on."""
+    """Median and mean ms per hfav_execute of a single-axiom, single-goal
+    chain (3 warm-up executions, then `reps` each timed with HIP events on
+    the stream the chain is launched on)."""
     import torch
     from paper_1710_08774_amd import hfav as H
 
@@ -136,21 +154,12 @@ def time_chain(spec, dims, mode, reps, inputs_fn):
     u = inputs_fn()
     o = torch.empty_like(u)
     ws = torch.empty(info.workspace_bytes, dtype=torch.uint8, device="cuda") if info.workspace_bytes else None
-    c.execute([u], [o], ws)
-    torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(reps):
-        c.execute([u], [o], ws)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+    med, mean = event_times(lambda: c.execute([u], [o], ws), reps)
     del u, o, ws
-    return ms, info
+    return med, mean, info
 
 
-def bandwidth_chains(reps=10, which=("hdiff", "biharm64", "biharm32"), unfused=True):
+def bandwidth_chains(reps=20, which=("hdiff", "biharm64", "biharm32"), unfused=True):
     """Fused vs unfused throughput of the bandwidth-bound chains at sizes whose
     working sets are far larger than the caches."""
     import torch
@@ -169,15 +178,15 @@ def bandwidth_chains(reps=10, which=("hdiff", "biharm64", "biharm32"), unfused=T
             dims, spec, es = (512, 512, 512), H.biharm_spec(dtype=H.F32), 4
             mk = lambda: torch.rand((512, 512, 512), dtype=torch.float32, device="cuda", generator=g.manual_seed(3))
         cells = dims[0] * dims[1] * dims[2]
-        ms, info = time_chain(spec, dims, H.MODE_FUSED, reps, mk)
+        ms, ms_mean, info = time_chain(spec, dims, H.MODE_FUSED, reps, mk)
         gbs = 2 * es * cells / (ms * 1e-3) / 1e9
-        r = {"dims": list(dims), "dtype": "f64" if es == 8 else "f32", "fused_ms": ms,
+        r = {"dims": list(dims), "dtype": "f64" if es == 8 else "f32", "fused_ms": ms, "fused_ms_mean": ms_mean,
              "fused_cell_updates_per_s": cells / (ms * 1e-3), "fused_GBs": gbs,
              "fused_frac_of_8TBs": gbs / HBM_PEAK_GBS,
              "bytes_per_cell_fused": info.bytes_per_cell_fused,
              "config": [info.config.block, info.config.tile_y, info.config.seg, info.config.variant]}
         if unfused:
-            ums, uinfo = time_chain(spec, dims, H.MODE_UNFUSED, max(2, reps // 3), mk)
+            ums, _, uinfo = time_chain(spec, dims, H.MODE_UNFUSED, max(2, reps // 3), mk)
             r.update({"unfused_ms": ums, "unfused_cell_updates_per_s": cells / (ums * 1e-3),
                       "fused_over_unfused": ums / ms, "bytes_per_cell_unfused": uinfo.bytes_per_cell_unfused})
         out[name] = r
@@ -207,17 +216,10 @@ def norm_chain(reps=20, nq=4, nj=4096, ni=4096, unfused=True):
         info = c.plan((ni, nj), mode=mode)
         ws = torch.empty(max(1, info.workspace_bytes), dtype=torch.uint8, device="cuda")
         args = ([u[q] for q in range(nq)], [o[q] for q in range(nq)], ws)
-        c.execute(*args)
-        torch.cuda.synchronize()
         n = reps if mode == H.MODE_FUSED else max(2, reps // 4)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(n):
-            c.execute(*args)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / n
+        ms, ms_mean = event_times(lambda: c.execute(*args), n)
         out[name + "_ms"] = ms
+        out[name + "_ms_mean"] = ms_mean
         out[name + "_cell_updates_per_s"] = cells / (ms * 1e-3)
         out["bytes_per_cell_" + name] = info.bytes_per_cell_fused if mode == H.MODE_FUSED \
             else info.bytes_per_cell_unfused
@@ -234,7 +236,7 @@ def norm_chain(reps=20, nq=4, nj=4096, ni=4096, unfused=True):
     return out
 
 
-def hdiff_in_place(reps=10, dims=(2048, 2048, 64)):
+def hdiff_in_place(reps=20, dims=(2048, 2048, 64)):
     """Horizontal diffusion written over its input (declared alias): the
     halo columns and rows at tile boundaries are saved by a copy kernel, the
     fused kernel then runs in place.  Footprint: one field plus the saved
@@ -249,19 +251,10 @@ def hdiff_in_place(reps=10, dims=(2048, 2048, 64)):
     c.alias("out", "u")
     info = c.plan(dims, mode=H.MODE_FUSED)
     ws = torch.empty(max(1, info.workspace_bytes), dtype=torch.uint8, device="cuda")
-    c.execute([u], [u], ws)
-    torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(reps):
-        c.execute([u], [u], ws)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+    ms, ms_mean = event_times(lambda: c.execute([u], [u], ws), reps)
     cells = ni * nj * nk
     field = cells * 8
-    out = {"dims": list(dims), "dtype": "f64", "ms": ms, "cell_updates_per_s": cells / (ms * 1e-3),
+    out = {"dims": list(dims), "dtype": "f64", "ms": ms, "ms_mean": ms_mean, "cell_updates_per_s": cells / (ms * 1e-3),
            "compulsory_GBs": 2 * field / (ms * 1e-3) / 1e9,
            "footprint_bytes_in_place": field + info.workspace_bytes, "footprint_bytes_out_of_place": 2 * field,
            "halo_copy_bytes": info.workspace_bytes,
