@@ -43,20 +43,25 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when the kernel source or its default configuration changed since
-    the counters were taken."""
+def load_counters(kernel):
+    """The committed rocprofv3 counter figures of one sweep kernel (HBM bytes
+    per launch, VALU busy, VALU instructions per 64 cells), or {} when the
+    kernel source or its default configuration changed since the counters
+    were taken."""
     path = os.path.join(ROOT, "profiles", "euler_sweeps_2048_traffic.json")
     try:
         with open(path) as fh:
             d = json.load(fh)
     except OSError:
-        return None
+        return {}
     if d.get("source_hash") != kernel_source_hash():
-        return None
-    k = d.get("kernels", {}).get(kernel)
-    return None if k is None else k.get("hbm_bytes_per_launch")
+        return {}
+    return d.get("kernels", {}).get(kernel) or {}
+
+
+def load_traffic(kernel):
+    """HBM bytes per launch from the committed counters, or None."""
+    return load_counters(kernel).get("hbm_bytes_per_launch")
 
 
 def run_gpu(mode, steps, warmup, U0, timing=True, dtype=None):
@@ -521,7 +526,11 @@ def main(argv=None):
                             "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": load_traffic(dom),
                             "avg_launch_ms": dur, "x_sweep_ms": kx, "y_sweep_ms": ky,
                             "flops_per_launch": flops, "x_config": fused["x_config"],
-                            "y_config": fused["y_config"]}
+                            "y_config": fused["y_config"],
+                            # issue-side view of the same kernel from the committed counters:
+                            # the flop count above weighs a divide or a 1/7 power as one
+                            "valu_busy": load_counters(dom).get("valu_busy"),
+                            "valu_instr_per_64_cells": load_counters(dom).get("valu_instr_per_64_cells")}
     if not a.no_aux:
         aux = bandwidth_chains()
         f32 = run_gpu(H.MODE_FUSED, a.steps, a.warmup, U0, False, dtype=torch.float32)
