@@ -226,8 +226,11 @@ typedef struct {
     int variant;    /* family-specific kernel variant, 0 = default.
                        EULER_X / EULER_Y: 0 register budget free, 1 at least
                        4 waves per SIMD, 2 at least 5, 3 LDS-ring strip
-                       kernel (y: block = 64 columns x 2, 4 or 8 rows; a
-                       segment of seg rows walks seg + 1 chunk rows).
+                       kernel (y: block = 64 columns x 2, 4 or 8 rows,
+                       segments of seg rows; x: one row, block = 64, 128
+                       or 256 cells per chunk, segments of seg cells, 0 =
+                       whole rows; a segment of seg cells walks seg + 1
+                       chunk positions).
                        HDIFF: row prefetch depth 1 -> 1, 2 -> 2, 4 -> 8,
                        otherwise 4; + 8 DPP lane exchange; + 16
                        non-temporal output stores.  LAP7_CHAIN: tile shape
