@@ -338,7 +338,7 @@ __device__ __forceinline__ double strip(const EArgs<T> &a, const EView<T> &v, bo
             return s < 0 ? s + L::RW : s;
         };
         // stage 1: the cell entering the window.  The previous chunk read
-        // these primitive slots in its stage 2, and three barriers have
+        // these primitive slots in its stage 2, and two barriers have
         // passed since (the prologue's reads: the barrier before the loop)
         T un[4];
         if (act) {
@@ -359,15 +359,14 @@ __device__ __forceinline__ double strip(const EArgs<T> &a, const EView<T> &v, bo
         }
         __syncthreads();
         // stage 3: Riemann problem and flux at interface p-1/2; the flux
-        // takes the slot of the plus face of cell p-1 once every lane holds
-        // its left state
+        // takes the slot of the plus face of cell p-1, whose only reader is
+        // this lane (just above), so no barrier separates the two
         T Lf[4];
         if (act) {
             const int sm = sl(-1);
 #pragma unroll
             for (int k = 0; k < 4; ++k) Lf[k] = S.fF[k][sm][wl];
         }
-        __syncthreads();
         if (act) {
             T G[4], F[4];
             riemann_T<T, G14>(Lf, minus, g, a.niter, G);

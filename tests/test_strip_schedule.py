@@ -8,9 +8,10 @@ wave q W / 64 (W = 64 lines: one wave per q; W = 1: 64 values of q per
 wave, in program order).  The model follows the kernel's
 stages: prologue (three primitive states, then the first plus face by
 wave 0), then per chunk: (1) the primitive state of p + 1, (2) slopes and
-trace of p from p - 1, p, p + 1 and its plus face, (3a) the left state
-(plus face of p - 1), (3b) the flux at p - 1/2 into that slot, (4) the
-update of p - 1 from the fluxes in the slots of p - 1 and p - 2."""
+trace of p from p - 1, p, p + 1 and its plus face, (3) the left state
+(plus face of p - 1) and then, with no barrier between, the flux at
+p - 1/2 into that slot, (4) the update of p - 1 from the fluxes in the
+slots of p - 1 and p - 2."""
 import itertools
 
 import pytest
@@ -47,7 +48,6 @@ def schedule(C, W, j0, j1, prologue_barrier=True):
         barrier()
         for q, p in waves:
             acc.append((ep, wave(q), "f", slot(p - 1), False))
-        barrier()
         for q, p in waves:
             acc.append((ep, wave(q), "f", slot(p - 1), True))
         barrier()
