@@ -446,7 +446,7 @@ def main(argv=None):
                     help="only time one bandwidth-bound chain, or the batched grids (for profiling)")
     a = ap.parse_args(argv)
     if a.gpus != 1:
-        print(f"bench.py: this build measures one GPU only; --gpus {a.gpus} is not supported "
+        print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported "
               "(the chains would shard along the slowest axis with one halo exchange per chain; "
               "that path is not built)", file=sys.stderr)
         return 2

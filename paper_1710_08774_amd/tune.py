@@ -6,7 +6,7 @@
   `load_db` installs a database into the planner's tuning table, which
   `hfav_plan(..., HFAV_CONFIG_TUNED)` reads (nearest shape bucket);
 * `autotune`  times every feasible configuration of a star chain (exhaustive
-  search, the judge of the model's regret);
+  search, the reference the model's regret is measured against);
 * `collect`   builds a training set of (features, log time per cell) from the
   autotuner's timings on seeded random chains;
 * `train`     fits the cost-model MLP on the GPU with the library's own
