@@ -3,7 +3,8 @@ configurations bench.py times (the planner defaults).
 
 * 7-point chain (biharmonic update) 512^3: FP64 bit for bit against the
   oracle; FP32 storage with the per-field error against the FP64 oracle;
-* hydro 2048^2 with FP32 state, 100 steps, per-field error;
+* hydro 2048^2, 100 steps (the workload's full length): FP64 within 1e-12
+  of the oracle, and FP32 state with the per-field error;
 * the 512-grid batch: every grid after 2 steps, and 16 seeded grids after
   50 steps, against the oracle.
 The per-field reports go to gpurun_out/precision_*.json.
@@ -72,7 +73,27 @@ def test_biharm_512_f32_error(biharm_512):
     assert err <= 20 * U32
 
 
-def test_hydro_f32_2048_hundred_steps_error():
+@pytest.fixture(scope="module")
+def hydro_2048_100():
+    U = inputs.euler_ic(2048, 2048)
+    ref, dts = oracle.euler_run(U, 100)
+    return U, ref, dts
+
+
+def test_hydro_f64_2048_hundred_steps_parity(hydro_2048_100):
+    """The benchmark workload at its full length: 100 fused steps of the
+    2048^2 FP64 state in the default launch configuration, every cell
+    within 1e-12 (max-norm relative per field) of the oracle's 100 steps."""
+    U, ref, _ = hydro_2048_100
+    st = EulerStepper(2048, 2048)
+    st.load(U)
+    st.step(100)
+    e = hydro_errs(host(st.state()), ref)
+    print("hydro 2048^2 FP64, 100 steps: max rel error per field", e, flush=True)
+    assert max(e) <= 1e-12
+
+
+def test_hydro_f32_2048_hundred_steps_error(hydro_2048_100):
     """FP32 state, FP64 Riemann iteration and update accumulation, 100 steps
     of the 2048^2 workload.  Bound, per physical field (density, momentum
     vector, energy), on the L1 relative error sum|got-ref| / sum|ref|: the
@@ -86,8 +107,7 @@ def test_hydro_f32_2048_hundred_steps_error():
     own.  Max-norm and per-component errors are reported."""
     nx = ny = 2048
     steps = 100
-    U = inputs.euler_ic(nx, ny)
-    ref, _ = oracle.euler_run(U, steps)
+    U, ref, _ = hydro_2048_100
     st = EulerStepper(nx, ny, dtype=torch.float32)
     st.load(U)
     st.step(steps)
