@@ -1,6 +1,7 @@
 """GPU parity at the benchmark workloads' full sizes, in the launch
 configurations bench.py times (the planner defaults).
 
+* horizontal diffusion 64 x 2048^2 FP64: bit for bit against the oracle;
 * 7-point chain (biharmonic update) 512^3: FP64 bit for bit against the
   oracle; FP32 storage with the per-field error against the FP64 oracle;
 * hydro 2048^2, 100 steps (the workload's full length): FP64 within 1e-12
@@ -31,6 +32,26 @@ def _report(name, data):
     with open(os.path.join("gpurun_out", f"precision_{name}.json"), "w") as f:
         json.dump(data, f, indent=1)
     print(name, json.dumps(data), flush=True)
+
+
+def test_hdiff_64x2048x2048_bitwise():
+    """The diffusion chain at its measurement size in the launch
+    configuration bench.py times, every output element equal to the
+    oracle's."""
+    nk, nj, ni = 64, 2048, 2048
+    a = inputs.hdiff_input(nk, nj, ni)
+    ref = oracle.hdiff(a)
+    c = H.Chain(H.hdiff_spec())
+    info = c.plan((ni, nj, nk))
+    assert info.fused
+    u = dev(a)
+    del a
+    out = torch.empty_like(u)
+    c.execute([u], [out])
+    got = host(out)
+    del u, out
+    torch.cuda.empty_cache()
+    assert np.array_equal(got, ref)
 
 
 @pytest.fixture(scope="module")
