@@ -169,21 +169,18 @@ def test_norm_f32_elementwise_bound():
         assert excess <= 1.0
 
 
-def test_norm_full_size_sampled_rows():
+def test_norm_full_size_all_rows():
     """The bench workload, 4 fields x 4096 rows x 4096 cells, in the
-    configuration the bench times: 64 sampled rows against the oracle (rows
-    are independent, so the oracle computes exactly these), and the unit
-    norm of every row's d."""
+    configuration the bench times: every row against the oracle (within
+    1e-12 per field and for the norms), and the unit norm of every row's d."""
     nq, nj, ni, c = 4, 4096, 4096, 1.0
     u = inputs.norm_input(nq, nj, ni)
     got, n, info = run_chain(u, (ni, nj), c=c)
     assert info.fused and info.family == 8
-    rows = np.sort(inputs.rng_for(inputs.BASE_SEED + 94).choice(nj, 64, replace=False))
-    rows[0] = 0                                            # a constant row
-    ref, nref = oracle.normalize(u[:, rows], c, norms=True)
+    ref, nref = oracle.normalize(u, c, norms=True)
     for q in range(nq):
-        assert relerr(got[q][rows], ref[q]) <= TOL
-    assert relerr(n[rows], nref) <= TOL
+        assert relerr(got[q], ref[q]) <= TOL
+    assert relerr(n, nref) <= TOL
     d = u - got
     s = (d ** 2).sum(axis=(0, 2))
     nz = n > 0
