@@ -1,11 +1,13 @@
 """GPU parity at the benchmark workloads' full sizes, in the launch
 configurations bench.py times (the planner defaults).
 
-* horizontal diffusion 64 x 2048^2 FP64: bit for bit against the oracle;
+* horizontal diffusion 64 x 2048^2 FP64: bit for bit against the oracle,
+  out of place and written over its input;
 * 7-point chain (biharmonic update) 512^3: FP64 bit for bit against the
   oracle; FP32 storage with the per-field error against the FP64 oracle;
 * hydro 2048^2, 100 steps (the workload's full length): FP64 within 1e-12
-  of the oracle, and FP32 state with the per-field error;
+  of the oracle, and FP32 state with the per-field error; both sweeps in
+  one kernel, 2 steps, within 1e-12;
 * the 512-grid batch: every grid after 2 steps, and 16 seeded grids after
   50 steps, against the oracle.
 The per-field reports go to gpurun_out/precision_*.json.
@@ -52,6 +54,38 @@ def test_hdiff_64x2048x2048_bitwise():
     del u, out
     torch.cuda.empty_cache()
     assert np.array_equal(got, ref)
+
+
+def test_hdiff_64x2048x2048_in_place_bitwise():
+    """The diffusion chain written over its input at the measurement size,
+    in the configuration bench.py times (halo copies, then the in-place
+    kernel): equal to the oracle's out-of-place result."""
+    nk, nj, ni = 64, 2048, 2048
+    a = inputs.hdiff_input(nk, nj, ni, seed=inputs.BASE_SEED + 95)
+    ref = oracle.hdiff(a)
+    c = H.Chain(H.hdiff_spec())
+    c.alias("out", "u")
+    info = c.plan((ni, nj, nk))
+    assert c.plan_json()["aliases"][0]["handling"] == "tile_halo_copies"
+    u = dev(a)
+    del a
+    ws = torch.empty(max(1, info.workspace_bytes), dtype=torch.uint8, device="cuda")
+    c.execute([u], [u], ws)
+    got = host(u)
+    del u, ws
+    torch.cuda.empty_cache()
+    assert np.array_equal(got, ref)
+
+
+def test_euler_both_sweeps_one_kernel_2048_two_steps():
+    """The two-sweep kernel (x then y of a step in one launch) on the 2048^2
+    workload, default configuration, 2 steps within 1e-12 of the oracle."""
+    U = inputs.euler_ic(2048, 2048)
+    ref, _ = oracle.euler_run(U, 2)
+    st = EulerStepper(2048, 2048, fused_step=True)
+    st.load(U)
+    st.step(2)
+    assert max(hydro_errs(host(st.state()), ref)) <= 1e-12
 
 
 @pytest.fixture(scope="module")
