@@ -406,6 +406,39 @@ int hfav_plan_term(const hfav_chain *chain, int index, hfav_term_info *info);
  * configuration); valid until the next call on this thread.  NULL on error. */
 const char *hfav_plan_json(const hfav_chain *chain);
 
+/* ------------------------------------------------------- nest fusion */
+/* An iteration nest as rule ids per phase (Design, "Iteration nests": a
+ * prologue, a steady state and an epilogue around the loops of its rank). */
+typedef struct {
+    int rank;                           /* rank of the iteration space */
+    int n_prologue, n_steady, n_epilogue;
+    int prologue[HFAV_MAX_RULES];       /* rule ids in [0, n_rules) */
+    int steady[HFAV_MAX_RULES];
+    int epilogue[HFAV_MAX_RULES];
+} hfav_nest;
+
+/* The nest-fusion walk of the planner (Design, "Fusion": fuse_inest_dag and
+ * fuse_inest) on caller-given nests, so that nests a concrete chain never
+ * hands the walk (a later nest with its own prologue or epilogue) can be
+ * fused too.  nests[0..n) are visited in order with one fusing nest; a nest
+ * joins it when fuse_inest allows, otherwise the fusing nest is closed and
+ * the nest starts the next one.  Equal ranks fuse phase by phase when
+ * (A.prologue <= B.steady), (B.prologue <= A.steady), (A.steady <=
+ * B.epilogue) and (B.steady <= A.epilogue) all hold, where (R <= S) means no
+ * rule of S is, or depends on, a rule of R.  Unequal ranks: the lower-rank
+ * nest goes into the prologue of the higher one if it can precede that
+ * nest's steady state and epilogue, else into its epilogue if the higher
+ * nest's prologue and steady state can precede it, else the pair is
+ * unfusable.  reach: n_rules * n_rules bytes (host), reach[a * n_rules + b]
+ * nonzero when rule b depends on rule a through a path of dataflow edges
+ * (a transitively closed relation).  out: host array with room for n nests;
+ * *n_out receives their number.  Host only, allocates nothing the caller
+ * must free.  Errors: EINVAL (null pointer, n_rules not in [1,
+ * HFAV_MAX_RULES], a phase count or rule id out of range, a fused phase
+ * longer than HFAV_MAX_RULES). */
+int hfav_fuse_nests(int n_rules, const unsigned char *reach, int n, const hfav_nest *nests,
+                    hfav_nest *out, int *n_out);
+
 #ifdef __cplusplus
 }
 #endif

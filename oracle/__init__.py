@@ -55,7 +55,7 @@ def _load():
     lib.oracle_mlp_nparams.argtypes = [C.c_int, C.c_int]
     lib.oracle_mlp_nparams.restype = C.c_size_t
     lib.oracle_mlp_forward.argtypes = [C.c_int, C.c_int, C.c_int, _dp, _dp, _dp]
-    lib.oracle_mlp_forward.restype = None
+    lib.oracle_mlp_forward.restype = C.c_int
     lib.oracle_mlp_loss_grad.argtypes = [C.c_int, C.c_int, C.c_int, _dp, _dp, _dp, _dp]
     lib.oracle_mlp_loss_grad.restype = C.c_double
     lib.oracle_adam_step.argtypes = [C.c_size_t, _dp, _dp, _dp, _dp, C.c_double, C.c_double,
@@ -259,7 +259,8 @@ def mlp_forward(x, P, H=64):
     X = _f64(x)
     n, d = X.shape
     y = np.empty(n)
-    _load().oracle_mlp_forward(n, d, H, _ptr(X), _ptr(_f64(P)), _ptr(y))
+    if _load().oracle_mlp_forward(n, d, H, _ptr(X), _ptr(_f64(P)), _ptr(y)) != 0:
+        raise ValueError(f"oracle MLP forward supports 1 <= H <= 512 hidden units, got {H}")
     return y
 
 
@@ -268,6 +269,8 @@ def mlp_loss_grad(x, t, P, H=64):
     T = _f64(t)
     Pp = _f64(P)
     n, d = X.shape
+    if not 1 <= H <= 512:
+        raise ValueError(f"oracle MLP gradient supports 1 <= H <= 512 hidden units, got {H}")
     G = np.empty_like(Pp)
     loss = _load().oracle_mlp_loss_grad(n, d, H, _ptr(X), _ptr(T), _ptr(Pp), _ptr(G))
     return loss, G

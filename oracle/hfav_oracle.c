@@ -659,19 +659,20 @@ static void dense(const double *W, const double *b, const double *x, double *y,
     }
 }
 
-void oracle_mlp_forward(int n, int d, int H, const double *x, const double *P, double *y)
+int oracle_mlp_forward(int n, int d, int H, const double *x, const double *P, double *y)
 {
+    if (H < 1 || H > 512) return ORA_EARG;   /* hidden activations live on the stack */
     const double *W1 = P, *b1 = W1 + (size_t)H * d, *W2 = b1 + H, *b2 = W2 + (size_t)H * H;
     const double *W3 = b2 + H, *b3 = W3 + (size_t)H * H, *W4 = b3 + H, *b4 = W4 + H;
     #pragma omp parallel for
     for (int s = 0; s < n; ++s) {
         double h1[512], h2[512], h3[512];
-        if (H > 512) continue;
         dense(W1, b1, x + (size_t)s * d, h1, H, d, 1);
         dense(W2, b2, h1, h2, H, H, 1);
         dense(W3, b3, h2, h3, H, H, 1);
         dense(W4, b4, h3, y + s, 1, H, 0);
     }
+    return 0;
 }
 
 /* Loss L = mean_s (y_s - t_s)^2 and its gradient with respect to every

@@ -95,17 +95,43 @@ bool fuse_inest(const Reach &D, const HNest &A, const HNest &B, HNest &out) {
     const bool before = dataflow_le(D, lo_all, hi_body);
     const bool after = dataflow_le(D, hi_head, lo_all);
     out = hi;
-    if (before) {                       // broadcast: lower nest in the prologue
-        std::vector<int> p = lo_all;
-        append(p, hi.prologue);
-        out.prologue = p;
+    // inside the phase that receives it, the lower nest goes ahead of the
+    // prologue's own rules and after the epilogue's, unless the dataflow
+    // between them asks for the other order
+    auto merge = [&](const std::vector<int> &phase, bool lo_first, std::vector<int> &dst) {
+        const bool lo_before = dataflow_le(D, lo_all, phase), lo_after = dataflow_le(D, phase, lo_all);
+        if (!lo_before && !lo_after) return false;
+        if (lo_before && (lo_first || !lo_after)) {
+            dst = lo_all;
+            append(dst, phase);
+        } else {
+            dst = phase;
+            append(dst, lo_all);
+        }
         return true;
-    }
-    if (after) {                        // after the steady state: epilogue
-        append(out.epilogue, lo_all);
-        return true;
-    }
+    };
+    if (before && merge(hi.prologue, true, out.prologue)) return true;    // broadcast: prologue
+    if (after && merge(hi.epilogue, false, out.epilogue)) return true;    // after the steady state: epilogue
+    out = HNest{};
     return false;
+}
+
+// fuse_inest_dag: walk the nests in the given (topological) order keeping
+// one fusing nest; a nest that cannot join it closes it and starts the next
+std::vector<HNest> fuse_inest_dag(const Reach &D, const std::vector<HNest> &initial) {
+    std::vector<HNest> nests;
+    if (initial.empty()) return nests;
+    HNest cur = initial[0];
+    for (size_t q = 1; q < initial.size(); ++q) {
+        HNest fused;
+        if (fuse_inest(D, cur, initial[q], fused)) cur = fused;
+        else {                          // split: close the fusing nest
+            nests.push_back(cur);
+            cur = initial[q];
+        }
+    }
+    nests.push_back(cur);
+    return nests;
 }
 
 int phase_of(const HNest &N, int r) {
@@ -644,18 +670,7 @@ int hfav_plan_impl(hfav_chain *c, const hfav_plan_opts *o, hfav_plan_info *info)
         n.steady = {r};
         initial.push_back(n);
     }
-    if (!initial.empty()) {
-        HNest cur = initial[0];
-        for (size_t q = 1; q < initial.size(); ++q) {
-            HNest fused;
-            if (fuse_inest(D, cur, initial[q], fused)) cur = fused;
-            else {                      // split: close the fusing nest
-                p.nests.push_back(cur);
-                cur = initial[q];
-            }
-        }
-        p.nests.push_back(cur);
-    }
+    p.nests = fuse_inest_dag(D, initial);
     if ((int)p.nests.size() > HFAV_MAX_NESTS) return hfav_fail(HFAV_EUNSUP, "too many nests after fusion");
 
     // ---- Minkowski extents, backward from the goals
@@ -1222,4 +1237,51 @@ extern "C" const char *hfav_plan_json(const hfav_chain *c) {
         return nullptr;
     }
     return c->plan.json.c_str();
+}
+
+// The nest-fusion walk on caller-given nests and dependences (the planner
+// applies the same routine to its one-nest-per-rule DAG).
+extern "C" int hfav_fuse_nests(int n_rules, const unsigned char *reach, int n, const hfav_nest *nests,
+                               hfav_nest *out, int *n_out) {
+    if (n_rules < 1 || n_rules > HFAV_MAX_RULES || !reach || n < 0 || (n > 0 && !nests) || !out || !n_out)
+        return hfav_fail(HFAV_EINVAL, "hfav_fuse_nests: bad arguments");
+    Reach D{n_rules, std::vector<char>((size_t)n_rules * n_rules, 0)};
+    for (int a = 0; a < n_rules; ++a)
+        for (int b = 0; b < n_rules; ++b) D.m[(size_t)a * n_rules + b] = reach[(size_t)a * n_rules + b] != 0;
+    std::vector<HNest> in;
+    auto take = [&](int cnt, const int *ids, std::vector<int> &dst) {
+        if (cnt < 0 || cnt > HFAV_MAX_RULES) return false;
+        for (int q = 0; q < cnt; ++q) {
+            if (ids[q] < 0 || ids[q] >= n_rules) return false;
+            dst.push_back(ids[q]);
+        }
+        return true;
+    };
+    for (int q = 0; q < n; ++q) {
+        HNest N;
+        N.rank = nests[q].rank;
+        if (!take(nests[q].n_prologue, nests[q].prologue, N.prologue) ||
+            !take(nests[q].n_steady, nests[q].steady, N.steady) ||
+            !take(nests[q].n_epilogue, nests[q].epilogue, N.epilogue))
+            return hfav_fail(HFAV_EINVAL, "hfav_fuse_nests: phase count or rule id out of range");
+        in.push_back(N);
+    }
+    const std::vector<HNest> res = fuse_inest_dag(D, in);
+    for (size_t q = 0; q < res.size(); ++q) {
+        const HNest &N = res[q];
+        if (N.prologue.size() > HFAV_MAX_RULES || N.steady.size() > HFAV_MAX_RULES ||
+            N.epilogue.size() > HFAV_MAX_RULES)
+            return hfav_fail(HFAV_EINVAL, "hfav_fuse_nests: a fused phase exceeds HFAV_MAX_RULES rules");
+        hfav_nest &o = out[q];
+        memset(&o, 0, sizeof(o));
+        o.rank = N.rank;
+        o.n_prologue = (int)N.prologue.size();
+        o.n_steady = (int)N.steady.size();
+        o.n_epilogue = (int)N.epilogue.size();
+        std::copy(N.prologue.begin(), N.prologue.end(), o.prologue);
+        std::copy(N.steady.begin(), N.steady.end(), o.steady);
+        std::copy(N.epilogue.begin(), N.epilogue.end(), o.epilogue);
+    }
+    *n_out = (int)res.size();
+    return HFAV_OK;
 }

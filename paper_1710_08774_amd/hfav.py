@@ -93,6 +93,12 @@ class hfav_term_info(C.Structure):
                 ("window_axis", C.c_int), ("window", C.c_int)]
 
 
+class hfav_nest(C.Structure):
+    _fields_ = [("rank", C.c_int), ("n_prologue", C.c_int), ("n_steady", C.c_int), ("n_epilogue", C.c_int),
+                ("prologue", C.c_int * MAX_RULES), ("steady", C.c_int * MAX_RULES),
+                ("epilogue", C.c_int * MAX_RULES)]
+
+
 # ----------------------------------------------------------------- library
 _lib = None
 EXPORTS = ["hfav_chain_create", "hfav_chain_infer", "hfav_chain_alias", "hfav_plan", "hfav_execute", "hfav_chain_destroy", "hfav_last_error",
@@ -143,6 +149,8 @@ def lib():
     L.hfav_costmodel_set.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
     L.hfav_costmodel_predict.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(hfav_config),
                                          C.POINTER(C.c_float)]
+    L.hfav_fuse_nests.argtypes = [C.c_int, C.POINTER(C.c_ubyte), C.c_int, C.POINTER(hfav_nest),
+                                  C.POINTER(hfav_nest), C.POINTER(C.c_int)]
     L.hfav_tuning_clear.restype = None
     L.hfav_tuning_add.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(hfav_config)]
     _lib = L
@@ -337,6 +345,32 @@ def chain_create(spec: ChainSpec) -> Chain:
 def chain_infer(spec: ChainSpec) -> Chain:
     """Chain inferred from rule patterns (pattern variables "q?")."""
     return Chain(spec, infer=True)
+
+
+def fuse_nests(n_rules, reach, nests):
+    """The planner's nest-fusion walk (hfav_fuse_nests) on explicit nests.
+
+    reach: n_rules x n_rules booleans, reach[a][b] true when rule b depends on
+    rule a.  nests: sequence of (rank, prologue, steady, epilogue) with rule
+    ids.  Returns the fused nests in the same form."""
+    flat = (C.c_ubyte * (n_rules * n_rules))(*[1 if reach[a][b] else 0 for a in range(n_rules)
+                                                for b in range(n_rules)])
+    src = (hfav_nest * max(1, len(nests)))()
+    for q, (rank, pro, ste, epi) in enumerate(nests):
+        n = src[q]
+        n.rank = rank
+        n.n_prologue, n.n_steady, n.n_epilogue = len(pro), len(ste), len(epi)
+        for k, r in enumerate(pro):
+            n.prologue[k] = r
+        for k, r in enumerate(ste):
+            n.steady[k] = r
+        for k, r in enumerate(epi):
+            n.epilogue[k] = r
+    out = (hfav_nest * max(1, len(nests)))()
+    n_out = C.c_int()
+    _check(lib().hfav_fuse_nests(n_rules, flat, len(nests), src, out, C.byref(n_out)))
+    return [(o.rank, list(o.prologue[:o.n_prologue]), list(o.steady[:o.n_steady]),
+             list(o.epilogue[:o.n_epilogue])) for o in out[:n_out.value]]
 
 
 def tuning_clear():

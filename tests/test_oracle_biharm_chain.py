@@ -179,3 +179,15 @@ def test_adam_constant_gradient_closed_form():
         oracle.adam_step(P, G, m, v, t, lr=1e-3, eps=0.0)
     # constant gradient: bias-corrected moments equal g and g^2, step = lr*sign(g)
     assert np.allclose(P, -10e-3 * np.sign(G), rtol=1e-12, atol=0)
+
+
+def test_mlp_hidden_width_beyond_oracle_limit_is_an_error():
+    # the oracle keeps hidden activations on the stack (at most 512 units):
+    # a wider network is refused instead of leaving outputs unset
+    d, H = 3, 513
+    P = np.zeros(oracle.mlp_nparams(d, H))
+    x = np.zeros((2, d))
+    with pytest.raises(ValueError):
+        oracle.mlp_forward(x, P, H)
+    with pytest.raises(ValueError):
+        oracle.mlp_loss_grad(x, np.zeros(2), P, H)

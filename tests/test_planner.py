@@ -363,3 +363,72 @@ def test_two_sweep_step_chain_fuses_into_one_nest():
     bad.rules[-1].inputs[-1] = ("dt2", (0, 0, 0))
     bad.axioms.append(("dt2", 0))
     assert H.Chain(bad).plan((64, 64)).family == 0
+
+
+# ------------------------------------------------------------ T-P8: fuse_inest
+def _closure(n, edges):
+    r = [[False] * n for _ in range(n)]
+    for a, b in edges:
+        r[a][b] = True
+    for k in range(n):
+        for a in range(n):
+            if r[a][k]:
+                for b in range(n):
+                    if r[k][b]:
+                        r[a][b] = True
+    return r
+
+
+# two rank-2 nests with all three phases: A = (0 | 1 | 2), B = (3 | 4 | 5)
+_A = (2, [0], [1], [2])
+_B = (2, [3], [4], [5])
+
+
+def test_fuse_inest_equal_rank_phase_by_phase():
+    """Design "Fusion": equal-rank nests fuse phase by phase when no ordering
+    check fails; forward dependences between them (A's phases feeding B's
+    same or later phases) do not prevent it."""
+    for edges in ([], [(1, 4)], [(0, 3), (0, 4), (1, 4), (1, 5), (2, 5), (0, 5)]):
+        got = H.fuse_nests(6, _closure(6, edges), [_A, _B])
+        assert got == [(2, [0, 3], [1, 4], [2, 5])], edges
+
+
+@pytest.mark.parametrize("which,edge", [
+    ("A.prologue <= B.steady", (4, 0)),    # B's steady state feeds A's prologue
+    ("B.prologue <= A.steady", (1, 3)),    # A's steady state feeds B's prologue
+    ("A.steady <= B.epilogue", (5, 1)),    # B's epilogue feeds A's steady state
+    ("B.steady <= A.epilogue", (2, 4)),    # A's epilogue feeds B's steady state
+])
+def test_fuse_inest_each_ordering_check_alone_splits(which, edge):
+    """Each of the four equal-rank checks violated alone (the other three
+    hold) leaves the nests unfused: the walk closes A and starts B."""
+    got = H.fuse_nests(6, _closure(6, [edge]), [_A, _B])
+    assert got == [_A, _B], which
+
+
+def test_fuse_inest_unequal_rank_placement():
+    """Lower-rank nest (rule 6, rank 1) against a rank-2 nest H = (0 | 1 | 2):
+    prologue when it can precede H's steady state and epilogue, epilogue
+    when H's prologue and steady state can precede it, else unfusable."""
+    Hn = (2, [0], [1], [2])
+    L = (1, [], [6], [])
+    assert H.fuse_nests(7, _closure(7, []), [Hn, L]) == [(2, [6, 0], [1], [2])]
+    assert H.fuse_nests(7, _closure(7, [(6, 1)]), [Hn, L]) == [(2, [6, 0], [1], [2])]   # broadcast
+    assert H.fuse_nests(7, _closure(7, [(1, 6)]), [Hn, L]) == [(2, [0], [1], [2, 6])]   # reduction
+    # the reduction feeds H's own epilogue: placed in the epilogue ahead of it
+    assert H.fuse_nests(7, _closure(7, [(1, 6), (6, 2)]), [Hn, L]) == [(2, [0], [1], [6, 2])]
+    # H's prologue feeds the broadcast: placed in the prologue after it
+    assert H.fuse_nests(7, _closure(7, [(0, 6), (6, 1)]), [Hn, L]) == [(2, [0, 6], [1], [2])]
+    # reached from H's epilogue and feeding H's steady state: unfusable
+    assert H.fuse_nests(7, _closure(7, [(2, 6), (6, 1)]), [Hn, L]) == [Hn, L]
+    # the walk: an unfusable nest closes the fusing nest, and the next
+    # equal-rank nest joins the new one
+    C = (1, [], [7], [])
+    got = H.fuse_nests(8, _closure(8, [(2, 6), (6, 1)]), [Hn, L, C])
+    assert got == [Hn, (1, [], [6, 7], [])]
+
+
+def test_fuse_nests_rejects_bad_arguments():
+    with pytest.raises(H.HfavError) as e:
+        H.fuse_nests(2, _closure(2, []), [(2, [], [5], [])])
+    assert e.value.code == H.EINVAL
