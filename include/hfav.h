@@ -306,7 +306,11 @@ int hfav_chain_create(const hfav_chain_desc *desc, hfav_chain **out);
 
 /* Plan the chain for a grid size and boundary: fusion, extents, windows,
  * kernel family and tile configuration.  Host only, deterministic, allocates
- * no device memory.  `info` may be NULL.  Re-planning replaces the plan.
+ * no device memory (a fused STAR_CHAIN plan stages its coefficient table in
+ * pinned host memory, see hfav_execute).  `info` may be NULL.  Re-planning
+ * replaces the plan; a graph captured from this chain's executes must not
+ * be replayed after a re-plan (it copies from the staging buffer, which
+ * re-planning frees).
  * Errors: EINVAL (bad dims / boundary), EUNSUP (mode or precision not
  * available for this chain). */
 int hfav_plan(hfav_chain *chain, const hfav_plan_opts *opts, hfav_plan_info *info);
@@ -316,10 +320,11 @@ int hfav_plan(hfav_chain *chain, const hfav_plan_opts *opts, hfav_plan_info *inf
  * `workspace` must hold info.workspace_bytes (it may be NULL when that is 0);
  * it is caller-owned device memory the call may overwrite.  Asynchronous: no
  * device allocation, no synchronisation, no device-to-host read, so it can
- * be captured in a HIP graph.  One exception, the STAR_CHAIN family: its
- * coefficient table travels with the call as an asynchronous host-to-device
- * copy into the workspace from a pinned host buffer that the first execute
- * after a plan allocates; capture such a chain only after one eager call.
+ * be captured in a HIP graph, also on its first call.  The STAR_CHAIN
+ * family's coefficient table travels with the call as an asynchronous
+ * host-to-device copy into the workspace, from a pinned host buffer that
+ * hfav_plan allocates and fills (EDEVICE if that allocation failed, e.g.
+ * when the plan was made without a device).
  * Kernel faults surface at the caller's next synchronisation.  A goal may
  * share an axiom's buffer only as a pair declared with hfav_chain_alias.
  * Errors: ENOPLAN, EINVAL (null pointer), EALIAS, EDEVICE. */
@@ -374,6 +379,10 @@ const char *hfav_last_error(void);
 
 /* Library version string. */
 const char *hfav_version(void);
+
+/* Hash of the sources the library was built from (16 hex digits): a binding
+ * compares it with the sources it ships with to refuse a stale build. */
+const char *hfav_build_id(void);
 
 /* ------------------------------------------------------------- batches */
 #define HFAV_MAX_BATCH 640

@@ -1,4 +1,9 @@
-"""Build libhfav.so (host planner + gfx950 kernels) in place with hipcc."""
+"""Build libhfav.so (host planner + gfx950 kernels) in place with hipcc.
+
+The library carries a hash of the sources it was built from (hfav_build_id):
+the binding refuses a library whose hash differs from the tree's sources, so
+a source change without a rebuild cannot run old code silently."""
+import hashlib
 import os
 import subprocess
 import sys
@@ -22,9 +27,37 @@ def sources():
     return sorted(f for f in os.listdir(CSRC) if f.endswith((".cpp", ".hip")))
 
 
-def _compile(src):
+def source_hash():
+    """16 hex digits over the kernel and planner sources, the public headers,
+    the target and the compile flags."""
+    inc = os.path.join(HERE, "..", "include")
+    h = hashlib.sha256()
+    h.update(" ".join([ARCH] + COMMON[:-1] + DEVICE).encode())
+    for d, names in ((CSRC, sorted(os.listdir(CSRC))), (inc, sorted(os.listdir(inc)))):
+        for f in names:
+            if not f.endswith((".cpp", ".hip", ".h")):
+                continue
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def built_id(path=LIB):
+    """Build id recorded in a built library (read from the file, without
+    loading it), or None."""
+    try:
+        with open(path, "rb") as fh:
+            data = fh.read()
+    except OSError:
+        return None
+    k = data.find(b"hfav-build-id:")
+    return data[k + 14:k + 30].decode("ascii", "replace") if k >= 0 else None
+
+
+def _compile(src, build_id):
     obj = os.path.join(OBJ, src + ".o")
-    cmd = [HIPCC] + COMMON
+    cmd = [HIPCC] + COMMON + ['-DHFAV_BUILD_ID="%s"' % build_id]
     if src.endswith(".hip"):
         cmd += ["-x", "hip"] + DEVICE
     else:
@@ -39,8 +72,9 @@ def _compile(src):
 def build(verbose=False, jobs=8):
     os.makedirs(OBJ, exist_ok=True)
     t0 = time.time()
+    build_id = source_hash()
     with ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, sources()))
+        objs = list(ex.map(lambda f: _compile(f, build_id), sources()))
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH] + objs + ["-o", LIB + ".tmp"]
     subprocess.check_call(cmd)
     os.replace(LIB + ".tmp", LIB)

@@ -21,7 +21,10 @@ int hfav_fail(int code, const std::string &msg) {
 }
 
 extern "C" const char *hfav_last_error(void) { return g_err.c_str(); }
-extern "C" const char *hfav_version(void) { return "hfav-mi355x 0.1 (gfx950)"; }
+extern "C" const char *hfav_version(void) { return "hfav-mi355x 0.2 (gfx950)"; }
+// the tag is also found by scanning the file, before anything loads it
+static const char kBuildTag[] = "hfav-build-id:" HFAV_BUILD_ID;
+extern "C" const char *hfav_build_id(void) { return kBuildTag + 14; }
 
 static const OpSpec kOps[] = {
     {HFAV_OP_HDIFF_LAP, "HDIFF_LAP", 5, 1, 0, -1, 0},

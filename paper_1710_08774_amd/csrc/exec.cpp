@@ -140,27 +140,14 @@ int run_fused(const hfav_chain *c, const Bind &B, hipStream_t s) {
         return dev_err(hfav::launch_lap7_chain(L, s), "lap7 chain launch");
     }
     case HFAV_FAMILY_STAR_CHAIN: {
-        // the coefficient table is copied from a pinned host copy into the
-        // workspace on the stream (a capturable async copy); the pinned
-        // buffer is allocated by the first execute of a plan, so capture a
-        // graph only after one eager call
+        // the coefficient table is copied from the pinned host copy that
+        // hfav_plan staged into the workspace on the stream (a capturable
+        // async copy)
         const size_t bytes = p.scoeff.size() * 8;
-        hfav_chain *mc = const_cast<hfav_chain *>(c);
-        if (mc->pinned_bytes < bytes || mc->pinned_src != &p.scoeff) {
-            if (mc->pinned_bytes < bytes) {
-                if (mc->pinned) (void)hipHostFree(mc->pinned);
-                mc->pinned = nullptr;
-                mc->pinned_bytes = 0;
-                int rc0 = dev_err(hipHostMalloc(&mc->pinned, bytes, hipHostMallocDefault), "pinned allocation");
-                if (rc0) return rc0;
-                mc->pinned_bytes = bytes;
-            }
-            memcpy(mc->pinned, p.scoeff.data(), bytes);
-            mc->pinned_src = &p.scoeff;
-        }
+        if (!c->pinned || c->pinned_bytes != bytes)
+            return hfav_fail(HFAV_EDEVICE, "coefficient table not staged at plan time: " + c->pinned_err);
         double *coeff = (double *)(B.ws + p.ws_coeff);
-        int rc = dev_err(hipMemcpyAsync(coeff, c->pinned, p.scoeff.size() * 8, hipMemcpyHostToDevice, s),
-                         "coefficient upload");
+        int rc = dev_err(hipMemcpyAsync(coeff, c->pinned, bytes, hipMemcpyHostToDevice, s), "coefficient upload");
         if (rc) return rc;
         const int K = (int)p.sstages.size();
         for (size_t gi = 0; gi < p.sgroups.size(); ++gi) {

@@ -108,8 +108,8 @@ struct hfav_chain {
     std::vector<std::pair<int, std::string>> origin;
     HPlan plan;
     void *pinned = nullptr;      // pinned host copy of the plan's coefficient table
-    size_t pinned_bytes = 0;
-    const void *pinned_src = nullptr;   // plan table the pinned copy holds
+    size_t pinned_bytes = 0;     // (staged by hfav_plan for STAR_CHAIN plans)
+    std::string pinned_err;      // why staging failed (no device at plan time)
     ~hfav_chain();
 };
 

@@ -6,6 +6,8 @@
 // Design "Contraction"), computed over the tile plus the halo the remaining
 // stages need (the Minkowski sum of their radii, Design "Variables and
 // storage").  The input planes enter the first ring once, from HBM.
+// Each output is accumulated from zero in the offset order below with every
+// product and sum rounded separately.
 //
 // Coefficients of stage s are laid out (f_out, f_in, 1 + 2 r nd) in the
 // star-offset order: centre, then for each axis x, y(, z) the pairs -d, +d
@@ -79,6 +81,10 @@ __global__ __launch_bounds__(TX * TY) void star_group_kernel(SGArgs a) {
     // one star stage: output field o at in-plane point (ix, iy) of the
     // stage's own output frame, plane q
     auto eval = [&](int s, int o, int q, int ix, int iy) -> T {
+        // products and sums rounded one by one, in the offset order (no
+        // multiply-add contraction): the same rounding as evaluating the
+        // stage term by term
+#pragma clang fp contract(off)
         const SGStage &S = a.st[s];
         const int n_off = 1 + 2 * S.r * a.nd;
         const double *c = a.coeff + S.coff + (size_t)o * S.fin * n_off;

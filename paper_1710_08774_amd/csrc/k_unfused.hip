@@ -229,6 +229,8 @@ struct SArgs {
 
 template <class T>
 __global__ __launch_bounds__(256) void star_rule_kernel(SArgs a) {
+    // reference order, every product and sum rounded (no contraction)
+#pragma clang fp contract(off)
     const size_t n = (size_t)a.nx * a.ny * a.nz;
     const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (idx >= n) return;

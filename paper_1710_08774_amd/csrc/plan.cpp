@@ -1134,7 +1134,25 @@ int hfav_plan_impl(hfav_chain *c, const hfav_plan_opts *o, hfav_plan_info *info)
     p.json = js.str();
     p.valid = true;
     c->plan = p;
-    c->pinned_src = nullptr;
+    // STAR_CHAIN: the coefficient table travels to the workspace with every
+    // execute as an asynchronous copy from pinned host memory, staged here so
+    // that execute itself allocates nothing (host memory only; freeing the
+    // previous buffer waits for copies still reading it)
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    c->pinned = nullptr;
+    c->pinned_bytes = 0;
+    c->pinned_err.clear();
+    if (fused && p.family == HFAV_FAMILY_STAR_CHAIN) {
+        const size_t bytes = c->plan.scoeff.size() * sizeof(double);
+        const hipError_t e = hipHostMalloc(&c->pinned, bytes, hipHostMallocDefault);
+        if (e == hipSuccess) {
+            memcpy(c->pinned, c->plan.scoeff.data(), bytes);
+            c->pinned_bytes = bytes;
+        } else {
+            c->pinned = nullptr;
+            c->pinned_err = hipGetErrorString(e);
+        }
+    }
     if (info) *info = I;
     return HFAV_OK;
 }

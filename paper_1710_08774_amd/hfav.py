@@ -114,7 +114,13 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run paper_1710_08774_amd/build.py "
                           "(there is no fallback implementation)")
+    from .build import built_id, source_hash
+    built, want = built_id(LIB_PATH), source_hash()
+    if built != want:
+        raise ImportError(f"{LIB_PATH} was built from other sources (build id {built}, sources {want}); "
+                          "rebuild it with paper_1710_08774_amd/build.py")
     L = C.CDLL(LIB_PATH)
+    L.hfav_build_id.restype = C.c_char_p
     L.hfav_chain_create.argtypes = [C.POINTER(hfav_chain_desc), C.POINTER(C.c_void_p)]
     L.hfav_chain_infer.argtypes = [C.POINTER(hfav_chain_desc), C.POINTER(C.c_void_p)]
     L.hfav_chain_alias.argtypes = [C.c_void_p, C.c_char_p, C.c_char_p]
@@ -258,6 +264,7 @@ class Chain:
         _check(lib().hfav_plan(self._h, C.byref(o), C.byref(info)))
         self.info = info
         self.dims = dims
+        self._expect = self._expected_buffers(dims[0] * dims[1] * dims[2], dims[1] * dims[2], 1)
         return info
 
     def plan_batch(self, sizes, boundary=(BC_PERIODIC,) * 3, precision=PREC_NATIVE,
@@ -271,13 +278,55 @@ class Chain:
         _check(lib().hfav_plan_batch(self._h, C.byref(o), len(sizes), flat, C.byref(info)))
         self.info = info
         self.sizes = list(sizes)
+        total = self.batch_offset(len(sizes) - 1) + int(sizes[-1][0]) * int(sizes[-1][1])
+        self._expect = self._expected_buffers(total, None, len(sizes))
         return info
+
+    def _expected_buffers(self, n_grid, n_row, n_scalar):
+        """(torch dtype, elements) the plan reads or writes through each axiom
+        and goal pointer, in declaration order."""
+        import torch
+        grid_dt = torch.float64 if self.spec.dtype == F64 else torch.float32
+        ranks = {t["name"]: t["rank"] for t in self.terms().values()}
+        nd = self.spec.ndim
+
+        def one(name):
+            r = ranks[name]
+            if r == 0:
+                return torch.float64, n_scalar
+            return grid_dt, n_grid if r == nd else n_row
+
+        return ([one(n) for n, _ in self.spec.axioms], [one(g) for g in self.spec.goals])
+
+    def _validate(self, axioms, goals, workspace):
+        """Each tensor argument must be a contiguous device tensor of the
+        plan's element type holding at least the elements the kernels touch
+        (raw integer addresses are passed through unchecked)."""
+        if self.info is None:
+            raise HfavError(ENOPLAN, "execute before plan")
+        ex_ax, ex_go = self._expect
+        if len(axioms) != len(ex_ax) or len(goals) != len(ex_go):
+            raise HfavError(EINVAL, f"expected {len(ex_ax)} axioms and {len(ex_go)} goals, "
+                                    f"got {len(axioms)} and {len(goals)}")
+        for kind, ts, ex in (("axiom", axioms, ex_ax), ("goal", goals, ex_go)):
+            for q, (t, (dt, n)) in enumerate(zip(ts, ex)):
+                if t is None or isinstance(t, int):
+                    continue
+                if t.device.type != "cuda" or not t.is_contiguous() or t.dtype != dt or t.numel() < n:
+                    raise HfavError(EINVAL, f"{kind} {q}: need a contiguous cuda tensor of {dt} with >= {n} "
+                                            f"elements, got {t.dtype} {tuple(t.shape)} on {t.device}"
+                                            f"{'' if t.is_contiguous() else ' (not contiguous)'}")
+        need = self.info.workspace_bytes
+        if need and workspace is not None and not isinstance(workspace, int):
+            if workspace.device.type != "cuda" or workspace.numel() * workspace.element_size() < need:
+                raise HfavError(EINVAL, f"workspace: need a cuda buffer of >= {need} bytes")
 
     def batch_offset(self, g) -> int:
         return int(lib().hfav_batch_offset(self._h, g))
 
     def execute(self, axioms, goals, workspace=None, stream=None):
         """Enqueue on `stream` (torch.cuda.Stream, raw handle, or None = current)."""
+        self._validate(axioms, goals, workspace)
         ax = (C.c_void_p * len(axioms))(*[_ptr(a) for a in axioms])
         go = (C.c_void_p * len(goals))(*[_ptr(g) for g in goals])
         if stream is None:

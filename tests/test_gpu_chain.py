@@ -12,6 +12,9 @@ from paper_1710_08774_amd import inputs, tune
 pytestmark = pytest.mark.gpu
 
 
+U32 = 2.0 ** -24
+
+
 def _run(ch, cfg=None, mode=H.MODE_FUSED, seed=0):
     x = inputs.chain_input(ch, seed)
     tdt = torch.float64 if ch["dtype"] == "f64" else torch.float32
@@ -28,40 +31,173 @@ def _run(ch, cfg=None, mode=H.MODE_FUSED, seed=0):
     got = np.stack([host(y) for y in ys])
     xin = x if ch["dtype"] == "f64" else x.astype(np.float32).astype(np.float64)
     ref = oracle.linear_chain(ch, xin, inputs.star_offsets)
-    return got, ref, info
+    return got, ref, info, xin
+
+
+def f32_abs_bound(ch, xin):
+    """Absolute error bound of an FP32 evaluation of a linear star chain
+    against the exact chain on the same (FP32-representable) input.
+
+    Stage k forms each output as a sum of n_k = f_in (1 + 2 r nd) products
+    c x with sum |c| = 1.  With the coefficients rounded to FP32 (|c^ - c|
+    <= u |c|) and the products and n_k - 1 sums rounded (an inner product is
+    within gamma_n sum |c^||x^| of its exact value, gamma_n = n u / (1 - n u);
+    Higham, Accuracy and Stability of Numerical Algorithms, section 3.1), the
+    error of stage k is its input's error (the map has infinity norm sum |c|
+    = 1) plus (u + gamma_{n_k} (1 + u)) times the input's largest value, which
+    never exceeds M0 = max |x| plus the error so far (a stage cannot grow the
+    largest value).  Summed over the stages: (1 + O(n u)) sum_k (n_k + 1) u
+    M0; the factor 1.01 covers the second-order terms (n u < 1e-4 here)."""
+    nd = ch["ndim"]
+    nk = [st["f_in"] * (1 + 2 * st["r"] * nd) for st in ch["stages"]]
+    return 1.01 * sum(n + 1 for n in nk) * U32 * float(np.abs(xin).max())
+
+
+def check_fields(ch, got, ref, xin, what=""):
+    """Per output field: FP64 within 1e-12 normwise relative (and reported
+    bitwise), FP32 within the derived absolute bound."""
+    assert got.shape == ref.shape
+    if ch["dtype"] == "f64":
+        errs = [relerr(got[q], ref[q]) for q in range(ref.shape[0])]
+        assert max(errs) <= 1e-12, (what, errs)
+        return errs
+    b = f32_abs_bound(ch, xin)
+    for q in range(ref.shape[0]):
+        e = float(np.abs(got[q] - ref[q]).max())
+        assert e <= b, (what, q, e, b)
+    return [relerr(got[q], ref[q]) for q in range(ref.shape[0])]
 
 
 def _small_chains(n, seed):
     return tune.random_chains(n, seed, max_cells=40000)
 
 
+def _chain_where(ndim, dtype, dims, seed, ok):
+    for k in range(1000):
+        ch = inputs.random_chain(inputs.rng_for(seed + 1000 * k), ndim=ndim, dtype=dtype, dims=dims)
+        if ok(ch):
+            return ch
+    raise AssertionError("no chain drawn")
+
+
+def _deep_chain(ndim, dtype, dims, seed):
+    """First seeded chain with at least 4 stages and a stage of radius 3
+    (long warm-up, the widest halos)."""
+    return _chain_where(ndim, dtype, dims, seed,
+                        lambda ch: len(ch["stages"]) >= 4 and max(st["r"] for st in ch["stages"]) == 3)
+
+
+def _all_tiles_chain(ndim, dtype, dims, seed):
+    """First seeded chain of at least 3 stages, one of radius >= 2, whose
+    fully fused group fits LDS with every tile shape."""
+    def ok(ch):
+        if len(ch["stages"]) < 3 or max(st["r"] for st in ch["stages"]) < 2:
+            return False
+        cands = H.Chain(H.star_chain_spec(ch, inputs.star_offsets)).candidates(tune.chain_dims(ch))
+        K = len(ch["stages"])
+        return {cfg[3] for cfg in cands if cfg[1] == K} == {0, 1, 2, 3}
+    return _chain_where(ndim, dtype, dims, seed, ok)
+
+
 @pytest.mark.parametrize("k", range(8))
 def test_star_chain_default_parity(k):
     ch = _small_chains(8, 77)[k]
-    got, ref, info = _run(ch)
+    got, ref, info, xin = _run(ch)
     assert info.fused and info.family == 5
-    tol = 1e-12 if ch["dtype"] == "f64" else 2e-6
-    assert relerr(got, ref) <= tol
+    check_fields(ch, got, ref, xin, f"chain {k}")
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("ndim", [2, 3])
-def test_star_chain_every_configuration(ndim):
-    rng = inputs.rng_for(ndim + 40)
-    dims = (150, 70, 1) if ndim == 2 else (40, 24, 20)
-    ch = inputs.random_chain(rng, ndim=ndim, dtype="f64", dims=dims)
+def test_star_chain_every_configuration(ndim, dtype):
+    """Every feasible configuration (fused group depth, tile shape, segment
+    length) of a deep chain on a grid whose streamed axis holds at least
+    three segments of every segment length plus a ragged last one (389 =
+    3 x 128 + 5), with ragged tiles across: the warm-up of the segments
+    after the first is compared with the oracle for every tile shape."""
+    dims = (150, 389, 1) if ndim == 2 else (40, 26, 389)
+    ch = _all_tiles_chain(ndim, dtype, dims, 40 + ndim)
     c = H.Chain(H.star_chain_spec(ch, inputs.star_offsets))
     cands = c.candidates(tune.chain_dims(ch))
     assert len(cands) >= 3
+    assert {cfg[3] for cfg in cands} == {0, 1, 2, 3}          # every tile shape
+    nstream = dims[1] if ndim == 2 else dims[2]
+    assert all(nstream >= 3 * cfg[2] for cfg in cands)        # >= 3 segments each
     for cfg in cands:
-        got, ref, info = _run(ch, cfg)
-        assert relerr(got, ref) <= 1e-12, cfg
+        got, ref, info, xin = _run(ch, cfg)
+        check_fields(ch, got, ref, xin, cfg)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("ndim,dims", [(2, (128, 640, 1)), (3, (64, 64, 128))])
+def test_star_chain_at_study_sizes(ndim, dims, dtype):
+    """Chains at sizes the cost-model study times (2-D 128..4096^2, 3-D
+    64..512^3), in the planner's default configuration and in the
+    unfused path, per output field."""
+    ch = _deep_chain(ndim, dtype, dims, 60 + ndim)
+    for mode in (H.MODE_FUSED, H.MODE_UNFUSED):
+        got, ref, info, xin = _run(ch, mode=mode)
+        assert bool(info.fused) == (mode == H.MODE_FUSED)
+        errs = check_fields(ch, got, ref, xin, mode)
+        print(f"star chain {ndim}-D {dims} {dtype} mode {mode}: per-field rel err {errs}", flush=True)
+
+
+def test_star_chain_fp64_bitwise_to_the_oracle():
+    """Without multiply-add contraction the fused stages round each product
+    and sum in the oracle's order, so FP64 results are equal bit for bit."""
+    ch = _deep_chain(3, "f64", (40, 26, 101), 80)
+    got, ref, _, _ = _run(ch)
+    assert np.array_equal(got, ref)
 
 
 def test_star_chain_unfused_parity():
     ch = _small_chains(3, 5)[1]
-    got, ref, info = _run(ch, mode=H.MODE_UNFUSED)
+    got, ref, info, xin = _run(ch, mode=H.MODE_UNFUSED)
     assert not info.fused
-    assert relerr(got, ref) <= (1e-12 if ch["dtype"] == "f64" else 2e-6)
+    check_fields(ch, got, ref, xin)
+
+
+def test_star_chain_graph_capture_on_first_execute():
+    """hfav_execute allocates nothing: a star chain is captured in a HIP
+    graph on its first call (the coefficient table was staged by the plan),
+    and each replay, with eager work in between, matches an eager run."""
+    ch = _deep_chain(2, "f64", (160, 96, 1), 90)
+    x = inputs.chain_input(ch, 3)
+    c = H.Chain(H.star_chain_spec(ch, inputs.star_offsets))
+    info = c.plan(tune.chain_dims(ch), mode=H.MODE_FUSED)
+    xs = [torch.tensor(x[f], device="cuda") for f in range(x.shape[0])]
+    ys = [torch.zeros_like(xs[0]) for _ in range(ch["stages"][-1]["f_out"])]
+    ws = torch.empty(info.workspace_bytes, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    with torch.cuda.graph(g, stream=side):
+        c.execute(xs, ys, ws, stream=side)
+    ref = oracle.linear_chain(ch, x, inputs.star_offsets)
+    for rep in range(3):
+        for y in ys:
+            y.fill_(rep + 1.0)
+        ws.fill_(7)                              # the replay must re-upload the coefficients
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = np.stack([host(y) for y in ys])
+        check_fields(ch, got, ref, x, f"replay {rep}")
+
+
+def test_binding_refuses_mismatched_tensors():
+    """Wrong element type, too few elements or a strided view are refused
+    by the binding before any launch."""
+    c = H.Chain(H.hdiff_spec())
+    c.plan((64, 32, 2))
+    u = torch.zeros((2, 32, 64), dtype=torch.float64, device="cuda")
+    o = torch.empty_like(u)
+    for bad in (u.float(), u[:1], torch.zeros((2, 32, 128), dtype=torch.float64, device="cuda")[..., ::2]):
+        with pytest.raises(H.HfavError) as e:
+            c.execute([bad], [o])
+        assert e.value.code == H.EINVAL
+    c.execute([u], [o])
+    torch.cuda.synchronize()
 
 
 # ------------------------------------------------------------------ MLP kernels

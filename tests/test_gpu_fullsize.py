@@ -143,8 +143,12 @@ def test_hydro_f64_2048_hundred_steps_parity(hydro_2048_100):
     st = EulerStepper(2048, 2048)
     st.load(U)
     st.step(100)
-    e = hydro_errs(host(st.state()), ref)
-    print("hydro 2048^2 FP64, 100 steps: max rel error per field", e, flush=True)
+    got = host(st.state())
+    e = hydro_errs(got, ref)
+    comp = dict(zip(("rho", "rho_u", "rho_v", "E"), field_errs(got, ref)))
+    _report("hydro_f64_2048x2048_100", {"max_rel_error_physical": dict(zip(("rho", "momentum", "E"), e)),
+                                        "max_rel_error_per_component": comp})
+    print("hydro 2048^2 FP64, 100 steps: max rel error per field", e, "per component", comp, flush=True)
     assert max(e) <= 1e-12
 
 
@@ -172,9 +176,15 @@ def test_hydro_f32_2048_hundred_steps_error(hydro_2048_100):
     l1 = dict(zip(names, field_l1_errs(got, ref)))
     phys = hydro_l1_errs(got, ref)
     _report("hydro_f32_2048x2048_100", {"max_rel_error": errs, "l1_rel_error": l1,
-                                        "l1_rel_error_physical": phys})
+                                        "l1_rel_error_physical": phys,
+                                        "max_rel_error_bound": 8 * steps * U32})
     for f, e in phys.items():
         assert e <= 2 * steps * U32, (f, e)
+    # max-norm per conserved component: 8 n u, stated from measurement (the
+    # largest errors sit at the discontinuities, where a rounding moves a
+    # wave by a fraction of a cell)
+    for f, e in errs.items():
+        assert e <= 8 * steps * U32, (f, e)
 
 
 @pytest.fixture(scope="module")
@@ -190,12 +200,17 @@ def test_batch_all_512_grids_two_steps(batch512):
     bt.step(2)
     torch.cuda.synchronize()
     worst = 0.0
+    worst_comp = [0.0] * 4
     for g, U in enumerate(states):
         ref, _ = oracle.euler_run(U, 2)
-        e = max(hydro_errs(host(bt.grid(g)), ref))
+        got = host(bt.grid(g))
+        e = max(hydro_errs(got, ref))
         worst = max(worst, e)
+        worst_comp = [max(a, b) for a, b in zip(worst_comp, field_errs(got, ref))]
         assert e <= 1e-12, (g, sizes[g], e)
-    print("batch 512 grids, 2 steps: worst", worst, flush=True)
+    _report("batch_512_grids_2_steps", {"worst_max_rel_error_physical": worst,
+                                        "worst_max_rel_error_per_component":
+                                            dict(zip(("rho", "rho_u", "rho_v", "E"), worst_comp))})
 
 
 def test_batch_sixteen_grids_fifty_steps(batch512):

@@ -6,8 +6,12 @@ rounded to FP32 once per sweep (relative error at most u = 2^-24 per
 element), and the Godunov scheme does not amplify perturbations in L1 (a
 monotone scheme is L1-contractive for a scalar conservation law; the working
 assumption for the system), so after n steps (2n sweeps) the error stays
-below 2n u.  Max-norm and per-component errors are reported with it in the
-JSON report in gpurun_out/."""
+below 2n u.  Beside it, the max-norm relative error of every conserved
+component (rho, rho u, rho v, E) is bounded by 8 n u, a bound stated from
+measurement: the largest max-norm errors sit in the cells of the
+discontinuities, where a rounding moves a wave by a fraction of a cell, and
+the largest measured value (rho v at 2048^2 after 100 steps, 2.1e-5) is 2.3
+times below it.  Both are reported in the JSON report in gpurun_out/."""
 import json
 import math
 import os
@@ -28,6 +32,12 @@ FIELDS = ("rho", "rho_u", "rho_v", "E")
 # (FP32 state): one FP32 rounding per sweep, accumulated linearly
 U32 = 2.0 ** -24
 BOUND_100 = {f: 2 * 100 * U32 for f in ("rho", "momentum", "E")}
+
+
+def maxnorm_bound(steps):
+    """Max-norm relative error bound per conserved component after `steps`
+    FP32 steps (stated from measurement, see the module docstring)."""
+    return 8 * steps * U32
 
 
 def _report(name, data):
@@ -57,6 +67,8 @@ def test_f32_hydro_per_field_error_vs_f64_oracle():
                                       "max_rel_error_arithmetic_only": errs_arith})
     for f, e in phys.items():
         assert e <= BOUND_100[f], (f, e)
+    for f, e in errs.items():
+        assert e <= maxnorm_bound(steps), (f, e)
 
 
 def test_f32_hydro_constant_state_bitwise_and_conservation():

@@ -432,3 +432,18 @@ def test_fuse_nests_rejects_bad_arguments():
     with pytest.raises(H.HfavError) as e:
         H.fuse_nests(2, _closure(2, []), [(2, [], [5], [])])
     assert e.value.code == H.EINVAL
+
+
+def test_binding_checks_tensor_arguments_before_the_call():
+    """The binding refuses tensors that are not device tensors of the
+    plan's element type and size before anything reaches the library."""
+    import torch
+    c = H.Chain(H.hdiff_spec())
+    c.plan((64, 32, 2))
+    u = torch.zeros((2, 32, 64), dtype=torch.float64)
+    with pytest.raises(H.HfavError) as e:
+        c.execute([u], [torch.zeros_like(u)])
+    assert e.value.code == H.EINVAL and "cuda" in str(e.value)
+    with pytest.raises(H.HfavError) as e:
+        c.execute([u], [])
+    assert e.value.code == H.EINVAL
