@@ -21,6 +21,9 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+# the oracle's OpenMP threads stay next to each other (set before any
+# library starts an OpenMP runtime)
+os.environ.setdefault("OMP_PROC_BIND", "close")
 
 METRIC = "cell-updates/s + % of 8 TB/s HBM, fused vs unfused on one MI355X"
 HBM_PEAK_GBS = 8000.0
@@ -147,21 +150,91 @@ def event_times(fn, reps, warmup=3):
     return t[len(t) // 2], sum(t) / len(t)
 
 
-def time_chain(spec, dims, mode, reps, inputs_fn):
+def event_times_rot(fns, reps, warmup=3):
+    """As event_times, cycling through the callables `fns` (the same work on
+    different buffer sets) so that consecutive executions do not find their
+    inputs in the 256 MB Infinity Cache."""
+    import torch
+    stream = torch.cuda.current_stream()
+    for q in range(warmup):
+        fns[q % len(fns)]()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for q, (e0, e1) in enumerate(ev):
+        e0.record(stream)
+        fns[q % len(fns)]()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    t = sorted(e0.elapsed_time(e1) for e0, e1 in ev)
+    return t[len(t) // 2], sum(t) / len(t)
+
+
+def time_chain(spec, dims, mode, reps, inputs_fn, sets=2):
     """Median and mean ms per hfav_execute of a single-axiom, single-goal
     chain (3 warm-up executions, then `reps` each timed with HIP events on
-    the stream the chain is launched on)."""
+    the stream the chain is launched on), rotating over `sets` input/output
+    buffer sets."""
     import torch
     from paper_1710_08774_amd import hfav as H
 
     c = H.Chain(spec)
     info = c.plan(dims, mode=mode)
-    u = inputs_fn()
-    o = torch.empty_like(u)
+    bufs = []
+    for _ in range(sets):
+        u = inputs_fn()
+        bufs.append((u, torch.empty_like(u)))
     ws = torch.empty(info.workspace_bytes, dtype=torch.uint8, device="cuda") if info.workspace_bytes else None
-    med, mean = event_times(lambda: c.execute([u], [o], ws), reps)
-    del u, o, ws
+    fns = [(lambda u=u, o=o: c.execute([u], [o], ws)) for u, o in bufs]
+    med, mean = event_times_rot(fns, reps)
+    del bufs, fns, ws
     return med, mean, info
+
+
+def copy_ceiling(nbytes, reps=20, pattern=None, sets=2):
+    """Read+write GB/s of plain device copies of `nbytes` (the bytes a chain
+    reads and writes once): a flat copy, and, when `pattern` gives the
+    geometry of a stencil kernel's tiles and segments, a copy in that
+    order.  Median of `reps` event-timed copies, rotating buffer sets."""
+    import torch
+    from paper_1710_08774_amd import hfav as H
+
+    bufs = [(torch.empty(nbytes, dtype=torch.uint8, device="cuda").fill_(1),
+             torch.empty(nbytes, dtype=torch.uint8, device="cuda")) for _ in range(sets)]
+    out = {"bytes_each_way": nbytes}
+    flat = [(lambda a=a, b=b: H.copy_probe(a, b, H.COPY_FLAT, nbytes=nbytes)) for a, b in bufs]
+    ms, _ = event_times_rot(flat, reps)
+    out["flat_GBs"] = 2 * nbytes / (ms * 1e-3) / 1e9
+    if pattern is not None:
+        seg = [(lambda a=a, b=b: H.copy_probe(a, b, H.COPY_SEGMENTS, **pattern)) for a, b in bufs]
+        ms, _ = event_times_rot(seg, reps)
+        out["pattern"] = dict(pattern)
+        out["pattern_GBs"] = 2 * nbytes / (ms * 1e-3) / 1e9
+    del bufs
+    torch.cuda.empty_cache()
+    return out
+
+
+# tile extents (x, y) of the 7-point chain's tile-shape variants
+LAP7_TILES = {1: (32, 8), 2: (64, 8), 3: (128, 2), 4: (32, 4), 5: (64, 16), 6: (64, 32), 7: (128, 16),
+              10: (64, 16), 11: (64, 8), 12: (32, 8), 13: (128, 8), 14: (32, 16)}
+
+
+def chain_copy_pattern(name, info, dims, es):
+    """Segment-copy geometry with the same tiles and segments as the fused
+    kernel of a bandwidth-bound chain."""
+    nx, ny, nz = dims
+    cfg = info.config
+    if name == "hdiff":            # a row piece of `block` cells streamed down `seg` rows
+        return {"slab_bytes": nx * es, "slabs": ny * nz, "row_bytes": nx * es, "band_bytes": cfg.block * es,
+                "tile_rows": 1, "seg": cfg.seg, "access_bytes": es}
+    var = cfg.variant & 31
+    if var == 8:
+        tx, ty = (128, 32) if es == 4 else (64, 32)
+    elif var == 9:
+        tx, ty = (256, 16) if es == 4 else (64, 32)
+    else:
+        tx, ty = LAP7_TILES.get(var, (64, 16))
+    return {"slab_bytes": nx * ny * es, "slabs": nz, "row_bytes": nx * es, "band_bytes": tx * es,
+            "tile_rows": ty, "seg": cfg.seg, "access_bytes": es}
 
 
 def bandwidth_chains(reps=20, which=("hdiff", "biharm64", "biharm32"), unfused=True):
@@ -185,9 +258,14 @@ def bandwidth_chains(reps=20, which=("hdiff", "biharm64", "biharm32"), unfused=T
         cells = dims[0] * dims[1] * dims[2]
         ms, ms_mean, info = time_chain(spec, dims, H.MODE_FUSED, reps, mk)
         gbs = 2 * es * cells / (ms * 1e-3) / 1e9
+        ceil = copy_ceiling(es * cells, reps, chain_copy_pattern(name, info, dims, es))
         r = {"dims": list(dims), "dtype": "f64" if es == 8 else "f32", "fused_ms": ms, "fused_ms_mean": ms_mean,
              "fused_cell_updates_per_s": cells / (ms * 1e-3), "fused_GBs": gbs,
              "fused_frac_of_8TBs": gbs / HBM_PEAK_GBS,
+             "copy_ceiling": ceil,
+             "fused_frac_of_flat_copy": gbs / ceil["flat_GBs"],
+             "fused_frac_of_pattern_copy": gbs / ceil["pattern_GBs"],
+             "buffer_sets": 2,
              "bytes_per_cell_fused": info.bytes_per_cell_fused,
              "config": [info.config.block, info.config.tile_y, info.config.seg, info.config.variant]}
         if unfused:
@@ -209,20 +287,20 @@ def norm_chain(reps=20, nq=4, nj=4096, ni=4096, unfused=True):
     from paper_1710_08774_amd import hfav as H
     from paper_1710_08774_amd import inputs
 
-    u = torch.as_tensor(inputs.norm_input(nq, nj, ni)).to("cuda")
-    o = torch.empty_like(u)
+    u0 = torch.as_tensor(inputs.norm_input(nq, nj, ni)).to("cuda")
+    sets = [(u0, torch.empty_like(u0)), (u0.clone(), torch.empty_like(u0))]
     cells = nj * ni
-    out = {"fields": nq, "rows": nj, "cells_per_row": ni, "dtype": "f64"}
-    stream = torch.cuda.current_stream()
+    out = {"fields": nq, "rows": nj, "cells_per_row": ni, "dtype": "f64", "buffer_sets": len(sets)}
     for mode, name in ((H.MODE_FUSED, "fused"), (H.MODE_UNFUSED, "unfused")):
         if mode == H.MODE_UNFUSED and not unfused:
             continue
         c = H.Chain(H.norm_spec(nq))
         info = c.plan((ni, nj), mode=mode)
         ws = torch.empty(max(1, info.workspace_bytes), dtype=torch.uint8, device="cuda")
-        args = ([u[q] for q in range(nq)], [o[q] for q in range(nq)], ws)
+        fns = [(lambda u=u, o=o: c.execute([u[q] for q in range(nq)], [o[q] for q in range(nq)], ws))
+               for u, o in sets]
         n = reps if mode == H.MODE_FUSED else max(2, reps // 4)
-        ms, ms_mean = event_times(lambda: c.execute(*args), n)
+        ms, ms_mean = event_times_rot(fns, n)
         out[name + "_ms"] = ms
         out[name + "_ms_mean"] = ms_mean
         out[name + "_cell_updates_per_s"] = cells / (ms * 1e-3)
@@ -230,13 +308,15 @@ def norm_chain(reps=20, nq=4, nj=4096, ni=4096, unfused=True):
             else info.bytes_per_cell_unfused
         if mode == H.MODE_FUSED:
             gbs = 2 * nq * 8 * cells / (ms * 1e-3) / 1e9
-            out.update({"fused_GBs": gbs, "fused_frac_of_8TBs": gbs / HBM_PEAK_GBS,
+            ceil = copy_ceiling(nq * 8 * cells, reps)
+            out.update({"fused_GBs": gbs, "fused_frac_of_8TBs": gbs / HBM_PEAK_GBS, "copy_ceiling": ceil,
+                        "fused_frac_of_flat_copy": gbs / ceil["flat_GBs"],
                         "config": [info.config.block, info.config.seg, info.config.variant],
                         "nests": info.n_nests, "outer_of_nest": list(info.outer_of_nest[:info.n_nests])})
         del ws
     if "unfused_ms" in out:
         out["fused_over_unfused"] = out["unfused_ms"] / out["fused_ms"]
-    del u, o
+    del u0, sets
     torch.cuda.empty_cache()
     return out
 
@@ -377,53 +457,56 @@ def batched_grids(steps=50, loop_steps=4):
 
 
 def cpu_model():
+    """CPU model name and logical CPU count, as lscpu and nproc report them."""
+    import subprocess
+    model = "unknown"
     try:
-        with open("/proc/cpuinfo") as fh:
-            for line in fh:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
-    except OSError:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in txt.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
         pass
-    return "unknown"
-
-
-def cpu_baseline(U0, budget_s=12.0, single_s=3.0):
-    """The FP64 oracle timed on the host: the full workload on all the
-    threads it uses (bounded to about budget_s), then one thread on a 512^2
-    grid of the same initial-state recipe (bounded to about single_s)."""
-    import oracle
-    from paper_1710_08774_amd import inputs
-    cores = oracle.num_threads()
-    U = U0.copy()
-    steps = 0
-    t0 = time.perf_counter()
-    while True:
-        U, _ = oracle.euler_run(U, 1)
-        steps += 1
-        if time.perf_counter() - t0 >= budget_s or steps >= 50:
-            break
-    dt = time.perf_counter() - t0
-    # one thread, smaller grid: cell-updates/s of the same chain
-    n1 = 512
-    V = inputs.euler_ic(n1, n1)
-    oracle.set_threads(1)
     try:
-        s1 = 0
-        t1 = time.perf_counter()
-        while True:
-            V, _ = oracle.euler_run(V, 1)
-            s1 += 1
-            if time.perf_counter() - t1 >= single_s or s1 >= 50:
-                break
-        d1 = time.perf_counter() - t1
-    finally:
-        oracle.set_threads(cores)
-    return {"value": NX * NY * steps / dt, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
-            "sample": f"FP64 oracle, {NX}x{NY} hydro chain, {steps} full steps from the initial state "
-                      f"({dt:.1f} s on {cores} OpenMP threads)",
-            "cpu": cpu_model(),
-            "single_thread": {"value": n1 * n1 * s1 / d1, "unit": "cell-updates/s",
-                              "sample": f"{n1}x{n1}, {s1} full steps on 1 thread ({d1:.1f} s)"}}
+        nproc = int(subprocess.run(["nproc"], capture_output=True, text=True, timeout=10).stdout.strip())
+    except (OSError, subprocess.SubprocessError, ValueError):
+        nproc = os.cpu_count()
+    return model, nproc
+
+
+def cpu_baseline(U0, steps_all=4, steps_one=1, runs=3):
+    """The FP64 oracle on the host, on the workload itself (the 2048^2 state
+    from its initial condition): `runs` timed runs of `steps_all` steps on
+    all the oracle's OpenMP threads and of `steps_one` step on one thread
+    (OMP_PROC_BIND=close), the median of each."""
+    import statistics
+    import oracle
+    cores = oracle.num_threads()
+
+    def median_rate(steps, threads):
+        oracle.set_threads(threads)
+        try:
+            ts = []
+            for _ in range(runs):
+                t0 = time.perf_counter()
+                oracle.euler_run(U0, steps)
+                ts.append(time.perf_counter() - t0)
+        finally:
+            oracle.set_threads(cores)
+        med = statistics.median(ts)
+        return NX * NY * steps / med, med, ts
+
+    v_all, t_all, _ = median_rate(steps_all, cores)
+    v_one, t_one, _ = median_rate(steps_one, 1)
+    model, nproc = cpu_model()
+    return {"value": v_all, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"FP64 oracle, {NX}x{NY} hydro chain, {steps_all} steps from the initial state on "
+                      f"{cores} OpenMP threads (OMP_PROC_BIND={os.environ.get('OMP_PROC_BIND')}), "
+                      f"median of {runs} runs ({t_all:.2f} s each)",
+            "cpu": model, "nproc": nproc,
+            "single_thread": {"value": v_one, "unit": "cell-updates/s", "cores": 1,
+                              "sample": f"the same workload, {steps_one} step on 1 thread, median of {runs} "
+                                        f"runs ({t_one:.2f} s each)"}}
 
 
 def main(argv=None):

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 #include "kernels.h"
 #include "ops.h"
+#include "xcd.h"
 
 namespace hfav {
 
@@ -19,8 +20,13 @@ struct UArgs {
     int bc[3];
     int n_in;
     int brow;                         // in[1] is a row term (broadcast along i)
+    int ntx;                          // 256-cell pieces per row
+    int nblk;                         // workgroups: ntx * ny * nz
+    int wide;                         // some |di| >= nx: general wrap along i
 };
 
+// general wrap (any offset), used for the outer axes (wave-uniform) and for
+// i when an offset reaches past a whole row
 __device__ __forceinline__ int uwrap(int i, int n, int bc) {
     if (bc == HFAV_BC_PERIODIC) {
         i %= n;
@@ -28,79 +34,103 @@ __device__ __forceinline__ int uwrap(int i, int n, int bc) {
     }
     return i < 0 ? 0 : (i >= n ? n - 1 : i);
 }
+// wrap along i for -n <= i < 2n: one compare and select per side
+__device__ __forceinline__ int xwrap(int i, int n, int bc) {
+    if (bc == HFAV_BC_PERIODIC) {
+        i = i < 0 ? i + n : i;
+        return i >= n ? i - n : i;
+    }
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+// The cell of a lane: workgroup w covers 256 cells of one row (j, k) of i;
+// workgroups are ordered so that every XCD walks one contiguous range of
+// rows (neighbouring rows share its L2).  Row, plane and the outer-axis
+// wraps are wave-uniform; only i is per lane, in 32 bits.
+struct UCell {
+    int i, j, k;
+    int row;                          // k * ny + j
+};
+__device__ __forceinline__ bool ucell(const UArgs &a, UCell &c) {
+    const int w = xcd_tile((int)blockIdx.x, a.nblk, -1);
+    c.row = w / a.ntx;
+    c.i = (w - c.row * a.ntx) * 256 + (int)threadIdx.x;
+    c.j = c.row % a.ny;
+    c.k = c.row / a.ny;
+    return c.i < a.nx;
+}
 
 template <class T>
-__device__ __forceinline__ T ld(const UArgs &a, int r, int i, int j, int k) {
-    const int ii = uwrap(i + a.off[r][0], a.nx, a.bc[0]);
-    const int jj = uwrap(j + a.off[r][1], a.ny, a.bc[1]);
-    const int kk = uwrap(k + a.off[r][2], a.nz, a.bc[2]);
-    return ((const T *)a.in[r])[((size_t)kk * a.ny + jj) * a.nx + ii];
+__device__ __forceinline__ T ld(const UArgs &a, int r, const UCell &c) {
+    const int jj = uwrap(c.j + a.off[r][1], a.ny, a.bc[1]);
+    const int kk = uwrap(c.k + a.off[r][2], a.nz, a.bc[2]);
+    const T *rowp = (const T *)a.in[r] + ((size_t)kk * a.ny + jj) * a.nx;
+    const int ii = a.wide ? uwrap(c.i + a.off[r][0], a.nx, a.bc[0]) : xwrap(c.i + a.off[r][0], a.nx, a.bc[0]);
+    return rowp[ii];
 }
 __device__ __forceinline__ double lds0(const UArgs &a, int r) { return *(const double *)a.in[r]; }
 
 template <class T>
-__device__ __forceinline__ void st(const UArgs &a, int o, size_t idx, T v) { ((T *)a.out[o])[idx] = v; }
+__device__ __forceinline__ void st(const UArgs &a, int o, const UCell &c, T v) {
+    ((T *)a.out[o] + (size_t)c.row * a.nx)[c.i] = v;
+}
 
 template <int OP, class T, class A, bool G14>
 __global__ __launch_bounds__(256) void rule_kernel(UArgs a) {
-    const size_t n = (size_t)a.nx * a.ny * a.nz;
-    const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
-    if (idx >= n) return;
-    const int i = (int)(idx % a.nx);
-    const int j = (int)((idx / a.nx) % a.ny);
-    const int k = (int)(idx / ((size_t)a.nx * a.ny));
-#define IN(r) ld<T>(a, r, i, j, k)
+    UCell cell;
+    if (!ucell(a, cell)) return;
+#define IN(r) ld<T>(a, r, cell)
     if constexpr (OP == HFAV_OP_HDIFF_LAP) {
-        st<T>(a, 0, idx, hdiff_lap(IN(0), IN(1), IN(2), IN(3), IN(4)));
+        st<T>(a, 0, cell, hdiff_lap(IN(0), IN(1), IN(2), IN(3), IN(4)));
     } else if constexpr (OP == HFAV_OP_HDIFF_FLX || OP == HFAV_OP_HDIFF_FLY) {
-        st<T>(a, 0, idx, hdiff_flux(IN(0), IN(1), IN(2), IN(3)));
+        st<T>(a, 0, cell, hdiff_flux(IN(0), IN(1), IN(2), IN(3)));
     } else if constexpr (OP == HFAV_OP_HDIFF_OUT) {
-        st<T>(a, 0, idx, hdiff_out(IN(0), IN(1), IN(2), IN(3), IN(4), (T)a.param[0]));
+        st<T>(a, 0, cell, hdiff_out(IN(0), IN(1), IN(2), IN(3), IN(4), (T)a.param[0]));
     } else if constexpr (OP == HFAV_OP_EULER_PRIM) {
         Prim<T> w = euler_prim(IN(0), IN(1), IN(2), IN(3), (T)a.param[0]);
-        st<T>(a, 0, idx, w.r); st<T>(a, 1, idx, w.un); st<T>(a, 2, idx, w.ut);
-        st<T>(a, 3, idx, w.p); st<T>(a, 4, idx, w.c);
+        st<T>(a, 0, cell, w.r); st<T>(a, 1, cell, w.un); st<T>(a, 2, cell, w.ut);
+        st<T>(a, 3, cell, w.p); st<T>(a, 4, cell, w.c);
     } else if constexpr (OP == HFAV_OP_EULER_SLOPE) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) st<T>(a, q, idx, vanleer(IN(3 * q), IN(3 * q + 1), IN(3 * q + 2)));
+        for (int q = 0; q < 4; ++q) st<T>(a, q, cell, vanleer(IN(3 * q), IN(3 * q + 1), IN(3 * q + 2)));
     } else if constexpr (OP == HFAV_OP_EULER_TRACE) {
         Prim<T> w;
         w.r = IN(0); w.un = IN(1); w.ut = IN(2); w.p = IN(3); w.c = IN(4);
         T plus[4], minus[4];
         euler_trace(w, IN(5), IN(6), IN(7), IN(8), (T)lds0(a, 9), plus, minus);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) { st<T>(a, q, idx, plus[q]); st<T>(a, 4 + q, idx, minus[q]); }
+        for (int q = 0; q < 4; ++q) { st<T>(a, q, cell, plus[q]); st<T>(a, 4 + q, cell, minus[q]); }
     } else if constexpr (OP == HFAV_OP_EULER_RIEMANN) {
         T L[4] = {IN(0), IN(1), IN(2), IN(3)};
         T R[4] = {IN(4), IN(5), IN(6), IN(7)};
         T G[4];
         riemann_T<T, G14>(L, R, (T)a.param[0], (int)a.param[1], G);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) st<T>(a, q, idx, G[q]);
+        for (int q = 0; q < 4; ++q) st<T>(a, q, cell, G[q]);
     } else if constexpr (OP == HFAV_OP_EULER_FLUX) {
         T G[4] = {IN(0), IN(1), IN(2), IN(3)};
         T F[4];
         euler_flux(G, (T)a.param[0], F);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) st<T>(a, q, idx, F[q]);
+        for (int q = 0; q < 4; ++q) st<T>(a, q, cell, F[q]);
     } else if constexpr (OP == HFAV_OP_EULER_UPDATE) {
         const A nu = (A)lds0(a, 12);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) st<T>(a, q, idx, euler_update(IN(q), IN(4 + q), IN(8 + q), nu));
+        for (int q = 0; q < 4; ++q) st<T>(a, q, cell, euler_update(IN(q), IN(4 + q), IN(8 + q), nu));
     } else if constexpr (OP == HFAV_OP_LAP7) {
-        st<T>(a, 0, idx, lap7(IN(0), IN(1), IN(2), IN(3), IN(4), IN(5), IN(6)));
+        st<T>(a, 0, cell, lap7(IN(0), IN(1), IN(2), IN(3), IN(4), IN(5), IN(6)));
     } else if constexpr (OP == HFAV_OP_AXPY) {
-        st<T>(a, 0, idx, axpy(IN(0), IN(1), (T)a.param[0]));
+        st<T>(a, 0, cell, axpy(IN(0), IN(1), (T)a.param[0]));
     } else if constexpr (OP == HFAV_OP_SUMSQ) {
         T acc = T(0);
         for (int r = 0; r < a.n_in; ++r) {
             const T v = IN(r);
             acc = fma(v, v, acc);
         }
-        st<T>(a, 0, idx, acc);
+        st<T>(a, 0, cell, acc);
     } else if constexpr (OP == HFAV_OP_DIV0) {
-        const T b = a.brow ? ((const T *)a.in[1])[(size_t)k * a.ny + j] : IN(1);
-        st<T>(a, 0, idx, b != T(0) ? IN(0) / b : T(0));
+        const T b = a.brow ? ((const T *)a.in[1])[cell.row] : IN(1);
+        st<T>(a, 0, cell, b != T(0) ? IN(0) / b : T(0));
     }
 #undef IN
 }
@@ -149,8 +179,8 @@ __global__ void rule_dt_kernel(UArgs a) {
 
 template <int OP, class T, class A, bool G14>
 static void launch_op(const UArgs &a, size_t n, hipStream_t s) {
-    const unsigned nb = (unsigned)((n + 255) / 256);
-    hipLaunchKernelGGL((rule_kernel<OP, T, A, G14>), dim3(nb), dim3(256), 0, s, a);
+    (void)n;
+    hipLaunchKernelGGL((rule_kernel<OP, T, A, G14>), dim3((unsigned)a.nblk), dim3(256), 0, s, a);
 }
 
 template <class T, class A, bool G14>
@@ -206,6 +236,13 @@ hipError_t launch_unfused_rule(const UnfusedRule &R, hipStream_t s) {
     for (int d = 0; d < 3; ++d) a.bc[d] = R.bc[d];
     a.n_in = R.n_in;
     a.brow = R.n_in > 1 && R.in_rank[1] == R.ndim - 1;
+    a.ntx = (R.nx + 255) / 256;
+    const int64_t nblk = (int64_t)a.ntx * R.ny * R.nz;
+    if (nblk > INT32_MAX) return hipErrorInvalidValue;
+    a.nblk = (int)nblk;
+    a.wide = 0;
+    for (int r = 0; r < R.n_in; ++r)
+        if (R.off[r][0] >= R.nx || -R.off[r][0] >= R.nx) a.wide = 1;
     double g = R.param[0];
     const bool g14 = (R.op == HFAV_OP_EULER_RIEMANN) && g == 1.4;
     if (R.dtype == HFAV_F64)
@@ -225,26 +262,26 @@ struct SArgs {
     void *out;
     int nx, ny, nz;
     int bc[3];
+    int ntx, nblk, wide;              // as in UArgs
 };
 
 template <class T>
 __global__ __launch_bounds__(256) void star_rule_kernel(SArgs a) {
     // reference order, every product and sum rounded (no contraction)
 #pragma clang fp contract(off)
-    const size_t n = (size_t)a.nx * a.ny * a.nz;
-    const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
-    if (idx >= n) return;
-    const int i = (int)(idx % a.nx);
-    const int j = (int)((idx / a.nx) % a.ny);
-    const int k = (int)(idx / ((size_t)a.nx * a.ny));
+    const int w = xcd_tile((int)blockIdx.x, a.nblk, -1);
+    const int row = w / a.ntx;
+    const int i = (w - row * a.ntx) * 256 + (int)threadIdx.x;
+    if (i >= a.nx) return;
+    const int j = row % a.ny, k = row / a.ny;
     T acc = T(0);
     for (int r = 0; r < a.n_in; ++r) {
-        const int ii = uwrap(i + a.off[r][0], a.nx, a.bc[0]);
         const int jj = uwrap(j + a.off[r][1], a.ny, a.bc[1]);
         const int kk = uwrap(k + a.off[r][2], a.nz, a.bc[2]);
-        acc += (T)a.coeff[r] * ((const T *)a.in[r])[((size_t)kk * a.ny + jj) * a.nx + ii];
+        const int ii = a.wide ? uwrap(i + a.off[r][0], a.nx, a.bc[0]) : xwrap(i + a.off[r][0], a.nx, a.bc[0]);
+        acc += (T)a.coeff[r] * ((const T *)a.in[r] + ((size_t)kk * a.ny + jj) * a.nx)[ii];
     }
-    ((T *)a.out)[idx] = acc;
+    ((T *)a.out + (size_t)row * a.nx)[i] = acc;
 }
 
 hipError_t launch_star_rule(const StarRule &R, hipStream_t s) {
@@ -259,8 +296,14 @@ hipError_t launch_star_rule(const StarRule &R, hipStream_t s) {
     a.out = R.out;
     a.nx = R.nx; a.ny = R.ny; a.nz = R.nz;
     for (int d = 0; d < 3; ++d) a.bc[d] = R.bc[d];
-    const size_t n = (size_t)R.nx * R.ny * R.nz;
-    const unsigned nb = (unsigned)((n + 255) / 256);
+    a.ntx = (R.nx + 255) / 256;
+    const int64_t nblk = (int64_t)a.ntx * R.ny * R.nz;
+    if (nblk > INT32_MAX) return hipErrorInvalidValue;
+    a.nblk = (int)nblk;
+    a.wide = 0;
+    for (int r = 0; r < R.n_in; ++r)
+        if (a.off[r][0] >= R.nx || -a.off[r][0] >= R.nx) a.wide = 1;
+    const unsigned nb = (unsigned)a.nblk;
     if (R.dtype == HFAV_F64) hipLaunchKernelGGL((star_rule_kernel<double>), dim3(nb), dim3(256), 0, s, a);
     else hipLaunchKernelGGL((star_rule_kernel<float>), dim3(nb), dim3(256), 0, s, a);
     return hipGetLastError();

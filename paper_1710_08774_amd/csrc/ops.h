@@ -231,32 +231,41 @@ __device__ __forceinline__ void pow_fan(double c, double g, double& c5, double& 
 // Exact Riemann solver sampled at x/t = 0: fixed `niter` Newton steps from
 // the PVRS guess, p kept above 1e-10.  Inputs/outputs (rho, un, ut, p) in
 // double.
+//
+// The two sides are handled as the lower- and the higher-pressure side
+// (lo, hi): an iterate between the two pressures, the usual case in smooth
+// flow, is a shock for lo and a rarefaction for hi in every lane, so the
+// lanes of a wave take the same branch of each pressure function where
+// left/right order would split them.  Every sum below is symmetric in the
+// sides or takes its sign from the swap, so the results are those of the
+// left/right evaluation bit for bit.
 template <bool G14>
 __device__ __forceinline__ void riemann0(const double* L, const double* R, double g, int niter,
                                          double* W) {
     if (G14) g = 1.4;     // the gamma constants below fold at compile time
-    const Side sl = make_side<G14>(L[0], L[1], L[3], g);
-    const Side sr = make_side<G14>(R[0], R[1], R[3], g);
-    const double du = sr.u - sl.u;
-    double p = 0.5 * (sl.p + sr.p) - 0.125 * du * (sl.r + sr.r) * (sl.c + sr.c);
+    const bool sw = L[3] > R[3];             // the left side has the higher pressure
+    const Side lo = make_side<G14>(sw ? R[0] : L[0], sw ? R[1] : L[1], sw ? R[3] : L[3], g);
+    const Side hi = make_side<G14>(sw ? L[0] : R[0], sw ? L[1] : R[1], sw ? L[3] : R[3], g);
+    const double du = sw ? lo.u - hi.u : hi.u - lo.u;      // u_R - u_L
+    double p = 0.5 * (lo.p + hi.p) - 0.125 * du * (lo.r + hi.r) * (lo.c + hi.c);
     p = fmax(p, 1e-10);
     for (int it = 0; it < niter; ++it) {
-        double fl, fdl, fr, fdr;
-        pres_fun<G14>(sl, p, g, fl, fdl);
-        pres_fun<G14>(sr, p, g, fr, fdr);
+        double flo, fdlo, fhi, fdhi;
+        pres_fun<G14>(lo, p, g, flo, fdlo);
+        pres_fun<G14>(hi, p, g, fhi, fdhi);
         // the step f/f' only needs a relative accuracy far below the
         // iteration's own convergence, so a refined reciprocal suffices
-        p = fmax(p - (fl + fr + du) * frcp(fdl + fdr), 1e-10);
+        p = fmax(p - (flo + fhi + du) * frcp(fdlo + fdhi), 1e-10);
     }
-    double fl, fdl, fr, fdr;
-    pres_fun<G14>(sl, p, g, fl, fdl);
-    pres_fun<G14>(sr, p, g, fr, fdr);
-    const double us = 0.5 * (sl.u + sr.u) + 0.5 * (fr - fl);
+    double flo, fdlo, fhi, fdhi;
+    pres_fun<G14>(lo, p, g, flo, fdlo);
+    pres_fun<G14>(hi, p, g, fhi, fdhi);
+    const double us = 0.5 * (lo.u + hi.u) + 0.5 * (sw ? flo - fhi : fhi - flo);
     const double g1 = (g - 1.0) / (2.0 * g), g2 = (g + 1.0) / (2.0 * g);
     const double g5 = 2.0 / (g + 1.0), g6 = (g - 1.0) / (g + 1.0), g7 = 0.5 * (g - 1.0);
     // sample: left of the contact when 0 <= u*
     const bool left = 0.0 <= us;
-    const Side& s = left ? sl : sr;
+    const Side& s = left != sw ? lo : hi;
     const double sg = left ? 1.0 : -1.0;     // mirror the right side onto the left case
     const double uk = sg * s.u;              // velocity in the mirrored frame
     const double ustar = sg * us;

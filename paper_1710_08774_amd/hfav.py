@@ -99,6 +99,15 @@ class hfav_nest(C.Structure):
                 ("epilogue", C.c_int * MAX_RULES)]
 
 
+class hfav_copy_desc(C.Structure):
+    _fields_ = [("pattern", C.c_int), ("bytes", C.c_int64), ("slab_bytes", C.c_int64), ("slabs", C.c_int64),
+                ("row_bytes", C.c_int64), ("band_bytes", C.c_int), ("tile_rows", C.c_int), ("seg", C.c_int),
+                ("access_bytes", C.c_int)]
+
+
+COPY_FLAT, COPY_SEGMENTS = 0, 1
+
+
 # ----------------------------------------------------------------- library
 _lib = None
 EXPORTS = ["hfav_chain_create", "hfav_chain_infer", "hfav_chain_alias", "hfav_plan", "hfav_execute", "hfav_chain_destroy", "hfav_last_error",
@@ -157,6 +166,7 @@ def lib():
                                          C.POINTER(C.c_float)]
     L.hfav_fuse_nests.argtypes = [C.c_int, C.POINTER(C.c_ubyte), C.c_int, C.POINTER(hfav_nest),
                                   C.POINTER(hfav_nest), C.POINTER(C.c_int)]
+    L.hfav_copy_probe.argtypes = [C.POINTER(hfav_copy_desc), C.c_void_p, C.c_void_p, C.c_void_p]
     L.hfav_tuning_clear.restype = None
     L.hfav_tuning_add.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(hfav_config)]
     _lib = L
@@ -420,6 +430,16 @@ def fuse_nests(n_rules, reach, nests):
     _check(lib().hfav_fuse_nests(n_rules, flat, len(nests), src, out, C.byref(n_out)))
     return [(o.rank, list(o.prologue[:o.n_prologue]), list(o.steady[:o.n_steady]),
              list(o.epilogue[:o.n_epilogue])) for o in out[:n_out.value]]
+
+
+def copy_probe(src, dst, pattern=COPY_FLAT, nbytes=0, slab_bytes=0, slabs=0, row_bytes=0, band_bytes=0,
+               tile_rows=1, seg=1, access_bytes=8, stream=None):
+    """Streaming-ceiling copy of src into dst (hfav_copy_probe)."""
+    d = hfav_copy_desc(pattern, nbytes, slab_bytes, slabs, row_bytes, band_bytes, tile_rows, seg, access_bytes)
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream().cuda_stream
+    _check(lib().hfav_copy_probe(C.byref(d), _ptr(src), _ptr(dst), stream))
 
 
 def tuning_clear():
