@@ -60,7 +60,9 @@ typedef enum {
                           chaining") */
     HFAV_ENOPLAN = 7,  /* execute before a successful plan, or a missing
                           workspace */
-    HFAV_EDEVICE = 8   /* HIP runtime or launch error; text in hfav_last_error */
+    HFAV_EDEVICE = 8,  /* HIP runtime or launch error; text in hfav_last_error */
+    HFAV_ESIZE = 9     /* the plan's workspace exceeds the library's static
+                          workspace (hfav_execute_noalloc) */
 } hfav_status;
 
 /* ------------------------------------------------------------------ enums */
@@ -331,6 +333,27 @@ int hfav_plan(hfav_chain *chain, const hfav_plan_opts *opts, hfav_plan_info *inf
 int hfav_execute(hfav_chain *chain, const void *const *axioms, void *const *goals,
                  void *workspace, void *stream);
 
+/* hfav_execute without a workspace argument, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  The plan's workspace
+ * (info.workspace_bytes) is taken from a static device array of
+ * HFAV_STATIC_WORKSPACE_BYTES that the library holds on each device it runs
+ * on, from the first call on that device (which looks up the array's
+ * address with that device current) until the process ends.  The call
+ * itself allocates nothing, device or host, and runs the same kernels as
+ * hfav_execute with the same results.  Every call on one device shares that
+ * device's array and leaves its contents behind; no part of it has to start
+ * at zero (every workspace byte a call reads was written earlier in the same
+ * call), so nothing is cleared.  Two calls whose work overlaps on one device
+ * (different streams or threads, not ordered by the caller) RACE on the
+ * array: order them, e.g. on one stream.  Arguments, ownership and the
+ * other errors as hfav_execute.
+ * Errors: ESIZE (info.workspace_bytes > HFAV_STATIC_WORKSPACE_BYTES; nothing
+ * is enqueued), EDEVICE (no current device, or the array's address could not
+ * be found), and those of hfav_execute. */
+#define HFAV_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+int hfav_execute_noalloc(hfav_chain *chain, const void *const *axioms, void *const *goals, void *stream);
+
 /* Create a chain by inference from rule patterns (Implementation,
  * "Inference").  The descriptor is that of hfav_chain_create, except that
  * rule term names may contain pattern variables: an identifier ending in
@@ -367,7 +390,8 @@ int hfav_chain_infer(const hfav_chain_desc *patterns, hfav_chain **out);
  * 0 only, else a copy of the whole axiom.  Other fused families fall back
  * to the unfused path (AUTO) or fail with EUNSUP (FUSED).  The plan JSON
  * lists each pair with the axiom's extent and the handling chosen.  The
- * goal and the axiom must have the same nonzero rank; each at most once.
+ * goal and the axiom must have the same nonzero rank; each at most once; at
+ * most 16 pairs per chain.
  * Errors: EINVAL, EDUP. */
 int hfav_chain_alias(hfav_chain *chain, const char *goal, const char *axiom);
 

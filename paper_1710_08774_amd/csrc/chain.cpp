@@ -129,8 +129,9 @@ static int build(const hfav_chain_desc *d, hfav_chain *c) {
         if (dr.n_param < need_param || (dr.n_param > 0 && !dr.param))
             return hfav_fail(HFAV_EINVAL, std::string("rule ") + std::to_string(r) + " (" + sp->name +
                                               "): missing parameters");
-        if (sp->op == HFAV_OP_STAR && dr.n_in > 96)
-            return hfav_fail(HFAV_EINVAL, "STAR rule with more than 96 references");
+        if (sp->op == HFAV_OP_STAR && dr.n_in > HFAV_MAX_STAR_REFS)
+            return hfav_fail(HFAV_EINVAL, "STAR rule with more than " + std::to_string(HFAV_MAX_STAR_REFS) +
+                                              " references");
         if (sp->out_rank0 && sp->op == HFAV_OP_EULER_SMAX && dr.reduce != HFAV_REDUCE_MAX)
             return hfav_fail(HFAV_EINVAL, "EULER_SMAX must declare reduce = MAX");
         if (sp->op == HFAV_OP_SUM_I && dr.reduce != HFAV_REDUCE_SUM)
@@ -312,6 +313,8 @@ extern "C" int hfav_chain_alias(hfav_chain *c, const char *goal, const char *axi
         return hfav_fail(HFAV_EINVAL, "an alias pairs a goal and an axiom of the same nonzero rank");
     for (const auto &pr : c->alias)
         if (pr.first == g || pr.second == a) return hfav_fail(HFAV_EDUP, "goal or axiom already aliased");
+    if ((int)c->alias.size() >= HFAV_MAX_ALIASES)
+        return hfav_fail(HFAV_EINVAL, "at most " + std::to_string(HFAV_MAX_ALIASES) + " in-place pairs");
     c->alias.push_back({g, a});
     c->plan.valid = false;
     return HFAV_OK;

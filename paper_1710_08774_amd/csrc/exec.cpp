@@ -17,11 +17,14 @@ struct Bind {
     const void *const *ax;
     void *const *go;
     char *ws;
-    std::vector<std::pair<int, const void *>> redirect;   // axioms read from a saved copy
+    // axioms read from a saved copy (fixed storage: executing allocates
+    // nothing, not even host memory)
+    int nredirect = 0;
+    std::pair<int, const void *> redirect[HFAV_MAX_ALIASES];
     const void *ptr(int t) const {
         const HTerm &T = c->terms[t];
-        for (const auto &r : redirect)
-            if (r.first == t) return r.second;
+        for (int q = 0; q < nredirect; ++q)
+            if (redirect[q].first == t) return redirect[q].second;
         if (T.kind == TK_AXIOM) return ax[T.axiom_slot];
         if (T.kind == TK_GOAL) return go[T.goal_slot];
         const int64_t off = c->plan.ws_off[t];
@@ -240,21 +243,23 @@ int run_unfused(const hfav_chain *c, Bind &B, hipStream_t s) {
         void *dst = B.ws + p.alias_ws[q];
         int rc = dev_err(hipMemcpyAsync(dst, src, term_bytes(c, a), hipMemcpyDeviceToDevice, s), "alias copy");
         if (rc) return rc;
-        B.redirect.push_back({a, dst});
+        if (B.nredirect >= HFAV_MAX_ALIASES) return hfav_fail(HFAV_EINVAL, "too many in-place pairs");
+        B.redirect[B.nredirect++] = {a, dst};
     }
     for (int r : p.exec_order) {
         const HRule &R = c->rules[r];
         if (R.op == HFAV_OP_STAR) {
-            std::vector<const void *> ptrs(R.in.size());
-            std::vector<int> offs(3 * R.in.size());
+            const void *ptrs[HFAV_MAX_STAR_REFS];
+            int offs[3 * HFAV_MAX_STAR_REFS];
+            if (R.in.size() > HFAV_MAX_STAR_REFS) return hfav_fail(HFAV_EINVAL, "star rule with too many references");
             for (size_t q = 0; q < R.in.size(); ++q) {
                 ptrs[q] = B.ptr(R.in[q].term);
                 for (int ax = 0; ax < 3; ++ax) offs[3 * q + ax] = R.in[q].off[ax];
             }
             hfav::StarRule S;
             S.n_in = (int)R.in.size();
-            S.in = ptrs.data();
-            S.off = offs.data();
+            S.in = ptrs;
+            S.off = offs;
             S.coeff = R.param.data();
             S.out = B.wptr(R.out[0]);
             S.nx = d[0]; S.ny = d[1]; S.nz = d[2];
@@ -294,8 +299,9 @@ int run_unfused(const hfav_chain *c, Bind &B, hipStream_t s) {
 
 }  // namespace
 
-extern "C" int hfav_execute(hfav_chain *c, const void *const *axioms, void *const *goals, void *workspace,
-                            void *stream) {
+// hfav_execute with the workspace already chosen (the caller's buffer, or
+// the library's static array for hfav_execute_noalloc)
+int hfav_execute_ws(hfav_chain *c, const void *const *axioms, void *const *goals, void *workspace, void *stream) {
     if (!c) return hfav_fail(HFAV_EINVAL, "null chain");
     if (!c->plan.valid) return hfav_fail(HFAV_ENOPLAN, "hfav_execute before a successful hfav_plan");
     if (!axioms || !goals) return hfav_fail(HFAV_EINVAL, "null axiom or goal array");
@@ -323,11 +329,16 @@ extern "C" int hfav_execute(hfav_chain *c, const void *const *axioms, void *cons
                 return hfav_fail(HFAV_EALIAS, "goals " + c->terms[c->goals[g]].name + " and " +
                                                   c->terms[c->goals[h]].name + " overlap");
     }
-    Bind B{c, axioms, goals, (char *)workspace, {}};
+    Bind B{c, axioms, goals, (char *)workspace};
     hipStream_t s = (hipStream_t)stream;
     try {
         return c->plan.info.fused ? run_fused(c, B, s) : run_unfused(c, B, s);
     } catch (...) {
         return hfav_fail(HFAV_EINVAL, "host exception while executing");
     }
+}
+
+extern "C" int hfav_execute(hfav_chain *c, const void *const *axioms, void *const *goals, void *workspace,
+                            void *stream) {
+    return hfav_execute_ws(c, axioms, goals, workspace, stream);
 }

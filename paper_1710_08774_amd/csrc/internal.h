@@ -113,6 +113,12 @@ struct hfav_chain {
     ~hfav_chain();
 };
 
+// limits that let hfav_execute run on fixed storage
+enum { HFAV_MAX_ALIASES = 16, HFAV_MAX_STAR_REFS = 96 };
+
+// hfav_execute with the workspace chosen (exec.cpp)
+int hfav_execute_ws(hfav_chain *c, const void *const *axioms, void *const *goals, void *workspace, void *stream);
+
 // error reporting (thread-local text)
 int hfav_fail(int code, const std::string &msg);
 

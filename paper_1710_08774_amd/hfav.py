@@ -20,9 +20,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhfav.so")
 
 # ----------------------------------------------------------------- constants
-OK, EINVAL, EUNSAT, EDUP, ECYCLE, EUNSUP, EALIAS, ENOPLAN, EDEVICE = range(9)
+OK, EINVAL, EUNSAT, EDUP, ECYCLE, EUNSUP, EALIAS, ENOPLAN, EDEVICE, ESIZE = range(10)
 STATUS = {0: "OK", 1: "EINVAL", 2: "EUNSAT", 3: "EDUP", 4: "ECYCLE", 5: "EUNSUP", 6: "EALIAS",
-          7: "ENOPLAN", 8: "EDEVICE"}
+          7: "ENOPLAN", 8: "EDEVICE", 9: "ESIZE"}
+# bytes of the library's static device workspace (hfav_execute_noalloc)
+STATIC_WORKSPACE_BYTES = 64 << 20
 F64, F32 = 0, 1
 OP = {
     "HDIFF_LAP": 1, "HDIFF_FLX": 2, "HDIFF_FLY": 3, "HDIFF_OUT": 4,
@@ -110,7 +112,8 @@ COPY_FLAT, COPY_SEGMENTS = 0, 1
 
 # ----------------------------------------------------------------- library
 _lib = None
-EXPORTS = ["hfav_chain_create", "hfav_chain_infer", "hfav_chain_alias", "hfav_plan", "hfav_execute", "hfav_chain_destroy", "hfav_last_error",
+EXPORTS = ["hfav_chain_create", "hfav_chain_infer", "hfav_chain_alias", "hfav_plan", "hfav_execute",
+           "hfav_execute_noalloc", "hfav_chain_destroy", "hfav_last_error",
            "hfav_version", "hfav_num_terms", "hfav_plan_term", "hfav_plan_json",
            "hfav_tuning_clear", "hfav_tuning_add", "hfav_tuning_size"]
 
@@ -136,6 +139,7 @@ def lib():
     L.hfav_plan.argtypes = [C.c_void_p, C.POINTER(hfav_plan_opts), C.POINTER(hfav_plan_info)]
     L.hfav_execute.argtypes = [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_void_p,
                                C.c_void_p]
+    L.hfav_execute_noalloc.argtypes = [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_void_p]
     L.hfav_chain_destroy.argtypes = [C.c_void_p]
     L.hfav_chain_destroy.restype = None
     L.hfav_last_error.restype = C.c_char_p
@@ -347,6 +351,27 @@ class Chain:
         else:
             s = stream.cuda_stream
         _check(lib().hfav_execute(self._h, ax, go, _ptr(workspace), s))
+
+    def execute_noalloc(self, axioms, goals, stream=None):
+        """hfav_execute_noalloc: the workspace is the library's static device
+        array (calls on one device must not overlap)."""
+        self._validate(axioms, goals, None)
+        ax = (C.c_void_p * len(axioms))(*[_ptr(a) for a in axioms])
+        go = (C.c_void_p * len(goals))(*[_ptr(g) for g in goals])
+        if stream is None:
+            import torch
+            s = torch.cuda.current_stream().cuda_stream
+        elif isinstance(stream, int):
+            s = stream
+        else:
+            s = stream.cuda_stream
+        _check(lib().hfav_execute_noalloc(self._h, ax, go, s))
+
+    def execute_noalloc_status(self, axioms, goals, stream=0):
+        """Like execute_noalloc but returns the status code instead of raising."""
+        ax = (C.c_void_p * len(axioms))(*[_ptr(a) for a in axioms])
+        go = (C.c_void_p * len(goals))(*[_ptr(g) for g in goals])
+        return lib().hfav_execute_noalloc(self._h, ax, go, stream)
 
     def execute_status(self, axioms, goals, workspace=None, stream=0):
         """Like execute but returns the status code instead of raising."""

@@ -30,3 +30,21 @@ def test_every_declared_symbol_is_exported():
 
 def test_version_string():
     assert "gfx950" in H.version()
+
+
+def test_static_workspace_size_matches_header():
+    text = open(os.path.join(INC, "hfav.h")).read()
+    m = re.search(r"#define HFAV_STATIC_WORKSPACE_BYTES \(\(size_t\)(\d+) << (\d+)\)", text)
+    assert m, "HFAV_STATIC_WORKSPACE_BYTES not found"
+    assert int(m.group(1)) << int(m.group(2)) == H.STATIC_WORKSPACE_BYTES
+
+
+def test_noalloc_refuses_before_touching_a_device():
+    """The size and plan checks of hfav_execute_noalloc run on the host
+    before any device call (the pointers below are never dereferenced)."""
+    c = H.Chain(H.hdiff_spec())
+    assert c.execute_noalloc_status([1], [2]) == H.ENOPLAN
+    info = c.plan((512, 512, 12), mode=H.MODE_UNFUSED)
+    assert info.workspace_bytes > H.STATIC_WORKSPACE_BYTES
+    assert c.execute_noalloc_status([1], [2]) == H.ESIZE
+    assert "static workspace" in H.last_error()
