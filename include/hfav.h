@@ -232,7 +232,11 @@ typedef struct {
                        segments of seg rows; x: one row, block = 64, 128
                        or 256 cells per chunk, segments of seg cells, 0 =
                        whole rows; a segment of seg cells walks seg + 1
-                       chunk positions).
+                       chunk positions); + 64 every Newton step of the
+                       Riemann solver is taken (by default the iteration
+                       stops once an iterate repeats, with the same
+                       result bit for bit).  EULER_XY and the batched
+                       sweeps take the + 64 bit too.
                        HDIFF: row prefetch depth 1 -> 1, 2 -> 2, 4 -> 8,
                        otherwise 4; + 8 DPP lane exchange; + 16
                        non-temporal output stores.  LAP7_CHAIN: tile shape

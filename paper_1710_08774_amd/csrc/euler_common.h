@@ -22,7 +22,11 @@ struct EArgs {
     int seg;
     int xcd;
     int bcy;           // boundary along y of the two-sweep kernel
+    int newton_all;    // take every Newton step (no stop at a repeated iterate)
 };
+
+// configuration variant bit of the Euler families: every Newton step taken
+constexpr int EULER_NEWTON_ALL = 64;
 
 __device__ __forceinline__ int bwrap(int i, int n, int bc) {
     if (bc == HFAV_BC_PERIODIC) {

@@ -132,7 +132,7 @@ __device__ __forceinline__ void x_row(const EArgs<T> &a, const EView<T> &v, int 
             T L[4], G[4], F[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) L[q] = S.f[q][sm];
-            riemann_T<T, G14>(L, minus, g, a.niter, G);
+            riemann_T<T, G14>(L, minus, g, a.niter, G, a.newton_all);
             euler_flux(G, g, F);
 #pragma unroll
             for (int q = 0; q < 4; ++q) S.F[q][s0] = F[q];
@@ -147,7 +147,7 @@ __device__ __forceinline__ void x_row(const EArgs<T> &a, const EView<T> &v, int 
 #pragma unroll
                 for (int q = 0; q < 4; ++q) Lr[q] = S.f[q][s0];
                 Rr[0] = S.w[0][s0]; Rr[1] = S.w[1][s0]; Rr[2] = S.w[2][s0]; Rr[3] = S.w[3][s0];
-                riemann_T<T, G14>(Lr, Rr, g, a.niter, Gr);
+                riemann_T<T, G14>(Lr, Rr, g, a.niter, Gr, a.newton_all);
                 euler_flux(Gr, g, S.Fn);
             }
         }
@@ -215,7 +215,7 @@ __device__ __forceinline__ double y_tile(const EArgs<T> &a, const EView<T> &v, i
             const Prim<T> w3 = P(j + 1, snew);
             T plus[4], minus[4], G[4], F[4];
             slope_trace(w1, w2, w3, nu, plus, minus);
-            riemann_T<T, G14>(fp, minus, g, a.niter, G);
+            riemann_T<T, G14>(fp, minus, g, a.niter, G, a.newton_all);
             euler_flux(G, g, F);                         // flux at j-1/2
             if (j > j0) {
                 const int su = snew == 2 ? 0 : snew + 1; // slot of cell j-1
@@ -369,7 +369,7 @@ __device__ __forceinline__ double strip(const EArgs<T> &a, const EView<T> &v, bo
         }
         if (act) {
             T G[4], F[4];
-            riemann_T<T, G14>(Lf, minus, g, a.niter, G);
+            riemann_T<T, G14>(Lf, minus, g, a.niter, G, a.newton_all);
             euler_flux(G, g, F);
             const int sm = sl(-1);
 #pragma unroll
@@ -538,6 +538,7 @@ static EArgs<T> make_args(const EulerLaunch &L) {
     a.smax_out = L.smax_out;
     a.seg = L.cfg.seg > 0 ? L.cfg.seg : 16;
     a.xcd = L.cfg.xcd;
+    a.newton_all = (L.cfg.variant & EULER_NEWTON_ALL) != 0;
     return a;
 }
 
@@ -546,7 +547,7 @@ static EArgs<T> make_args(const EulerLaunch &L) {
 // VGPRs), 2 for 5 waves (96 VGPRs; the Riemann solver's state partly spills
 // to scratch).
 #define E_LAUNCH(KER, BB)                                                                     \
-    switch (L.cfg.variant) {                                                                  \
+    switch (L.cfg.variant & ~EULER_NEWTON_ALL) {                                              \
     case 1: hipLaunchKernelGGL((KER<T, A, G14, BB, 4>), grid, dim3(BB), 0, s, a); break;      \
     case 2: hipLaunchKernelGGL((KER<T, A, G14, BB, 5>), grid, dim3(BB), 0, s, a); break;      \
     default: hipLaunchKernelGGL((KER<T, A, G14, BB, 1>), grid, dim3(BB), 0, s, a); break;     \
@@ -556,7 +557,7 @@ template <class T, class A, bool G14>
 static hipError_t euler_x_dispatch(const EulerLaunch &L, hipStream_t s) {
     EArgs<T> a = make_args<T>(L);
     dim3 grid(L.ny);
-    if (L.cfg.variant == 3) {
+    if ((L.cfg.variant & ~EULER_NEWTON_ALL) == 3) {
         // segments of cfg.seg cells (0: whole rows)
         a.seg = L.cfg.seg > 0 && L.cfg.seg < L.nx ? L.cfg.seg : L.nx;
         grid = dim3((unsigned)(L.ny * ((L.nx + a.seg - 1) / a.seg)));
@@ -578,7 +579,7 @@ static hipError_t euler_x_dispatch(const EulerLaunch &L, hipStream_t s) {
 template <class T, class A, bool G14>
 static hipError_t euler_y_dispatch(const EulerLaunch &L, hipStream_t s) {
     EArgs<T> a = make_args<T>(L);
-    if (L.cfg.variant == 3) {
+    if ((L.cfg.variant & ~EULER_NEWTON_ALL) == 3) {
         // 64 columns per workgroup, block / 64 rows per chunk
         dim3 grid(((L.nx + 63) / 64) * ((L.ny + a.seg - 1) / a.seg));
         switch (L.cfg.block) {

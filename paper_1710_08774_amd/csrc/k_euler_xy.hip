@@ -71,7 +71,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void eu
         slope_trace(nb<true>(w, l == 0), w, nb<false>(w, l == 63), nu, plus, minus);
 #pragma unroll
         for (int q = 0; q < 4; ++q) mr[q] = nb<false>(minus[q], l == 63);
-        riemann_T<T, G14>(plus, mr, g, a.niter, G);      // face col + 1/2
+        riemann_T<T, G14>(plus, mr, g, a.niter, G, a.newton_all);      // face col + 1/2
         euler_flux(G, g, F);
         T Fm[4];
 #pragma unroll
@@ -112,7 +112,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void eu
         const int j = r - 1;                         // rows j-1, j, j+1 in the window
         T plus[4], minus[4], G[4], F[4];
         slope_trace(wa, wb, wc, nu, plus, minus);
-        riemann_T<T, G14>(fp, minus, g, a.niter, G);
+        riemann_T<T, G14>(fp, minus, g, a.niter, G, a.newton_all);
         euler_flux(G, g, F);                         // flux at j-1/2
         if (j > j0 && out_lane) {
             const int su = (j - 1 - j0) % 3;         // slot of row j-1
@@ -141,6 +141,7 @@ hipError_t launch_xy_t(const EulerLaunch &L, hipStream_t s) {
     a.smax_out = L.smax_out;
     a.seg = L.cfg.seg > 0 ? L.cfg.seg : 16;
     a.xcd = L.cfg.xcd;
+    a.newton_all = (L.cfg.variant & EULER_NEWTON_ALL) != 0;
     const int ns = (L.nx + XY_W - 1) / XY_W, nsg = (L.ny + a.seg - 1) / a.seg;
     const dim3 grid((unsigned)(ns * nsg));
     if (L.gamma == 1.4) hipLaunchKernelGGL((euler_xy_kernel<T, A, true>), grid, dim3(64), 0, s, a);

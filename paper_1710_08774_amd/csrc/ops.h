@@ -228,9 +228,66 @@ __device__ __forceinline__ void pow_fan(double c, double g, double& c5, double& 
     }
 }
 
+// One Newton step of the pressure iteration, p kept above 1e-10.  The step
+// f/f' only needs a relative accuracy far below the iteration's own
+// convergence, so a refined reciprocal suffices.
+template <bool G14>
+__device__ __forceinline__ double newton_step(const Side& lo, const Side& hi, double du, double p, double g) {
+    double flo, fdlo, fhi, fdhi;
+    pres_fun<G14>(lo, p, g, flo, fdlo);
+    pres_fun<G14>(hi, p, g, fhi, fdhi);
+    return fmax(p - (flo + fhi + du) * frcp(fdlo + fdhi), 1e-10);
+}
+
+// Earlier iterates each new Newton iterate is compared with, and the first
+// step after which the comparison is made.
+constexpr int NEWTON_HIST = 6;
+constexpr int NEWTON_TEST_FROM = 5;
+
+// The iterate after NI Newton steps from p0 (NI known at compile time: the
+// loop is unrolled and every iterate stays in its own register).
+//
+// A step maps p to a value that depends on p alone (the side constants are
+// fixed), so if p_K == p_{K-m} the iterates repeat with period m from
+// p_{K-m} on, and p_NI = p_{K-m+((NI-K) mod m)}.  Near the root the rounding
+// of f/f' leaves the iterates jittering among a few neighbouring values,
+// which such a repeat soon reveals.  After each step K from NEWTON_TEST_FROM
+// on, the wave stops when every active lane's p_K equals one of its last
+// NEWTON_HIST iterates, and each lane takes p_NI from its own cycle: bit
+// for bit the iterate after all NI steps (every iterate is at least 1e-10,
+// so equal values are equal bit patterns).  Lanes never leave the loop on
+// their own, so the test is a few compares and one wave vote per step.
+// all_steps = true takes every step.
+template <bool G14, int NI>
+__device__ __forceinline__ double newton_fixed(const Side& lo, const Side& hi, double du, double p0, double g,
+                                               bool all_steps) {
+    double h[NI + 1];
+    h[0] = p0;
+#pragma unroll
+    for (int k = 1; k <= NI; ++k) {
+        h[k] = newton_step<G14>(lo, hi, du, h[k - 1], g);
+        if (k >= NEWTON_TEST_FROM && k < NI && !all_steps) {
+            bool rep = false;
+#pragma unroll
+            for (int m = 1; m <= NEWTON_HIST && m <= k; ++m) rep = rep || h[k] == h[k - m];
+            if (__all(rep)) {
+                // any m with p_K == p_{K-m} gives p_NI
+                double r = h[k];
+#pragma unroll
+                for (int m = NEWTON_HIST; m >= 1; --m)
+                    if (m <= k && h[k] == h[k - m]) r = h[k - m + (NI - k) % m];
+                return r;
+            }
+        }
+    }
+    return h[NI];
+}
+
 // Exact Riemann solver sampled at x/t = 0: fixed `niter` Newton steps from
 // the PVRS guess, p kept above 1e-10.  Inputs/outputs (rho, un, ut, p) in
-// double.
+// double.  For the usual niter = 10 the steps run unrolled with the exact
+// early stop of newton_fixed (all_steps = true takes every step); any other
+// count runs as a plain loop of every step.
 //
 // The two sides are handled as the lower- and the higher-pressure side
 // (lo, hi): an iterate between the two pressures, the usual case in smooth
@@ -241,7 +298,7 @@ __device__ __forceinline__ void pow_fan(double c, double g, double& c5, double& 
 // left/right evaluation bit for bit.
 template <bool G14>
 __device__ __forceinline__ void riemann0(const double* L, const double* R, double g, int niter,
-                                         double* W) {
+                                         double* W, bool all_steps = false) {
     if (G14) g = 1.4;     // the gamma constants below fold at compile time
     const bool sw = L[3] > R[3];             // the left side has the higher pressure
     const Side lo = make_side<G14>(sw ? R[0] : L[0], sw ? R[1] : L[1], sw ? R[3] : L[3], g);
@@ -249,13 +306,10 @@ __device__ __forceinline__ void riemann0(const double* L, const double* R, doubl
     const double du = sw ? lo.u - hi.u : hi.u - lo.u;      // u_R - u_L
     double p = 0.5 * (lo.p + hi.p) - 0.125 * du * (lo.r + hi.r) * (lo.c + hi.c);
     p = fmax(p, 1e-10);
-    for (int it = 0; it < niter; ++it) {
-        double flo, fdlo, fhi, fdhi;
-        pres_fun<G14>(lo, p, g, flo, fdlo);
-        pres_fun<G14>(hi, p, g, fhi, fdhi);
-        // the step f/f' only needs a relative accuracy far below the
-        // iteration's own convergence, so a refined reciprocal suffices
-        p = fmax(p - (flo + fhi + du) * frcp(fdlo + fdhi), 1e-10);
+    if (niter == 10) {
+        p = newton_fixed<G14, 10>(lo, hi, du, p, g, all_steps);
+    } else {
+        for (int it = 0; it < niter; ++it) p = newton_step<G14>(lo, hi, du, p, g);
     }
     double flo, fdlo, fhi, fdhi;
     pres_fun<G14>(lo, p, g, flo, fdlo);
@@ -329,11 +383,11 @@ __device__ __forceinline__ T euler_speed(T rho, T mx, T my, T E, T g) {
 // Riemann problem on T-typed face states: promotes to double for the
 // pressure iteration and sampling; the result is rounded back to T.
 template <class T, bool G14>
-__device__ __forceinline__ void riemann_T(const T* L, const T* R, T g, int niter, T* G) {
+__device__ __forceinline__ void riemann_T(const T* L, const T* R, T g, int niter, T* G, bool all_steps = false) {
     double l[4] = {(double)L[0], (double)L[1], (double)L[2], (double)L[3]};
     double r[4] = {(double)R[0], (double)R[1], (double)R[2], (double)R[3]};
     double w[4];
-    riemann0<G14>(l, r, (double)g, niter, w);
+    riemann0<G14>(l, r, (double)g, niter, w, all_steps);
     G[0] = (T)w[0]; G[1] = (T)w[1]; G[2] = (T)w[2]; G[3] = (T)w[3];
 }
 

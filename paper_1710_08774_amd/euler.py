@@ -94,7 +94,8 @@ class EulerBatchStepper:
     slot.  `capture(steps)` records `steps` (even) steps into a HIP graph."""
 
     def __init__(self, sizes, dtype=torch.float64, gamma=1.4, cfl=0.5, niter=10, bc=H.BC_PERIODIC,
-                 precision=H.PREC_NATIVE, config_source=H.CONFIG_DEFAULT, forced_y=None, device="cuda"):
+                 precision=H.PREC_NATIVE, config_source=H.CONFIG_DEFAULT, forced_y=None, device="cuda",
+                 forced_x=None):
         self.sizes = [(int(a), int(b)) for a, b in sizes]
         self.dtype = dtype
         cd = H.F64 if dtype == torch.float64 else H.F32
@@ -105,7 +106,9 @@ class EulerBatchStepper:
         self.smax_chain.plan_batch(self.sizes, (bc, bc))
         self.cx = H.Chain(H.euler_sweep_spec(0, gamma, niter, cfl, "smax", False, cd))
         self.cy = H.Chain(H.euler_sweep_spec(1, gamma, niter, cfl, "smax", True, cd))
-        self.ix = self.cx.plan_batch(self.sizes, (bc, bc), precision=precision, config_source=config_source)
+        src_x = H.CONFIG_FORCED if forced_x is not None else config_source
+        self.ix = self.cx.plan_batch(self.sizes, (bc, bc), precision=precision, config_source=src_x,
+                                     forced=forced_x)
         src_y = H.CONFIG_FORCED if forced_y is not None else config_source
         self.iy = self.cy.plan_batch(self.sizes, (bc, bc), precision=precision, config_source=src_y,
                                      forced=forced_y)
