@@ -5,15 +5,24 @@
 // families, one lane per cell, reading every input reference at its offset
 // with the boundary applied as index arithmetic.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+
 #include "kernels.h"
 #include "ops.h"
 #include "xcd.h"
 
 namespace hfav {
 
+// rows (cells along i at one j) of one plane k that a workgroup of the
+// rule kernels walks
+constexpr int UF_ROWS = 8;
+
 struct UArgs {
     const void *in[UF_MAX_IN];
     int off[UF_MAX_IN][3];
+    long long shift[UF_MAX_IN];       // elements from a cell to reference r when no wrap applies:
+                                      // (dk * ny + dj) * nx (the i offset is added per lane)
     void *out[UF_MAX_OUT];
     double param[UF_MAX_PARAM];
     int nx, ny, nz;
@@ -21,12 +30,13 @@ struct UArgs {
     int n_in;
     int brow;                         // in[1] is a row term (broadcast along i)
     int ntx;                          // 256-cell pieces per row
-    int nblk;                         // workgroups: ntx * ny * nz
-    int wide;                         // some |di| >= nx: general wrap along i
+    int nrb;                          // row blocks per plane: ceil(ny / UF_ROWS)
+    int nblk;                         // workgroups: ntx * nrb * nz
+    int wide;                         // bit a: some |offset| along axis a reaches a whole axis
+    int djmin, djmax, dkmin, dkmax;   // offset ranges along j and k over the references
 };
 
-// general wrap (any offset), used for the outer axes (wave-uniform) and for
-// i when an offset reaches past a whole row
+// general wrap (any offset)
 __device__ __forceinline__ int uwrap(int i, int n, int bc) {
     if (bc == HFAV_BC_PERIODIC) {
         i %= n;
@@ -34,7 +44,7 @@ __device__ __forceinline__ int uwrap(int i, int n, int bc) {
     }
     return i < 0 ? 0 : (i >= n ? n - 1 : i);
 }
-// wrap along i for -n <= i < 2n: one compare and select per side
+// wrap for -n <= i < 2n: one compare and select per side
 __device__ __forceinline__ int xwrap(int i, int n, int bc) {
     if (bc == HFAV_BC_PERIODIC) {
         i = i < 0 ? i + n : i;
@@ -42,31 +52,43 @@ __device__ __forceinline__ int xwrap(int i, int n, int bc) {
     }
     return i < 0 ? 0 : (i >= n ? n - 1 : i);
 }
+__device__ __forceinline__ int awrap(int i, int n, int bc, bool wide) {
+    return wide ? uwrap(i, n, bc) : xwrap(i, n, bc);
+}
 
-// The cell of a lane: workgroup w covers 256 cells of one row (j, k) of i;
-// workgroups are ordered so that every XCD walks one contiguous range of
-// rows (neighbouring rows share its L2).  Row, plane and the outer-axis
-// wraps are wave-uniform; only i is per lane, in 32 bits.
+// The cells of a lane: workgroup w covers 256 cells along i of UF_ROWS
+// consecutive rows of one plane; workgroups are ordered so that every XCD
+// walks one contiguous range of row blocks (neighbouring rows share its L2).
+// A block whose rows and plane reach no boundary through any reference
+// ("interior": all but the first and last blocks of a plane for the usual
+// stencils, and no offset along i as long as a row) reads reference r at the
+// fixed element shift[r] plus the lane's wrapped i; the others wrap j and k
+// per reference and row.
 struct UCell {
     int i, j, k;
     int row;                          // k * ny + j
 };
-__device__ __forceinline__ bool ucell(const UArgs &a, UCell &c) {
+__device__ __forceinline__ UCell ucell0(const UArgs &a, int &j1, bool &interior) {
     const int w = xcd_tile((int)blockIdx.x, a.nblk, -1);
-    c.row = w / a.ntx;
-    c.i = (w - c.row * a.ntx) * 256 + (int)threadIdx.x;
-    c.j = c.row % a.ny;
-    c.k = c.row / a.ny;
-    return c.i < a.nx;
+    const int t = w / a.ntx;                  // row block over (k, block of j)
+    UCell c;
+    c.i = (w - t * a.ntx) * 256 + (int)threadIdx.x;
+    c.k = t / a.nrb;
+    c.j = (t - c.k * a.nrb) * UF_ROWS;
+    c.row = c.k * a.ny + c.j;
+    j1 = min(c.j + UF_ROWS, a.ny);
+    interior = c.j + a.djmin >= 0 && j1 - 1 + a.djmax < a.ny && c.k + a.dkmin >= 0 && c.k + a.dkmax < a.nz &&
+               !(a.wide & 1);
+    return c;
 }
 
-template <class T>
+template <class T, bool FAST>
 __device__ __forceinline__ T ld(const UArgs &a, int r, const UCell &c) {
-    const int jj = uwrap(c.j + a.off[r][1], a.ny, a.bc[1]);
-    const int kk = uwrap(c.k + a.off[r][2], a.nz, a.bc[2]);
-    const T *rowp = (const T *)a.in[r] + ((size_t)kk * a.ny + jj) * a.nx;
-    const int ii = a.wide ? uwrap(c.i + a.off[r][0], a.nx, a.bc[0]) : xwrap(c.i + a.off[r][0], a.nx, a.bc[0]);
-    return rowp[ii];
+    if (FAST) return ((const T *)a.in[r])[(long long)c.row * a.nx + a.shift[r] + xwrap(c.i + a.off[r][0], a.nx, a.bc[0])];
+    const int ii = awrap(c.i + a.off[r][0], a.nx, a.bc[0], a.wide & 1);
+    const int jj = awrap(c.j + a.off[r][1], a.ny, a.bc[1], a.wide & 2);
+    const int kk = awrap(c.k + a.off[r][2], a.nz, a.bc[2], a.wide & 4);
+    return ((const T *)a.in[r] + ((size_t)kk * a.ny + jj) * a.nx)[ii];
 }
 __device__ __forceinline__ double lds0(const UArgs &a, int r) { return *(const double *)a.in[r]; }
 
@@ -75,64 +97,114 @@ __device__ __forceinline__ void st(const UArgs &a, int o, const UCell &c, T v) {
     ((T *)a.out[o] + (size_t)c.row * a.nx)[c.i] = v;
 }
 
+// outputs of a rule body (it fills v[0 .. rule_nout - 1])
+template <int OP>
+constexpr int rule_nout() {
+    return OP == HFAV_OP_EULER_PRIM ? 5
+         : OP == HFAV_OP_EULER_TRACE ? 8
+         : (OP == HFAV_OP_EULER_SLOPE || OP == HFAV_OP_EULER_RIEMANN || OP == HFAV_OP_EULER_FLUX ||
+            OP == HFAV_OP_EULER_UPDATE) ? 4
+         : 1;
+}
+
+template <int OP, class T, class A, bool G14, bool FAST>
+__device__ __forceinline__ void rule_cell(const UArgs &a, const UCell &cell, T *v);
+
+// The rows of a block two at a time: both rows' outputs are computed into
+// registers before either is stored, so the loads of the second row do not
+// wait behind the first row's stores (an output may alias no input, but the
+// compiler cannot know that) and twice the bytes are in flight per wave.
+template <int OP, class T, class A, bool G14, bool FAST>
+__device__ __forceinline__ void rule_rows(const UArgs &a, UCell c, int j1) {
+    constexpr int NO = rule_nout<OP>();
+    for (; c.j + 1 < j1; c.j += 2, c.row += 2) {
+        UCell d = c;
+        ++d.j;
+        ++d.row;
+        T v0[NO], v1[NO];
+        rule_cell<OP, T, A, G14, FAST>(a, c, v0);
+        rule_cell<OP, T, A, G14, FAST>(a, d, v1);
+#pragma unroll
+        for (int q = 0; q < NO; ++q) st<T>(a, q, c, v0[q]);
+#pragma unroll
+        for (int q = 0; q < NO; ++q) st<T>(a, q, d, v1[q]);
+    }
+    if (c.j < j1) {
+        T v0[NO];
+        rule_cell<OP, T, A, G14, FAST>(a, c, v0);
+#pragma unroll
+        for (int q = 0; q < NO; ++q) st<T>(a, q, c, v0[q]);
+    }
+}
+
 template <int OP, class T, class A, bool G14>
 __global__ __launch_bounds__(256) void rule_kernel(UArgs a) {
-    UCell cell;
-    if (!ucell(a, cell)) return;
-#define IN(r) ld<T>(a, r, cell)
+    int j1;
+    bool interior;
+    const UCell cell = ucell0(a, j1, interior);
+    if (cell.i >= a.nx) return;
+    if (interior) rule_rows<OP, T, A, G14, true>(a, cell, j1);
+    else rule_rows<OP, T, A, G14, false>(a, cell, j1);
+}
+
+template <int OP, class T, class A, bool G14, bool FAST>
+__device__ __forceinline__ void rule_cell(const UArgs &a, const UCell &cell, T *v) {
+#define IN(r) ld<T, FAST>(a, r, cell)
+#define OUT(o, x) (v[o] = (x))
     if constexpr (OP == HFAV_OP_HDIFF_LAP) {
-        st<T>(a, 0, cell, hdiff_lap(IN(0), IN(1), IN(2), IN(3), IN(4)));
+        OUT(0, hdiff_lap(IN(0), IN(1), IN(2), IN(3), IN(4)));
     } else if constexpr (OP == HFAV_OP_HDIFF_FLX || OP == HFAV_OP_HDIFF_FLY) {
-        st<T>(a, 0, cell, hdiff_flux(IN(0), IN(1), IN(2), IN(3)));
+        OUT(0, hdiff_flux(IN(0), IN(1), IN(2), IN(3)));
     } else if constexpr (OP == HFAV_OP_HDIFF_OUT) {
-        st<T>(a, 0, cell, hdiff_out(IN(0), IN(1), IN(2), IN(3), IN(4), (T)a.param[0]));
+        OUT(0, hdiff_out(IN(0), IN(1), IN(2), IN(3), IN(4), (T)a.param[0]));
     } else if constexpr (OP == HFAV_OP_EULER_PRIM) {
         Prim<T> w = euler_prim(IN(0), IN(1), IN(2), IN(3), (T)a.param[0]);
-        st<T>(a, 0, cell, w.r); st<T>(a, 1, cell, w.un); st<T>(a, 2, cell, w.ut);
-        st<T>(a, 3, cell, w.p); st<T>(a, 4, cell, w.c);
+        OUT(0, w.r); OUT(1, w.un); OUT(2, w.ut);
+        OUT(3, w.p); OUT(4, w.c);
     } else if constexpr (OP == HFAV_OP_EULER_SLOPE) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) st<T>(a, q, cell, vanleer(IN(3 * q), IN(3 * q + 1), IN(3 * q + 2)));
+        for (int q = 0; q < 4; ++q) OUT(q, vanleer(IN(3 * q), IN(3 * q + 1), IN(3 * q + 2)));
     } else if constexpr (OP == HFAV_OP_EULER_TRACE) {
         Prim<T> w;
         w.r = IN(0); w.un = IN(1); w.ut = IN(2); w.p = IN(3); w.c = IN(4);
         T plus[4], minus[4];
         euler_trace(w, IN(5), IN(6), IN(7), IN(8), (T)lds0(a, 9), plus, minus);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) { st<T>(a, q, cell, plus[q]); st<T>(a, 4 + q, cell, minus[q]); }
+        for (int q = 0; q < 4; ++q) { OUT(q, plus[q]); OUT(4 + q, minus[q]); }
     } else if constexpr (OP == HFAV_OP_EULER_RIEMANN) {
         T L[4] = {IN(0), IN(1), IN(2), IN(3)};
         T R[4] = {IN(4), IN(5), IN(6), IN(7)};
         T G[4];
         riemann_T<T, G14>(L, R, (T)a.param[0], (int)a.param[1], G);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) st<T>(a, q, cell, G[q]);
+        for (int q = 0; q < 4; ++q) OUT(q, G[q]);
     } else if constexpr (OP == HFAV_OP_EULER_FLUX) {
         T G[4] = {IN(0), IN(1), IN(2), IN(3)};
         T F[4];
         euler_flux(G, (T)a.param[0], F);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) st<T>(a, q, cell, F[q]);
+        for (int q = 0; q < 4; ++q) OUT(q, F[q]);
     } else if constexpr (OP == HFAV_OP_EULER_UPDATE) {
         const A nu = (A)lds0(a, 12);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) st<T>(a, q, cell, euler_update(IN(q), IN(4 + q), IN(8 + q), nu));
+        for (int q = 0; q < 4; ++q) OUT(q, euler_update(IN(q), IN(4 + q), IN(8 + q), nu));
     } else if constexpr (OP == HFAV_OP_LAP7) {
-        st<T>(a, 0, cell, lap7(IN(0), IN(1), IN(2), IN(3), IN(4), IN(5), IN(6)));
+        OUT(0, lap7(IN(0), IN(1), IN(2), IN(3), IN(4), IN(5), IN(6)));
     } else if constexpr (OP == HFAV_OP_AXPY) {
-        st<T>(a, 0, cell, axpy(IN(0), IN(1), (T)a.param[0]));
+        OUT(0, axpy(IN(0), IN(1), (T)a.param[0]));
     } else if constexpr (OP == HFAV_OP_SUMSQ) {
         T acc = T(0);
         for (int r = 0; r < a.n_in; ++r) {
             const T v = IN(r);
             acc = fma(v, v, acc);
         }
-        st<T>(a, 0, cell, acc);
+        OUT(0, acc);
     } else if constexpr (OP == HFAV_OP_DIV0) {
         const T b = a.brow ? ((const T *)a.in[1])[cell.row] : IN(1);
-        st<T>(a, 0, cell, b != T(0) ? IN(0) / b : T(0));
+        OUT(0, b != T(0) ? IN(0) / b : T(0));
     }
 #undef IN
+#undef OUT
 }
 
 // SQRT over n elements (a grid or a row term)
@@ -224,6 +296,18 @@ static hipError_t dispatch_rule(const UnfusedRule &R, const UArgs &a, hipStream_
     return hipGetLastError();
 }
 
+// bit a set when some offset along axis a reaches a whole axis length (the
+// wrap then takes a modulo instead of one compare per side)
+template <class OFF>
+static int wide_bits(int n_in, const OFF &off, int nx, int ny, int nz) {
+    const int n[3] = {nx, ny, nz};
+    int w = 0;
+    for (int r = 0; r < n_in; ++r)
+        for (int d = 0; d < 3; ++d)
+            if (off[r][d] >= n[d] || -off[r][d] >= n[d]) w |= 1 << d;
+    return w;
+}
+
 hipError_t launch_unfused_rule(const UnfusedRule &R, hipStream_t s) {
     UArgs a;
     for (int r = 0; r < UF_MAX_IN; ++r) {
@@ -237,12 +321,18 @@ hipError_t launch_unfused_rule(const UnfusedRule &R, hipStream_t s) {
     a.n_in = R.n_in;
     a.brow = R.n_in > 1 && R.in_rank[1] == R.ndim - 1;
     a.ntx = (R.nx + 255) / 256;
-    const int64_t nblk = (int64_t)a.ntx * R.ny * R.nz;
-    if (nblk > INT32_MAX) return hipErrorInvalidValue;
+    a.nrb = (R.ny + UF_ROWS - 1) / UF_ROWS;
+    const int64_t nblk = (int64_t)a.ntx * a.nrb * R.nz;
+    if (nblk > INT32_MAX || (int64_t)R.ny * R.nz > INT32_MAX) return hipErrorInvalidValue;
     a.nblk = (int)nblk;
-    a.wide = 0;
-    for (int r = 0; r < R.n_in; ++r)
-        if (R.off[r][0] >= R.nx || -R.off[r][0] >= R.nx) a.wide = 1;
+    a.wide = wide_bits(R.n_in, R.off, R.nx, R.ny, R.nz);
+    a.djmin = a.djmax = a.dkmin = a.dkmax = 0;
+    for (int r = 0; r < UF_MAX_IN; ++r) {
+        a.shift[r] = r < R.n_in ? ((long long)R.off[r][2] * R.ny + R.off[r][1]) * R.nx : 0;
+        if (r >= R.n_in) continue;
+        a.djmin = std::min(a.djmin, R.off[r][1]); a.djmax = std::max(a.djmax, R.off[r][1]);
+        a.dkmin = std::min(a.dkmin, R.off[r][2]); a.dkmax = std::max(a.dkmax, R.off[r][2]);
+    }
     double g = R.param[0];
     const bool g14 = (R.op == HFAV_OP_EULER_RIEMANN) && g == 1.4;
     if (R.dtype == HFAV_F64)
@@ -262,7 +352,8 @@ struct SArgs {
     void *out;
     int nx, ny, nz;
     int bc[3];
-    int ntx, nblk, wide;              // as in UArgs
+    int ntx, nrb, nblk, wide;                 // as in UArgs
+    int djmin, djmax, dkmin, dkmax;
 };
 
 template <class T>
@@ -270,39 +361,54 @@ __global__ __launch_bounds__(256) void star_rule_kernel(SArgs a) {
     // reference order, every product and sum rounded (no contraction)
 #pragma clang fp contract(off)
     const int w = xcd_tile((int)blockIdx.x, a.nblk, -1);
-    const int row = w / a.ntx;
-    const int i = (w - row * a.ntx) * 256 + (int)threadIdx.x;
+    const int t = w / a.ntx;
+    const int i = (w - t * a.ntx) * 256 + (int)threadIdx.x;
     if (i >= a.nx) return;
-    const int j = row % a.ny, k = row / a.ny;
-    T acc = T(0);
-    for (int r = 0; r < a.n_in; ++r) {
-        const int jj = uwrap(j + a.off[r][1], a.ny, a.bc[1]);
-        const int kk = uwrap(k + a.off[r][2], a.nz, a.bc[2]);
-        const int ii = a.wide ? uwrap(i + a.off[r][0], a.nx, a.bc[0]) : xwrap(i + a.off[r][0], a.nx, a.bc[0]);
-        acc += (T)a.coeff[r] * ((const T *)a.in[r] + ((size_t)kk * a.ny + jj) * a.nx)[ii];
+    const int k = t / a.nrb;
+    const int j0 = (t - k * a.nrb) * UF_ROWS, j1 = min(j0 + UF_ROWS, a.ny);
+    const bool interior =
+        j0 + a.djmin >= 0 && j1 - 1 + a.djmax < a.ny && k + a.dkmin >= 0 && k + a.dkmax < a.nz && !(a.wide & 1);
+    for (int j = j0; j < j1; ++j) {
+        const long long row = (long long)k * a.ny + j;
+        T acc = T(0);
+        for (int r = 0; r < a.n_in; ++r) {
+            long long o;
+            if (interior) {
+                o = (row + (long long)a.off[r][2] * a.ny + a.off[r][1]) * a.nx + xwrap(i + a.off[r][0], a.nx, a.bc[0]);
+            } else {
+                const int ii = awrap(i + a.off[r][0], a.nx, a.bc[0], a.wide & 1);
+                const int jj = awrap(j + a.off[r][1], a.ny, a.bc[1], a.wide & 2);
+                const int kk = awrap(k + a.off[r][2], a.nz, a.bc[2], a.wide & 4);
+                o = ((long long)kk * a.ny + jj) * a.nx + ii;
+            }
+            acc += (T)a.coeff[r] * ((const T *)a.in[r])[o];
+        }
+        ((T *)a.out + row * a.nx)[i] = acc;
     }
-    ((T *)a.out + (size_t)row * a.nx)[i] = acc;
 }
 
 hipError_t launch_star_rule(const StarRule &R, hipStream_t s) {
     if (R.n_in < 1 || R.n_in > STAR_MAX) return hipErrorInvalidValue;
     SArgs a;
     a.n_in = R.n_in;
+    int off[STAR_MAX][3];
+    a.djmin = a.djmax = a.dkmin = a.dkmax = 0;
     for (int r = 0; r < STAR_MAX; ++r) {
         a.in[r] = r < R.n_in ? R.in[r] : nullptr;
-        for (int d = 0; d < 3; ++d) a.off[r][d] = r < R.n_in ? R.off[3 * r + d] : 0;
+        for (int d = 0; d < 3; ++d) off[r][d] = a.off[r][d] = r < R.n_in ? R.off[3 * r + d] : 0;
         a.coeff[r] = r < R.n_in ? R.coeff[r] : 0.0;
+        a.djmin = std::min(a.djmin, off[r][1]); a.djmax = std::max(a.djmax, off[r][1]);
+        a.dkmin = std::min(a.dkmin, off[r][2]); a.dkmax = std::max(a.dkmax, off[r][2]);
     }
     a.out = R.out;
     a.nx = R.nx; a.ny = R.ny; a.nz = R.nz;
     for (int d = 0; d < 3; ++d) a.bc[d] = R.bc[d];
     a.ntx = (R.nx + 255) / 256;
-    const int64_t nblk = (int64_t)a.ntx * R.ny * R.nz;
-    if (nblk > INT32_MAX) return hipErrorInvalidValue;
+    a.nrb = (R.ny + UF_ROWS - 1) / UF_ROWS;
+    const int64_t nblk = (int64_t)a.ntx * a.nrb * R.nz;
+    if (nblk > INT32_MAX || (int64_t)R.ny * R.nz > INT32_MAX) return hipErrorInvalidValue;
     a.nblk = (int)nblk;
-    a.wide = 0;
-    for (int r = 0; r < R.n_in; ++r)
-        if (a.off[r][0] >= R.nx || -a.off[r][0] >= R.nx) a.wide = 1;
+    a.wide = wide_bits(R.n_in, off, R.nx, R.ny, R.nz);
     const unsigned nb = (unsigned)a.nblk;
     if (R.dtype == HFAV_F64) hipLaunchKernelGGL((star_rule_kernel<double>), dim3(nb), dim3(256), 0, s, a);
     else hipLaunchKernelGGL((star_rule_kernel<float>), dim3(nb), dim3(256), 0, s, a);
