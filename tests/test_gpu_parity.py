@@ -348,6 +348,52 @@ def test_biharm_f32_tile_variants_equal_default(variant):
     assert relerr(outs[1], oracle.biharm(u.astype(np.float32).astype(np.float64))) <= 1e-6
 
 
+@pytest.mark.parametrize("dtype,nx", [(H.F32, 150), (H.F32, 301), (H.F64, 151)])
+@pytest.mark.parametrize("variant", [6, 7, 8, 9])
+def test_biharm_large_tiles_scalar_fetch(dtype, nx, variant):
+    """The 1024-lane tiles (2 or 4 points per lane) on rows whose length is
+    not a multiple of 4, with ragged tiles in x and y: the same results as
+    the 64 x 16 tiles (FP32: bit for bit; FP64: also the oracle bit for
+    bit)."""
+    shape = (7, 37, nx)
+    u = inputs.biharm_input(shape=shape, seed=nx + variant)
+    tdt = torch.float32 if dtype == H.F32 else torch.float64
+    d = dev(u, tdt)
+    outs = []
+    for cfg in ((1024, 2, 5, 5), (1024, 2, 5, variant)):
+        c = H.Chain(H.biharm_spec(dtype=dtype))
+        c.plan((nx, 37, 7), mode=H.MODE_FUSED, config_source=H.CONFIG_FORCED, forced=cfg)
+        o = torch.empty_like(d)
+        c.execute([d], [o])
+        outs.append(host(o))
+    assert np.array_equal(outs[0], outs[1])
+    if dtype == H.F64:
+        assert np.array_equal(outs[1], oracle.biharm(u))
+
+
+@pytest.mark.parametrize("dtype", [H.F32, H.F64])
+def test_biharm_unaligned_buffers(dtype):
+    """Buffers that do not start on a 16-byte boundary give the results of
+    aligned buffers."""
+    shape = (6, 20, 64)
+    nz, ny, nx = shape
+    u = inputs.biharm_input(shape=shape, seed=44)
+    tdt = torch.float32 if dtype == H.F32 else torch.float64
+    n = nx * ny * nz
+    big = torch.zeros(n + 1, dtype=tdt, device="cuda")
+    big[1:] = torch.as_tensor(u.reshape(-1), dtype=tdt)
+    obig = torch.zeros(n + 1, dtype=tdt, device="cuda")
+    d = dev(u, tdt)
+    o = torch.empty_like(d)
+    c = H.Chain(H.biharm_spec(dtype=dtype))
+    c.plan((nx, ny, nz), mode=H.MODE_FUSED, config_source=H.CONFIG_FORCED, forced=(1024, 2, 4, 7))
+    c.execute([d], [o])
+    c.execute([big[1:]], [obig[1:]])
+    assert np.array_equal(host(obig[1:]).reshape(shape), host(o))
+    if dtype == H.F64:
+        assert np.array_equal(host(o), oracle.biharm(u))
+
+
 def test_biharm_f32_error_bound():
     shape = (32, 32, 32)
     u = inputs.biharm_input(shape=shape, seed=8)
