@@ -67,12 +67,12 @@ def load_traffic(kernel):
     return load_counters(kernel).get("hbm_bytes_per_launch")
 
 
-def run_gpu(mode, steps, warmup, U0, timing=True, dtype=None):
+def run_gpu(mode, steps, warmup, U0, timing=True, dtype=None, in_place=False):
     import torch
     from paper_1710_08774_amd import hfav as H
     from paper_1710_08774_amd.euler import EulerStepper
 
-    st = EulerStepper(NX, NY, mode=mode, dtype=dtype or torch.float64)
+    st = EulerStepper(NX, NY, mode=mode, dtype=dtype or torch.float64, in_place=in_place)
     st.load(U0)
     st.step(warmup)
     st.load(U0)
@@ -104,6 +104,7 @@ def run_gpu(mode, steps, warmup, U0, timing=True, dtype=None):
     out["y_kernel"] = "euler_y_strip_kernel" if st.iy.config.variant == 3 else "euler_y_kernel"
     out["x_config"] = [st.ix.config.block, st.ix.config.seg, st.ix.config.variant]
     out["y_config"] = [st.iy.config.block, st.iy.config.seg, st.iy.config.variant]
+    out["footprint_bytes"] = st.footprint_bytes()
     return out
 
 
@@ -622,6 +623,12 @@ def main(argv=None):
         aux["euler_f32_state_f64_riemann"] = {
             "ms_per_step": f32["ms_per_step"], "cell_updates_per_s": cells / (f32["ms_per_step"] * 1e-3),
             "compulsory_GBs": 64 * cells / (f32["ms_per_step"] * 1e-3) / 1e9}
+        ip = run_gpu(H.MODE_FUSED, a.steps, a.warmup, U0, True, in_place=True)
+        aux["euler_in_place"] = {
+            "ms_per_step": ip["ms_per_step"], "cell_updates_per_s": cells / (ip["ms_per_step"] * 1e-3),
+            "x_ms": ip.get("x_ms"), "y_ms": ip.get("y_ms"),
+            "footprint_bytes_in_place": ip["footprint_bytes"], "footprint_bytes_two_states": fused["footprint_bytes"],
+            "note": "one state; each sweep first saves the cells around its segment boundaries, then writes over it"}
         aux["batch_512_grids"] = batched_grids()
         aux["hdiff_256x256x8"] = hdiff_config_shape()
         aux["norm_4x4096x4096"] = norm_chain()

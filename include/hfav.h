@@ -389,7 +389,10 @@ int hfav_chain_infer(const hfav_chain_desc *patterns, hfav_chain **out);
  * overwritten and saves them first: nothing for the normalisation kernel
  * (a row is on chip before it is written), the halo columns and rows at the
  * tile and segment boundaries for the horizontal-diffusion kernel (a copy
- * kernel into the workspace), and for the unfused path nothing when the
+ * kernel into the workspace), for the hydro sweeps (each goal over the axiom
+ * of its own field; the strip kernels) the cells b-2 .. b+1 around every
+ * segment boundary b of every line (a copy kernel into the workspace;
+ * batches are not built in place), and for the unfused path nothing when the
  * goal's producer is the last rule to read the axiom and reads it at offset
  * 0 only, else a copy of the whole axiom.  Other fused families fall back
  * to the unfused path (AUTO) or fail with EUNSUP (FUSED).  The plan JSON

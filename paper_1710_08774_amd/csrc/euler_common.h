@@ -23,6 +23,12 @@ struct EArgs {
     int xcd;
     int bcy;           // boundary along y of the two-sweep kernel
     int newton_all;    // take every Newton step (no stop at a repeated iterate)
+    // in place (goal q written over axiom q): the state of the cells around
+    // every segment boundary b of every line (cells b-2 .. b+1, boundary
+    // b = s * seg for s < nsg), saved before the sweep; null otherwise.
+    // Layout [field][s][cell][line].
+    const T *halo;
+    int nsg;
 };
 
 // configuration variant bit of the Euler families: every Newton step taken

@@ -126,6 +126,12 @@ int run_fused(const hfav_chain *c, const Bind &B, hipStream_t s) {
         L.dtype = c->dtype;
         L.precision = p.opts.precision;
         L.cfg = p.info.config;
+        // in place when some goal is its axiom's buffer: the saved segment
+        // halos live in the workspace
+        for (size_t q = 0; q < c->alias.size(); ++q)
+            if (p.alias_handling[q] == HPlan::ALIAS_SEG_HALOS)
+                for (int f = 0; f < 4; ++f)
+                    if (L.in[f] == L.out[f]) L.halo = B.ws + p.alias_ws[q];
         if (L.smax_out) {
             int rc = dev_err(hfav::launch_fill_scalar(L.smax_out, 0.0, s), "reduction init");
             if (rc) return rc;

@@ -83,7 +83,7 @@ struct HPlan {
     int64_t ws_coeff = -1;                      // workspace offset of the coefficient table
     // in/out chaining: per declared alias (goal, axiom) how the plan keeps
     // it correct, and where the saved input values live in the workspace
-    enum { ALIAS_SAFE = 0, ALIAS_TILE_HALOS = 1, ALIAS_FULL_COPY = 2, ALIAS_ROWS_ON_CHIP = 3 };
+    enum { ALIAS_SAFE = 0, ALIAS_TILE_HALOS = 1, ALIAS_FULL_COPY = 2, ALIAS_ROWS_ON_CHIP = 3, ALIAS_SEG_HALOS = 4 };
     std::vector<int> alias_handling;
     std::vector<int64_t> alias_ws;              // workspace offset of the saved values, -1
     // batched plans: per-grid sizes, y-pass segment lengths and offsets

@@ -24,6 +24,9 @@
 // segment, 4-row strips for y) fill the chip evenly.  The batched sweeps run
 // the same strip body on (grid, line, segment) items.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+
 #include "kernels.h"
 #include "euler_common.h"
 #include "ops.h"
@@ -276,7 +279,17 @@ __device__ __forceinline__ int wrap_cell(int i, int n, int bc) {
     return (unsigned)i < (unsigned)n ? i : bwrap(i, n, bc);
 }
 
-template <class T, class A, bool G14, int W, int C>
+// In place (IP), a segment [j0, j1) of a line writes only its own cells but
+// reads cells j0-2 .. j1+1: the two cells before it and the two after it
+// belong to the neighbouring segments (with a periodic wrap, the first and
+// the last segment are neighbours; a single segment wraps onto itself), which
+// may already have written them.  Those reads come from the copy saved
+// before the sweep (a.halo).  A read that a transmissive end clamps onto a
+// cell of the segment itself stays direct (it comes before the segment
+// writes that cell); so do the reads of the segment's own cells, each made
+// before the cell is written (the update of cell p-1 reads it in the same
+// statement).
+template <class T, class A, bool G14, int W, int C, bool IP = false>
 __device__ __forceinline__ double strip(const EArgs<T> &a, const EView<T> &v, bool xdir, int line0, int j0, int j1,
                                         double dt, bool want_smax, SLds<T, W, C> &S) {
     using L = SLds<T, W, C>;
@@ -295,6 +308,21 @@ __device__ __forceinline__ double strip(const EArgs<T> &a, const EView<T> &v, bo
     const A nuA = (A)dt;
     double smax = 0.0;
     auto addr = [&](int cell) { return lb + (size_t)wrap_cell(cell, n, a.bc) * sa; };
+    // conserved state of a cell (unwrapped index along the sweep)
+    auto load_u = [&](int cell, T *u) {
+        const int wc = wrap_cell(cell, n, a.bc);
+        if (IP && (cell < j0 || cell >= j1) && (a.bc == HFAV_BC_PERIODIC || wc < j0 || wc >= j1)) {
+            const int s0 = j0 / a.seg;
+            const int sb = cell < j0 ? s0 : (s0 + 1 == a.nsg ? 0 : s0 + 1);     // boundary
+            const int c = cell < j0 ? cell - (j0 - 2) : 2 + (cell - j1);        // cell slot 0..3
+            const size_t fs = (size_t)a.nsg * 4 * nlines;                        // field stride
+            const size_t h = ((size_t)sb * 4 + c) * nlines + (line0 + wl);
+            u[0] = a.halo[h]; u[1] = a.halo[fs + h]; u[2] = a.halo[2 * fs + h]; u[3] = a.halo[3 * fs + h];
+            return;
+        }
+        const size_t o = lb + (size_t)wc * sa;
+        u[0] = v.rho[o]; u[1] = v.mn[o]; u[2] = v.mt[o]; u[3] = v.E[o];
+    };
     // ring slot of a cell (both rings: cell - j0 + 2 modulo C + 2)
     auto fs = [&](int cell) { return (cell - j0 + 2) % L::RF; };
     auto put = [&](int sl, const Prim<T> &w) {
@@ -312,8 +340,9 @@ __device__ __forceinline__ double strip(const EArgs<T> &a, const EView<T> &v, bo
     // prologue: cells j0-2, j0-1, j0 (C may be below 3) and the plus face of
     // cell j0-1
     for (int k = q; lact && k < 3; k += C) {
-        const size_t o = addr(j0 - 2 + k);
-        put(fs(j0 - 2 + k), euler_prim(v.rho[o], v.mn[o], v.mt[o], v.E[o], g));
+        T u0[4];
+        load_u(j0 - 2 + k, u0);
+        put(fs(j0 - 2 + k), euler_prim(u0[0], u0[1], u0[2], u0[3], g));
     }
     __syncthreads();
     if (lact && q == 0) {
@@ -341,10 +370,7 @@ __device__ __forceinline__ double strip(const EArgs<T> &a, const EView<T> &v, bo
         // these primitive slots in its stage 2, and two barriers have
         // passed since (the prologue's reads: the barrier before the loop)
         T un[4];
-        if (act) {
-            const size_t o = addr(p + 1);
-            un[0] = v.rho[o]; un[1] = v.mn[o]; un[2] = v.mt[o]; un[3] = v.E[o];
-        }
+        if (act) load_u(p + 1, un);
         if (act) put(sl(1), euler_prim(un[0], un[1], un[2], un[3], g));
         __syncthreads();
         // stage 2: slopes and trace of cell p; the plus face goes to the
@@ -395,18 +421,18 @@ __device__ __forceinline__ double strip(const EArgs<T> &a, const EView<T> &v, bo
 // x pass as strips: one workgroup per segment of a.seg cells of a row
 // (W = 1, C = B lanes along it); a segment recomputes two halo cells and
 // one interface at its start, like a y segment
-template <class T, class A, bool G14, int B>
+template <class T, class A, bool G14, int B, bool IP = false>
 __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(4))) void euler_x_strip_kernel(EArgs<T> a) {
     __shared__ SLds<T, 1, B> S;
     const int nsg = (a.nx + a.seg - 1) / a.seg;
     const int tile = xcd_tile(blockIdx.x, a.ny * nsg, a.xcd);
     const int j = tile / nsg, i0 = (tile % nsg) * a.seg;
-    strip<T, A, G14, 1, B>(a, full_view(a), true, j, i0, min(i0 + a.seg, a.nx), read_dt(a.dt_src, a.dt_mode, a.cfl),
-                           false, S);
+    strip<T, A, G14, 1, B, IP>(a, full_view(a), true, j, i0, min(i0 + a.seg, a.nx),
+                               read_dt(a.dt_src, a.dt_mode, a.cfl), false, S);
 }
 
 // y pass as strips: 64 columns x C rows per chunk, segments of a.seg rows
-template <class T, class A, bool G14, int C>
+template <class T, class A, bool G14, int C, bool IP = false>
 __global__ __launch_bounds__(64 * C) __attribute__((amdgpu_waves_per_eu(4))) void euler_y_strip_kernel(EArgs<T> a) {
     __shared__ SLds<T, 64, C> S;
     const int ntx = (a.nx + 63) / 64, nsg = (a.ny + a.seg - 1) / a.seg;
@@ -414,9 +440,29 @@ __global__ __launch_bounds__(64 * C) __attribute__((amdgpu_waves_per_eu(4))) voi
     const int i0 = (tile % ntx) * 64;
     const int j0 = (tile / ntx) * a.seg;
     const int j1 = min(j0 + a.seg, a.ny);
-    const double smax = strip<T, A, G14, 64, C>(a, full_view(a), false, i0, j0, j1,
-                                                read_dt(a.dt_src, a.dt_mode, a.cfl), a.smax_out != nullptr, S);
+    const double smax = strip<T, A, G14, 64, C, IP>(a, full_view(a), false, i0, j0, j1,
+                                                    read_dt(a.dt_src, a.dt_mode, a.cfl), a.smax_out != nullptr, S);
     if (a.smax_out) block_max_to<64 * C>(smax, a.smax_out);
+}
+
+// Saves the state of the cells b-2 .. b+1 around every segment boundary
+// b = s * seg (s < nsg) of every line, boundary applied, for an in-place
+// sweep (layout [field][s][cell][line]: consecutive threads take
+// consecutive lines, contiguous in memory for the y sweep).
+template <class T>
+__global__ __launch_bounds__(256) void euler_halo_save_kernel(EArgs<T> a, int xdir, T *halo) {
+    const int n = xdir ? a.nx : a.ny, nlines = xdir ? a.ny : a.nx;
+    const size_t per_field = (size_t)a.nsg * 4 * nlines;
+    for (size_t q = (size_t)blockIdx.x * 256 + threadIdx.x; q < 4 * per_field; q += (size_t)gridDim.x * 256) {
+        const int f = (int)(q / per_field);
+        const size_t r = q - (size_t)f * per_field;
+        const int line = (int)(r % nlines);
+        const int sc = (int)(r / nlines), c = sc & 3, sg = sc >> 2;
+        const int cell = bwrap(sg * a.seg - 2 + c, n, a.bc);
+        const size_t o = xdir ? (size_t)line * a.nx + cell : (size_t)cell * a.nx + line;
+        const T *src = f == 0 ? a.rho : f == 1 ? a.mn : f == 2 ? a.mt : a.E;
+        halo[q] = src[o];
+    }
 }
 
 // ------------------------------------------------------------------ batches
@@ -539,7 +585,32 @@ static EArgs<T> make_args(const EulerLaunch &L) {
     a.seg = L.cfg.seg > 0 ? L.cfg.seg : 16;
     a.xcd = L.cfg.xcd;
     a.newton_all = (L.cfg.variant & EULER_NEWTON_ALL) != 0;
+    a.halo = (const T *)L.halo;
+    a.nsg = 0;
     return a;
+}
+
+int euler_strip_seg(int n, int dir, const hfav_config &cfg) {
+    if (dir == 0) return cfg.seg > 0 && cfg.seg < n ? cfg.seg : n;
+    return cfg.seg > 0 ? cfg.seg : 16;
+}
+
+size_t euler_inplace_bytes(int nx, int ny, int dir, int dtype, const hfav_config &cfg) {
+    const int n = dir == 0 ? nx : ny, nlines = dir == 0 ? ny : nx;
+    const size_t nsg = (n + euler_strip_seg(n, dir, cfg) - 1) / euler_strip_seg(n, dir, cfg);
+    return 4 * nsg * 4 * (size_t)nlines * (dtype == HFAV_F64 ? 8 : 4);
+}
+
+// in place: save the segment-boundary cells, then run the in-place strip
+template <class T>
+static hipError_t save_halos(EArgs<T> &a, bool xdir, hipStream_t s) {
+    const int n = xdir ? a.nx : a.ny, nlines = xdir ? a.ny : a.nx;
+    a.nsg = (n + a.seg - 1) / a.seg;
+    const size_t total = 4 * (size_t)a.nsg * 4 * nlines;
+    const unsigned nb = (unsigned)std::min<size_t>((total + 255) / 256, 8192);
+    hipLaunchKernelGGL((euler_halo_save_kernel<T>), dim3(nb), dim3(256), 0, s, a, xdir ? 1 : 0,
+                       const_cast<T *>(a.halo));
+    return hipGetLastError();
 }
 
 // The variant sets the occupancy the compiler must reach: 0 leaves the
@@ -559,8 +630,15 @@ static hipError_t euler_x_dispatch(const EulerLaunch &L, hipStream_t s) {
     dim3 grid(L.ny);
     if ((L.cfg.variant & ~EULER_NEWTON_ALL) == 3) {
         // segments of cfg.seg cells (0: whole rows)
-        a.seg = L.cfg.seg > 0 && L.cfg.seg < L.nx ? L.cfg.seg : L.nx;
+        a.seg = euler_strip_seg(L.nx, 0, L.cfg);
         grid = dim3((unsigned)(L.ny * ((L.nx + a.seg - 1) / a.seg)));
+        if (L.halo) {
+            if (L.cfg.block != 64) return hipErrorInvalidValue;
+            const hipError_t e = save_halos(a, true, s);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL((euler_x_strip_kernel<T, A, G14, 64, true>), grid, dim3(64), 0, s, a);
+            return hipGetLastError();
+        }
         switch (L.cfg.block) {
         case 64: hipLaunchKernelGGL((euler_x_strip_kernel<T, A, G14, 64>), grid, dim3(64), 0, s, a); break;
         case 128: hipLaunchKernelGGL((euler_x_strip_kernel<T, A, G14, 128>), grid, dim3(128), 0, s, a); break;
@@ -568,6 +646,7 @@ static hipError_t euler_x_dispatch(const EulerLaunch &L, hipStream_t s) {
         }
         return hipGetLastError();
     }
+    if (L.halo) return hipErrorInvalidValue;      // in place: strip kernels only
     switch (L.cfg.block) {
     case 64: E_LAUNCH(euler_x_kernel, 64); break;
     case 128: E_LAUNCH(euler_x_kernel, 128); break;
@@ -582,6 +661,13 @@ static hipError_t euler_y_dispatch(const EulerLaunch &L, hipStream_t s) {
     if ((L.cfg.variant & ~EULER_NEWTON_ALL) == 3) {
         // 64 columns per workgroup, block / 64 rows per chunk
         dim3 grid(((L.nx + 63) / 64) * ((L.ny + a.seg - 1) / a.seg));
+        if (L.halo) {
+            if (L.cfg.block != 256) return hipErrorInvalidValue;
+            const hipError_t e = save_halos(a, false, s);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL((euler_y_strip_kernel<T, A, G14, 4, true>), grid, dim3(256), 0, s, a);
+            return hipGetLastError();
+        }
         switch (L.cfg.block) {
         case 128: hipLaunchKernelGGL((euler_y_strip_kernel<T, A, G14, 2>), grid, dim3(128), 0, s, a); break;
         case 512: hipLaunchKernelGGL((euler_y_strip_kernel<T, A, G14, 8>), grid, dim3(512), 0, s, a); break;
@@ -589,6 +675,7 @@ static hipError_t euler_y_dispatch(const EulerLaunch &L, hipStream_t s) {
         }
         return hipGetLastError();
     }
+    if (L.halo) return hipErrorInvalidValue;      // in place: strip kernels only
     const int B = (L.cfg.block == 64 || L.cfg.block == 128 || L.cfg.block == 256) ? L.cfg.block : 64;
     dim3 grid(((L.nx + B - 1) / B) * ((L.ny + a.seg - 1) / a.seg));
     switch (B) {

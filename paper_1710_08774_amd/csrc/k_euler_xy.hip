@@ -142,6 +142,8 @@ hipError_t launch_xy_t(const EulerLaunch &L, hipStream_t s) {
     a.seg = L.cfg.seg > 0 ? L.cfg.seg : 16;
     a.xcd = L.cfg.xcd;
     a.newton_all = (L.cfg.variant & EULER_NEWTON_ALL) != 0;
+    a.halo = nullptr;
+    a.nsg = 0;
     const int ns = (L.nx + XY_W - 1) / XY_W, nsg = (L.ny + a.seg - 1) / a.seg;
     const dim3 grid((unsigned)(ns * nsg));
     if (L.gamma == 1.4) hipLaunchKernelGGL((euler_xy_kernel<T, A, true>), grid, dim3(64), 0, s, a);

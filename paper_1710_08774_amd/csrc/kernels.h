@@ -27,7 +27,16 @@ struct EulerLaunch {
     int precision;         // hfav_precision
     hfav_config cfg;
     int bcy;               // boundary along y (both sweeps in one kernel)
+    // in place (out[q] == in[q]): workspace of euler_inplace_bytes for the
+    // cells around the segment boundaries, saved before the sweep; null
+    // when not in place.  Strip kernels only (variant 3; x: 64-cell chunks,
+    // y: 4-row chunks).
+    void *halo = nullptr;
 };
+// workspace bytes of an in-place sweep along x (dir 0) or y (dir 1)
+size_t euler_inplace_bytes(int nx, int ny, int dir, int dtype, const hfav_config &cfg);
+// segment length a strip sweep runs with (the configuration's, or its default)
+int euler_strip_seg(int n, int dir, const hfav_config &cfg);
 hipError_t launch_euler_x(const EulerLaunch &L, hipStream_t s);
 // x sweep then y sweep of one time step in one kernel; in/out in the
 // physical frame (rho, mx, my, E), bc along x, bcy along y, cfg.seg rows per

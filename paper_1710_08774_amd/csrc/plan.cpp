@@ -941,19 +941,46 @@ int hfav_plan_impl(hfav_chain *c, const hfav_plan_opts *o, hfav_plan_info *info)
     //  * HDIFF: only the 2-wide halo columns and rows at tile and segment
     //    boundaries are at risk (the LDS ring is the rolling input buffer):
     //    saved by a copy kernel;
+    //  * EULER_X / EULER_Y (each goal written over the axiom of the same
+    //    field): a strip segment reads the 2 cells on either side of it,
+    //    which the neighbouring segments write: the cells around every
+    //    segment boundary are saved by a copy kernel (strip kernels only);
     //  * other fused families: not built; AUTO falls back to unfused;
     //  * unfused: safe when the goal's producer is the last rule to read the
     //    axiom and reads it at offset 0 only; otherwise the whole axiom is
     //    copied and every rule reads the copy.
     p.alias_handling.assign(c->alias.size(), HPlan::ALIAS_SAFE);
     p.alias_ws.assign(c->alias.size(), -1);
+    bool euler_ip = false;
     if (!c->alias.empty() && fused) {
         const bool norm_ok = p.family == HFAV_FAMILY_NORM && cfg.variant != 1;
         const bool hdiff_ok = p.family == HFAV_FAMILY_HDIFF;
-        if (!norm_ok && !hdiff_ok) {
+        bool euler_ok = false;
+        if (p.family == HFAV_FAMILY_EULER_X || p.family == HFAV_FAMILY_EULER_Y) {
+            euler_ok = true;
+            for (const auto &pr : c->alias) {
+                bool same_field = false;
+                for (int q = 0; q < 4; ++q)
+                    if (pr.first == p.fam_out[q] && pr.second == p.fam_in[q]) same_field = true;
+                euler_ok = euler_ok && same_field;
+            }
+            // the in-place sweep runs the strip kernel: 64-cell chunks of
+            // one row along x, 64 columns x 4 rows along y
+            const int sblock = p.family == HFAV_FAMILY_EULER_X ? 64 : 256;
+            if (euler_ok && src != HFAV_CONFIG_FORCED && ((cfg.variant & 63) != 3 || cfg.block != sblock)) {
+                cfg.variant = 3 | (cfg.variant & 64);
+                cfg.block = sblock;
+                if (p.family == HFAV_FAMILY_EULER_Y && cfg.seg <= 0) cfg.seg = 15;
+            }
+            euler_ok = euler_ok && (cfg.variant & 63) == 3 && cfg.block == sblock;
+            euler_ip = euler_ok;
+        }
+        if (!norm_ok && !hdiff_ok && !euler_ok) {
             if (o->mode == HFAV_MODE_FUSED)
-                return hfav_fail(HFAV_EUNSUP, "in-place execution of this fused kernel family is not built "
-                                              "(normalisation with the row on chip, horizontal diffusion)");
+                return hfav_fail(HFAV_EUNSUP, "in-place execution of this fused kernel family or configuration is "
+                                              "not built (normalisation with the row on chip, horizontal "
+                                              "diffusion, the hydro sweeps' strip kernels with each goal over "
+                                              "its own field's axiom)");
             fused = false;
         }
         // in place, wider tiles and longer segments mean fewer boundaries
@@ -994,6 +1021,20 @@ int hfav_plan_impl(hfav_chain *c, const hfav_plan_opts *o, hfav_plan_info *info)
         if (fused) {
             if (p.family == HFAV_FAMILY_NORM) {
                 p.alias_handling[q] = HPlan::ALIAS_ROWS_ON_CHIP;
+            } else if (euler_ip) {      // one area of saved segment halos serves every pair
+                p.alias_handling[q] = HPlan::ALIAS_SEG_HALOS;
+                bool first = true;
+                for (size_t r = 0; r < q; ++r)
+                    if (p.alias_handling[r] == HPlan::ALIAS_SEG_HALOS) {
+                        p.alias_ws[q] = p.alias_ws[r];
+                        first = false;
+                    }
+                if (first) {
+                    p.alias_ws[q] = (int64_t)p.ws_bytes;
+                    p.ws_bytes += (hfav::euler_inplace_bytes(o->dims[0], o->dims[1],
+                                                             p.family == HFAV_FAMILY_EULER_X ? 0 : 1, c->dtype, cfg) +
+                                   255) / 256 * 256;
+                }
             } else {                    // HDIFF: one halo-copy area serves the pair
                 p.alias_handling[q] = HPlan::ALIAS_TILE_HALOS;
                 p.alias_ws[q] = (int64_t)p.ws_bytes;
@@ -1116,7 +1157,8 @@ int hfav_plan_impl(hfav_chain *c, const hfav_plan_opts *o, hfav_plan_info *info)
     }
     js << "],\"aliases\":[";
     for (size_t q = 0; q < c->alias.size(); ++q) {
-        static const char *hname[] = {"safe", "tile_halo_copies", "full_copy", "rows_on_chip"};
+        static const char *hname[] = {"safe", "tile_halo_copies", "full_copy", "rows_on_chip",
+                                      "segment_halo_copies"};
         const HTermPlan &tp = p.terms[c->alias[q].second];
         js << (q ? "," : "") << "{\"goal\":" << jstr(c->terms[c->alias[q].first].name)
            << ",\"axiom\":" << jstr(c->terms[c->alias[q].second].name) << ",\"extent_lo\":";
@@ -1176,6 +1218,7 @@ extern "C" int hfav_plan_batch(hfav_chain *chain, const hfav_plan_opts *opts, in
         if (dims[2 * g] < 1 || dims[2 * g] > 65535 || dims[2 * g + 1] < 1 || dims[2 * g + 1] > 65535)
             return hfav_fail(HFAV_EINVAL, "batch grid size out of range");
     if (opts->mode == HFAV_MODE_UNFUSED) return hfav_fail(HFAV_EUNSUP, "batches run the fused kernels only");
+    if (!chain->alias.empty()) return hfav_fail(HFAV_EUNSUP, "in-place batches are not built");
     hfav_plan_opts o = *opts;
     o.dims[0] = dims[0];
     o.dims[1] = dims[1];

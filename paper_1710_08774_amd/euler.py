@@ -17,13 +17,17 @@ from . import hfav as H
 class EulerStepper:
     """fused_step=True runs each step as ONE chain (both sweeps; the
     two-sweep kernel keeps the x-swept state on chip); otherwise one chain
-    per sweep."""
+    per sweep.  in_place=True keeps ONE state: each sweep's goals are
+    declared over its axioms (hfav_chain_alias) and written over them."""
 
     def __init__(self, nx, ny, dtype=torch.float64, gamma=1.4, cfl=0.5, niter=10,
                  bc=H.BC_PERIODIC, mode=H.MODE_FUSED, precision=H.PREC_NATIVE,
                  config_source=H.CONFIG_DEFAULT, forced_x=None, forced_y=None, device="cuda",
-                 fused_step=False, forced_xy=None):
+                 fused_step=False, forced_xy=None, in_place=False):
+        if in_place and fused_step:
+            raise ValueError("in-place execution runs one chain per sweep")
         self.nx, self.ny = nx, ny
+        self.in_place = in_place
         self.dtype = dtype
         cd = H.F64 if dtype == torch.float64 else H.F32
         if cd == H.F32 and precision == H.PREC_NATIVE:
@@ -33,6 +37,10 @@ class EulerStepper:
         self.smax_chain.plan((nx, ny), (bc, bc), mode=H.MODE_AUTO)
         self.cx = H.Chain(H.euler_sweep_spec(0, gamma, niter, cfl, "smax", False, cd))
         self.cy = H.Chain(H.euler_sweep_spec(1, gamma, niter, cfl, "smax", True, cd))
+        if in_place:
+            for ch in (self.cx, self.cy):
+                for g, a in zip(H.EULER_GOALS, H.EULER_AXIOMS):
+                    ch.alias(g, a)
         fx = H.CONFIG_FORCED if forced_x is not None else config_source
         fy = H.CONFIG_FORCED if forced_y is not None else config_source
         self.ix = self.cx.plan((nx, ny), (bc, bc), mode=mode, precision=precision, config_source=fx,
@@ -45,13 +53,22 @@ class EulerStepper:
             fxy = H.CONFIG_FORCED if forced_xy is not None else config_source
             self.ixy = self.cxy.plan((nx, ny), (bc, bc), mode=mode, precision=precision, config_source=fxy,
                                      forced=forced_xy)
-        self.U = [torch.empty((4, ny, nx), dtype=dtype, device=device) for _ in range(2)]
+        if in_place:
+            u = torch.empty((4, ny, nx), dtype=dtype, device=device)
+            self.U = [u, u]          # both sweeps read and write the one state
+        else:
+            self.U = [torch.empty((4, ny, nx), dtype=dtype, device=device) for _ in range(2)]
         self.smax = torch.zeros(2, dtype=torch.float64, device=device)
         ws = max(self.ix.workspace_bytes, self.iy.workspace_bytes,
                  self.ixy.workspace_bytes if self.ixy is not None else 0)
         self.ws = torch.empty(ws, dtype=torch.uint8, device=device) if ws else None
         self.cur = 0
         self.slot = 0
+
+    def footprint_bytes(self):
+        """Device bytes of the state buffers and the workspace."""
+        states = 1 if self.in_place else 2
+        return states * self.U[0].numel() * self.U[0].element_size() + (self.ws.numel() if self.ws is not None else 0)
 
     def load(self, U):
         self.U[0].copy_(torch.as_tensor(U, dtype=self.dtype))

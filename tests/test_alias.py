@@ -101,3 +101,60 @@ def test_alias_declaration_errors_and_execute_rules():
                        rules=[H.Rule("DIV0", [("u", Z), ("r", Z)], ["y"])])
     with pytest.raises(H.HfavError):
         H.Chain(rank).alias("y", "r")
+
+
+def _euler_in_place(direction, pairs=None):
+    c = H.Chain(H.euler_sweep_spec(direction, with_smax=direction == 1))
+    for g, a in pairs or zip(H.EULER_GOALS, H.EULER_AXIOMS):
+        c.alias(g, a)
+    return c
+
+
+@pytest.mark.parametrize("direction", [0, 1])
+def test_hydro_sweeps_in_place_save_segment_halos(direction):
+    """Each sweep written over its state: the strip kernel, and a workspace
+    for the cells b-2 .. b+1 around every segment boundary b of every line,
+    4 fields."""
+    nx, ny = 300, 200
+    c = _euler_in_place(direction)
+    info = c.plan((nx, ny))
+    assert info.fused
+    cfg = info.config
+    assert cfg.variant & 63 == 3 and cfg.block == (64 if direction == 0 else 256)
+    al = _aliases(c)
+    assert len(al) == 4 and all(a["handling"] == "segment_halo_copies" for a in al.values())
+    n, nlines = (nx, ny) if direction == 0 else (ny, nx)
+    seg = cfg.seg if direction == 1 else (cfg.seg if 0 < cfg.seg < nx else nx)
+    nsg = -(-n // seg)
+    assert info.workspace_bytes == (4 * nsg * 4 * nlines * 8 + 255) // 256 * 256
+    # out of place: no workspace
+    assert H.Chain(H.euler_sweep_spec(direction)).plan((nx, ny)).workspace_bytes == 0
+
+
+def test_hydro_in_place_needs_each_goal_over_its_own_field():
+    pairs = [("rho_n", "E"), ("E_n", "rho")]
+    c = _euler_in_place(0, pairs)
+    info = c.plan((128, 64))                      # AUTO: the unfused path
+    assert not info.fused
+    with pytest.raises(H.HfavError) as e:
+        c.plan((128, 64), mode=H.MODE_FUSED)
+    assert e.value.code == H.EUNSUP
+
+
+def test_hydro_in_place_with_a_forced_non_strip_kernel_falls_back():
+    c = _euler_in_place(1)
+    info = c.plan((128, 64), config_source=H.CONFIG_FORCED, forced=(64, 1, 16, 0))
+    assert not info.fused
+    with pytest.raises(H.HfavError) as e:
+        c.plan((128, 64), mode=H.MODE_FUSED, config_source=H.CONFIG_FORCED, forced=(64, 1, 16, 0))
+    assert e.value.code == H.EUNSUP
+    # a forced strip configuration runs fused in place
+    info = c.plan((128, 64), mode=H.MODE_FUSED, config_source=H.CONFIG_FORCED, forced=(256, 1, 7, 3))
+    assert info.fused and info.workspace_bytes > 0
+
+
+def test_in_place_batches_are_refused():
+    c = _euler_in_place(0)
+    with pytest.raises(H.HfavError) as e:
+        c.plan_batch([(64, 32), (40, 50)])
+    assert e.value.code == H.EUNSUP

@@ -152,6 +152,20 @@ def test_hydro_f64_2048_hundred_steps_parity(hydro_2048_100):
     assert max(e) <= 1e-12
 
 
+def test_hydro_in_place_2048_hundred_steps_parity(hydro_2048_100):
+    """The 2048^2 workload over its 100 steps with each sweep written over
+    the one state: within 1e-12 of the oracle per physical field."""
+    U, ref, dts = hydro_2048_100
+    st = EulerStepper(2048, 2048, in_place=True)
+    st.load(U)
+    st.step(100)
+    got = host(st.state())
+    e = hydro_errs(got, ref)
+    _report("hydro_f64_in_place_2048x2048_100", {"max_rel_error_physical": dict(zip(("rho", "momentum", "E"), e)),
+                                                 "footprint_bytes": st.footprint_bytes()})
+    assert max(e) <= 1e-12
+
+
 def test_hydro_f32_2048_hundred_steps_error(hydro_2048_100):
     """FP32 state, FP64 Riemann iteration and update accumulation, 100 steps
     of the 2048^2 workload.  Bound, per physical field (density, momentum
