@@ -78,7 +78,11 @@ def run_gpu(mode, steps, warmup, U0, timing=True, dtype=None, in_place=False):
     st.load(U0)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)] if timing else None
+    # two events per step on the launch stream: before the x sweep and
+    # between the sweeps; the end of a step is the start of the next (one
+    # more event after the last step)
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(steps)] if timing else None
+    end = torch.cuda.Event(enable_timing=True) if timing else None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(steps):
@@ -89,14 +93,15 @@ def run_gpu(mode, steps, warmup, U0, timing=True, dtype=None, in_place=False):
             evs[s][1].record(stream)
         st.sweep_y()
         st.slot = 1 - st.slot
-        if timing:
-            evs[s][2].record(stream)
+    if timing:
+        end.record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     out = {"ms_per_step": (t1 - t0) * 1e3 / steps, "seconds": t1 - t0}
     if timing:
+        nxt = [evs[s + 1][0] for s in range(steps - 1)] + [end]
         out["x_ms"] = sum(e[0].elapsed_time(e[1]) for e in evs) / steps
-        out["y_ms"] = sum(e[1].elapsed_time(e[2]) for e in evs) / steps
+        out["y_ms"] = sum(e[1].elapsed_time(n) for e, n in zip(evs, nxt)) / steps
     out["state_finite"] = bool(torch.isfinite(st.state()).all())
     out["info_fused"] = int(st.ix.fused and st.iy.fused)
     # kernel names of the fused sweeps (variant 3 selects the strip kernels)
