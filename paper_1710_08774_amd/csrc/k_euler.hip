@@ -505,7 +505,7 @@ __device__ __forceinline__ EView<T> grid_view(const EArgs<T> &a, const BatchDims
 constexpr int BATCH_XSEG = 191;
 
 template <class T, class A, bool G14>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void euler_x_batch_kernel(EArgs<T> a, BatchDims d, long long items) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void euler_x_batch_kernel(EArgs<T> a, BatchDims d, long long items) {
     __shared__ SLds<T, 1, 64> S;
     Cursor c{0, 0, 0};
     auto segs = [&](int g) { return (long long)d.ny[g] * ((d.nx[g] + BATCH_XSEG - 1) / BATCH_XSEG); };
@@ -522,7 +522,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void eu
 
 // y items: tiles of 64 columns x seg[g] rows, 4-wave strips (C = 4)
 template <class T, class A, bool G14>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void euler_y_batch_kernel(EArgs<T> a, BatchDims d, long long items) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void euler_y_batch_kernel(EArgs<T> a, BatchDims d, long long items) {
     __shared__ SLds<T, 64, 4> S;
     Cursor c{0, 0, 0};
     auto tiles = [&](int g) {
@@ -754,9 +754,11 @@ static hipError_t batch_dispatch(const EulerLaunch &L, const EulerBatch &Bt, boo
         items += x ? (long long)Bt.ny[g] * ((Bt.nx[g] + BATCH_XSEG - 1) / BATCH_XSEG)
                    : (long long)((Bt.nx[g] + 63) / 64) * ((Bt.ny[g] + Bt.seg[g] - 1) / Bt.seg[g]);
     }
-    // resident pool: 5 waves per SIMD on 256 CUs, as one-wave x workgroups
-    // or four-wave y workgroups
-    const long long cap = (long long)(Bt.workgroups > 0 ? Bt.workgroups : (x ? 256 * 20 : 256 * 5));
+    // resident pool: 4 waves per SIMD on 256 CUs (the register budget at
+    // which the sweep bodies run without spilling: at 5 waves the unrolled
+    // Newton loop spilled 72-84 bytes per lane and a step took 17.1-17.3 ms
+    // against 15.6), as one-wave x workgroups or four-wave y workgroups
+    const long long cap = (long long)(Bt.workgroups > 0 ? Bt.workgroups : (x ? 256 * 16 : 256 * 4));
     const unsigned nwg = (unsigned)(items < cap ? items : cap);
     if (nwg == 0) return hipSuccess;
     if (x) hipLaunchKernelGGL((euler_x_batch_kernel<T, A, G14>), dim3(nwg), dim3(64), 0, s, a, d, items);
