@@ -46,7 +46,7 @@ __device__ __forceinline__ Prim<T> nb(const Prim<T> &w, bool edge) {
 }
 
 template <class T, class A, bool G14>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void euler_xy_kernel(EArgs<T> a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void euler_xy_kernel(EArgs<T> a) {
     __shared__ T s_u[3][4][64];            // U^x of the lane's last three rows (y frame)
     const int nx = a.nx, ny = a.ny, l = threadIdx.x;
     const int ns = (nx + XY_W - 1) / XY_W, nsg = (ny + a.seg - 1) / a.seg;

@@ -110,14 +110,23 @@ constexpr int rule_nout() {
 template <int OP, class T, class A, bool G14, bool FAST>
 __device__ __forceinline__ void rule_cell(const UArgs &a, const UCell &cell, T *v);
 
+// the hydro rules compute far more per byte than they stream
+template <int OP>
+constexpr bool euler_rule() {
+    return OP == HFAV_OP_EULER_PRIM || OP == HFAV_OP_EULER_SLOPE || OP == HFAV_OP_EULER_TRACE ||
+           OP == HFAV_OP_EULER_RIEMANN || OP == HFAV_OP_EULER_FLUX || OP == HFAV_OP_EULER_UPDATE;
+}
+
 // The rows of a block two at a time: both rows' outputs are computed into
 // registers before either is stored, so the loads of the second row do not
 // wait behind the first row's stores (an output may alias no input, but the
 // compiler cannot know that) and twice the bytes are in flight per wave.
+// The hydro rules take one row at a time: paired, the Riemann rule needs
+// 129 registers (3 waves per SIMD) for no streaming gain.
 template <int OP, class T, class A, bool G14, bool FAST>
 __device__ __forceinline__ void rule_rows(const UArgs &a, UCell c, int j1) {
     constexpr int NO = rule_nout<OP>();
-    for (; c.j + 1 < j1; c.j += 2, c.row += 2) {
+    for (; !euler_rule<OP>() && c.j + 1 < j1; c.j += 2, c.row += 2) {
         UCell d = c;
         ++d.j;
         ++d.row;
@@ -129,7 +138,7 @@ __device__ __forceinline__ void rule_rows(const UArgs &a, UCell c, int j1) {
 #pragma unroll
         for (int q = 0; q < NO; ++q) st<T>(a, q, d, v1[q]);
     }
-    if (c.j < j1) {
+    for (; c.j < j1; ++c.j, ++c.row) {
         T v0[NO];
         rule_cell<OP, T, A, G14, FAST>(a, c, v0);
 #pragma unroll
