@@ -434,7 +434,9 @@ def hdiff_config_shape(execs=1000):
 def batched_grids(steps=50, loop_steps=4):
     """512 independent grids of uneven sizes (sides 64..1024), each with its
     own dt: the batched persistent sweeps with `steps` steps captured in one
-    HIP graph, against a loop of per-grid fused launches."""
+    HIP graph, against a loop of per-grid fused launches, and against the
+    one-launch step (both sweeps of every grid in one persistent launch per
+    step, the same segments; its final state compared bit for bit)."""
     import torch
     from paper_1710_08774_amd import hfav as H
     from paper_1710_08774_amd import inputs, tune
@@ -449,6 +451,8 @@ def batched_grids(steps=50, loop_steps=4):
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     bt = EulerBatchStepper(sizes, config_source=H.CONFIG_TUNED)
+    one = EulerBatchStepper(sizes, config_source=H.CONFIG_TUNED, fused_step=True)
+    assert one.y_segments() == bt.y_segments()
     segs = {}
     for (nx, ny), sg in zip(sizes, bt.y_segments()):
         b = "64-255" if max(nx, ny) < 256 else ("256-511" if max(nx, ny) < 512 else "512-1024")
@@ -465,7 +469,18 @@ def batched_grids(steps=50, loop_steps=4):
     torch.cuda.synchronize()
     ms_batch = e0.elapsed_time(e1) / steps
     finite = bool(torch.isfinite(bt.U[0]).all())
-    del bt
+    one.load(states)
+    one.step(2)
+    one.capture(steps)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    one.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_one = e0.elapsed_time(e1) / steps
+    one_status = one.step_status()
+    one_equal = bool(torch.equal(one.U[one.cur], bt.U[bt.cur]) and torch.equal(one.smax, bt.smax))
+    del bt, one
     torch.cuda.empty_cache()
     loop = []
     for (nx, ny), U in zip(sizes, states):
@@ -489,7 +504,10 @@ def batched_grids(steps=50, loop_steps=4):
             "loop_of_per_grid_launches": {"ms_per_step": ms_loop, "cell_updates_per_s": cells / (ms_loop * 1e-3),
                                           "steps": loop_steps},
             "batched_over_loop": ms_loop / ms_batch, "state_finite": finite,
-            "y_segments_by_bucket": segs}
+            "y_segments_by_bucket": segs,
+            "one_launch_step": {"ms_per_step": ms_one, "cell_updates_per_s": cells / (ms_one * 1e-3),
+                                "per_sweep_over_one_launch": ms_batch / ms_one,
+                                "bitwise_equal_to_per_sweep": one_equal, "status": one_status}}
 
 
 def cpu_model():

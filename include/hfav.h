@@ -418,9 +418,11 @@ const char *hfav_build_id(void);
 /* ------------------------------------------------------------- batches */
 #define HFAV_MAX_BATCH 640
 
-/* Plan a 2-D Euler sweep chain (or its CFL reduction) for a batch of
- * independent grids of different sizes, advanced together by persistent
- * kernels (one launch per sweep for all grids).  dims: host array
+/* Plan a 2-D Euler sweep chain, a time step of both sweeps (the chain of
+ * the EULER_XY family), or the CFL reduction for a batch of independent
+ * grids of different sizes, advanced together by persistent kernels: one
+ * launch per sweep for all grids, or for the time step ONE launch for both
+ * sweeps of all grids.  dims: host array
  * (n_grids, 2) of (nx, ny), each in [1, 65535]; opts.dims is ignored.  Every
  * grid term is then ONE packed device buffer holding grid g at element
  * offset hfav_batch_offset(chain, g), and every 0-D term is a device array of
@@ -429,8 +431,28 @@ const char *hfav_build_id(void);
  * from the configuration source (the tuning table is consulted with that
  * grid's own size; a forced configuration gives every grid its seg).  Host
  * only; allocates nothing.
+ *
+ * The time step in one launch (Design, "Fusing iteration nests": the two
+ * sweeps' nests fused; the x-swept state is not contracted across grids'
+ * work items, so it lives in the workspace): each execute first deals the
+ * grids to the device's XCDs (one launch of one workgroup: snake order over
+ * the grid sizes, largest first), then runs every item of a grid on its
+ * XCD, so the x-swept state passes through one L2.  Per XCD one atomic
+ * cursor hands out the x items of its grids (4 rows x 191 cells) before any
+ * y item; a y item of grid g first waits until every x item of g has
+ * finished (a bounded number of polls).  info.workspace_bytes = 4096 + 4
+ * planes of the packed size, each padded to 256 bytes.  Workspace byte 0
+ * holds a 32-bit status word after the step: 0, or bit 0 set when a y item
+ * gave up waiting (its cells are not updated and its grid's CFL slot holds
+ * NaN), bit 1 when the items of an XCD were not all taken (an XCD that ran
+ * no workgroup).  No correct run sets either: every item a y item waits for
+ * is already held by a running workgroup, and the hardware deals the
+ * 1024 workgroups round robin over the XCDs.  Configuration variant bit
+ * 128 makes every wait target a count that is never reached, with 64
+ * polls, to test that path.
  * Errors: EINVAL (bad sizes, n_grids not in [1, HFAV_MAX_BATCH]), EUNSUP
- * (chain not an Euler sweep or CFL reduction, or unfused mode). */
+ * (chain not an Euler sweep, time step or CFL reduction, unfused mode, or
+ * in-place aliases). */
 int hfav_plan_batch(hfav_chain *chain, const hfav_plan_opts *opts, int n_grids, const int *dims,
                     hfav_plan_info *info);
 

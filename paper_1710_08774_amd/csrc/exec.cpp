@@ -74,8 +74,10 @@ int run_batch(const hfav_chain *c, const Bind &B, hipStream_t s) {
     hfav::EulerLaunch L;
     for (int q = 0; q < 4; ++q) { L.in[q] = B.ptr(p.fam_in[q]); L.out[q] = B.wptr(p.fam_out[q]); }
     L.nx = L.ny = 0;
+    const bool step = p.family == HFAV_FAMILY_EULER_XY;
     const int dir = p.family == HFAV_FAMILY_EULER_X ? 0 : 1;
-    L.bc = p.opts.boundary[dir];
+    L.bc = p.opts.boundary[step ? 0 : dir];
+    L.bcy = p.opts.boundary[1];
     L.gamma = p.fam_param[0];
     L.niter = (int)p.fam_param[1];
     L.dt_src = (const double *)B.ptr(p.fam_dt_term);
@@ -85,6 +87,14 @@ int run_batch(const hfav_chain *c, const Bind &B, hipStream_t s) {
     L.dtype = c->dtype;
     L.precision = p.opts.precision;
     L.cfg = p.info.config;
+    if (step) {
+        // the configuration's variant bit 128 makes every wait target a
+        // count the x items never reach (tests the give-up path)
+        const bool test_giveup = (L.cfg.variant & hfav::EULER_STEP_TEST_GIVEUP) != 0;
+        return dev_err(hfav::launch_euler_step_batch(L, Bt, B.ws, test_giveup ? 64 : hfav::STEP_BATCH_SPIN_LIMIT,
+                                                     test_giveup ? 1u : 0u, s),
+                       "batched step launch");
+    }
     if (L.smax_out) {
         int rc = dev_err(hfav::launch_fill_batch(L.smax_out, Bt.n, 0.0, s), "reduction init");
         if (rc) return rc;

@@ -541,6 +541,196 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void e
     }
 }
 
+// ------------------------------------------------------------------ batch step
+// Both sweeps of a time step for every grid of a batch in ONE persistent
+// launch.  x items: 4 rows x a 191-cell segment (lanes take 4 adjacent rows
+// of 64-cell chunks); y items: 64 columns x seg[g] rows, as in the y pool.
+// x items write the x-swept state to a workspace copy; a y item of grid g
+// reads it once every x item of g has finished.
+//
+// Every item of a grid runs on ONE XCD, so the x-swept state passes through
+// that XCD's L2 only: the 8 L2 caches are not coherent with each other
+// within a launch, and making every x item's stores visible to all of them
+// (an L2 write-back per x item) tripled the step time.  Before the step the
+// grids are dealt to the XCDs in snake order over their sizes, largest
+// first (cells balance to within about one small grid), and each XCD has its
+// own cursor: a workgroup reads its XCD from the hardware register and draws
+// that XCD's items, the x items of its grids before any y item.
+//
+// Ordering within an XCD: after an x item each wave waits until its stores
+// have reached the L2 (vmcnt 0, the release of an agent with one L2), then a
+// barrier and one counter increment for the grid; a y item polls its grid's
+// counter until it holds the grid's x item count, then every thread acquires
+// at device scope (L1 invalidated) before reading.
+//
+// Progress: an item is only handed to a running workgroup, and the x items a
+// y item waits for were handed out before it on the same XCD, so running
+// workgroups hold them and finish them without waiting.  The wait is still
+// bounded (spin_limit polls): a y item that gives up skips its work, sets
+// status bit 0 and writes NaN into its grid's CFL slot.  A workgroup whose
+// XCD index is not below the XCD count takes no item (its XCD has no list);
+// the last workgroup to finish sets status bit 1 if an XCD's items were not
+// all taken (an XCD without workgroups).
+struct StepBatch {
+    void *w;                        // x-swept state: 4 planes (rho, mx, my, E) of w_stride elements
+    long long w_stride;
+    unsigned char *ctl;             // control block, zeroed and dealt by the init kernel
+    int nxcd;                       // XCDs of the device (1..8)
+    int spin_limit;
+    unsigned wait_extra;            // added to the awaited count (0; 1 only to test the give-up path)
+};
+
+// control block (bytes): status, exit count, per-XCD cursors and x / y item
+// totals, per-grid counters (STEP_BATCH_CNT_OFFSET), per-grid XCD
+constexpr int SB_STATUS = 0, SB_EXIT = 4, SB_CURSOR = 64, SB_XTOT = 128, SB_YTOT = 192;
+constexpr int SB_XCD = (int)STEP_BATCH_CNT_OFFSET + 4 * HFAV_MAX_BATCH;
+constexpr int SB_MAX_XCD = 8;
+static_assert(SB_XCD + HFAV_MAX_BATCH <= (int)STEP_BATCH_CTL_BYTES, "step control block");
+
+constexpr int STEP_XROWS = 4;
+
+__device__ __forceinline__ long long step_x_items(const BatchDims &d, int g) {
+    return (long long)((d.ny[g] + STEP_XROWS - 1) / STEP_XROWS) * ((d.nx[g] + BATCH_XSEG - 1) / BATCH_XSEG);
+}
+
+__device__ __forceinline__ long long step_y_items(const BatchDims &d, int g) {
+    return (long long)((d.nx[g] + 63) / 64) * ((d.ny[g] + d.seg[g] - 1) / d.seg[g]);
+}
+
+// advance a cursor over the grids dealt to XCD k
+template <class F>
+__device__ __forceinline__ void advance_on(Cursor &c, long long item, const BatchDims &d, const unsigned char *xcd,
+                                           int k, F count) {
+    while (c.g < d.n && (xcd[c.g] != k || item >= c.base + count(c.g))) {
+        if (xcd[c.g] == k) c.base += count(c.g);
+        c.off += (long long)d.nx[c.g] * d.ny[c.g];
+        ++c.g;
+    }
+}
+
+template <class T, class A, bool G14>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void euler_step_batch_kernel(
+    EArgs<T> a, BatchDims d, StepBatch sb) {
+    using LX = SLds<T, STEP_XROWS, 64>;
+    using LY = SLds<T, 64, 4>;
+    __shared__ __align__(16) unsigned char lds[sizeof(LX) > sizeof(LY) ? sizeof(LX) : sizeof(LY)];
+    __shared__ long long s_item;
+    __shared__ int s_go;
+    LX &SX = *reinterpret_cast<LX *>(lds);
+    LY &SY = *reinterpret_cast<LY *>(lds);
+    unsigned *status = (unsigned *)(sb.ctl + SB_STATUS);
+    unsigned long long *cursor = (unsigned long long *)(sb.ctl + SB_CURSOR);
+    const long long *xtot = (const long long *)(sb.ctl + SB_XTOT), *ytot = (const long long *)(sb.ctl + SB_YTOT);
+    unsigned *cnt = (unsigned *)(sb.ctl + STEP_BATCH_CNT_OFFSET);
+    const unsigned char *xcd = sb.ctl + SB_XCD;
+    // XCC_ID hardware register, bits 3:0
+    const int k = (int)__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20);
+    if (k < sb.nxcd) {
+        EArgs<T> ay = a;
+        ay.bc = a.bcy;
+        T *w = (T *)sb.w;
+        const long long ws = sb.w_stride;
+        const long long nxi = xtot[k], total = nxi + ytot[k];
+        Cursor cx{0, 0, 0}, cy{0, 0, 0};    // the items a workgroup draws increase
+        for (;;) {
+            __syncthreads();                // everyone has read s_item / s_go of the previous item
+            if (threadIdx.x == 0) s_item = (long long)atomicAdd(cursor + k, 1ull);
+            __syncthreads();
+            const long long it = s_item;
+            if (it >= total) break;
+            if (it < nxi) {
+                advance_on(cx, it, d, xcd, k, [&](int g) { return step_x_items(d, g); });
+                const int g = cx.g;
+                const long long o = cx.off;
+                const EView<T> v{a.rho + o, a.mn + o, a.mt + o, a.E + o,
+                                 w + o, w + ws + o, w + 2 * ws + o, w + 3 * ws + o, d.nx[g], d.ny[g]};
+                const int nsg = (v.nx + BATCH_XSEG - 1) / BATCH_XSEG;
+                const int local = (int)(it - cx.base);
+                const int j = (local / nsg) * STEP_XROWS, i0 = (local % nsg) * BATCH_XSEG;
+                const double dt = read_dt(a.dt_src + g, a.dt_mode, a.cfl);
+                strip<T, A, G14, STEP_XROWS, 64>(a, v, true, j, i0, min(i0 + BATCH_XSEG, v.nx), dt, false, SX);
+                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+                __syncthreads();
+                if (threadIdx.x == 0) __hip_atomic_fetch_add(cnt + g, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                advance_on(cy, it - nxi, d, xcd, k, [&](int g) { return step_y_items(d, g); });
+                const int g = cy.g;
+                if (threadIdx.x == 0) {
+                    const unsigned need = (unsigned)step_x_items(d, g) + sb.wait_extra;
+                    int polls = 0;
+                    bool ok = __hip_atomic_load(cnt + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need;
+                    while (!ok && polls < sb.spin_limit) {
+                        __builtin_amdgcn_s_sleep(2);
+                        ++polls;
+                        ok = __hip_atomic_load(cnt + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need;
+                    }
+                    s_go = ok;
+                    if (!ok) {
+                        atomicOr(status, 1u);
+                        if (a.smax_out) atomic_max_nonneg(a.smax_out + g, __longlong_as_double(0x7ff8000000000000ll));
+                    }
+                }
+                __syncthreads();
+                if (!s_go) continue;
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                const long long o = cy.off;
+                // y frame: normal momentum my, tangential mx
+                const EView<T> v{w + o, w + 2 * ws + o, w + ws + o, w + 3 * ws + o,
+                                 a.orho + o, a.omt + o, a.omn + o, a.oE + o, d.nx[g], d.ny[g]};
+                const int ntx = (v.nx + 63) / 64;
+                const int tile = (int)(it - nxi - cy.base);
+                const int i0 = (tile % ntx) * 64, j0 = (tile / ntx) * d.seg[g];
+                const int j1 = min(j0 + (int)d.seg[g], v.ny);
+                const double dt = read_dt(a.dt_src + g, a.dt_mode, a.cfl);
+                const double smax = strip<T, A, G14, 64, 4>(ay, v, false, i0, j0, j1, dt, a.smax_out != nullptr, SY);
+                if (a.smax_out) block_max_to<256>(smax, a.smax_out + g);
+            }
+        }
+    }
+    // the last workgroup to finish: were all items of every XCD taken?
+    if (threadIdx.x == 0 &&
+        __hip_atomic_fetch_add((unsigned *)(sb.ctl + SB_EXIT), 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) ==
+            gridDim.x - 1) {
+        for (int q = 0; q < sb.nxcd; ++q)
+            if (__hip_atomic_load(cursor + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+                (unsigned long long)(xtot[q] + ytot[q]))
+                atomicOr(status, 2u);
+    }
+}
+
+// Before each step: zero the status, exit count, cursors, per-grid counters
+// and CFL slots, and deal the grids to the XCDs (rank by cells, largest
+// first, ties by index; snake order over the ranks) with each XCD's item
+// totals.
+__global__ __launch_bounds__(256) void step_batch_init_kernel(BatchDims d, unsigned char *ctl, int nxcd, double *smax) {
+    __shared__ unsigned long long s_x[SB_MAX_XCD], s_y[SB_MAX_XCD];
+    const int n = d.n, t = threadIdx.x;
+    unsigned *w32 = (unsigned *)ctl;
+    for (int q = t; q < SB_XTOT / 4; q += 256) w32[q] = 0u;                 // status, exit, cursors
+    for (int q = t; q < n; q += 256) w32[STEP_BATCH_CNT_OFFSET / 4 + q] = 0u;
+    if (smax)
+        for (int q = t; q < n; q += 256) smax[q] = 0.0;
+    if (t < SB_MAX_XCD) s_x[t] = s_y[t] = 0ull;
+    __syncthreads();
+    for (int g = t; g < n; g += 256) {
+        const long long cg = (long long)d.nx[g] * d.ny[g];
+        int r = 0;
+        for (int h = 0; h < n; ++h) {
+            const long long ch = (long long)d.nx[h] * d.ny[h];
+            r += ch > cg || (ch == cg && h < g);
+        }
+        const int p = r % (2 * nxcd), k = p < nxcd ? p : 2 * nxcd - 1 - p;
+        ctl[SB_XCD + g] = (unsigned char)k;
+        atomicAdd(&s_x[k], (unsigned long long)step_x_items(d, g));
+        atomicAdd(&s_y[k], (unsigned long long)step_y_items(d, g));
+    }
+    __syncthreads();
+    if (t < SB_MAX_XCD) {
+        ((long long *)(ctl + SB_XTOT))[t] = (long long)s_x[t];
+        ((long long *)(ctl + SB_YTOT))[t] = (long long)s_y[t];
+    }
+}
+
 template <class T, int B>
 __global__ __launch_bounds__(B) void euler_smax_batch_kernel(const T *rho, const T *mx, const T *my, const T *E,
                                                              BatchDims d, double g, double *out) {
@@ -774,6 +964,71 @@ hipError_t launch_euler_batch(const EulerLaunch &L, const EulerBatch &Bt, bool x
     if (L.precision == HFAV_PREC_F32_F64ACC)
         return g14 ? batch_dispatch<float, double, true>(L, Bt, x, s) : batch_dispatch<float, double, false>(L, Bt, x, s);
     return g14 ? batch_dispatch<float, float, true>(L, Bt, x, s) : batch_dispatch<float, float, false>(L, Bt, x, s);
+}
+
+// workspace of the one-launch batch step: the control block, then the
+// x-swept state as 4 planes, each padded to 256 bytes
+static size_t step_batch_plane(long long cells, int dtype) {
+    const size_t es = dtype == HFAV_F64 ? 8 : 4;
+    return ((size_t)cells * es + 255) / 256 * 256;
+}
+
+size_t step_batch_ws_bytes(long long cells, int dtype) {
+    return STEP_BATCH_CTL_BYTES + 4 * step_batch_plane(cells, dtype);
+}
+
+// XCDs of the current device: 32 compute units each on gfx950 (1 to 8)
+static int device_xcds() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    const int x = cus / 32;
+    return x < 1 ? 1 : (x > SB_MAX_XCD ? SB_MAX_XCD : x);
+}
+
+template <class T, class A, bool G14>
+static hipError_t step_batch_dispatch(const EulerLaunch &L, const EulerBatch &Bt, void *ws, int spin_limit,
+                                      unsigned wait_extra, hipStream_t s) {
+    EArgs<T> a = make_args<T>(L);
+    a.bcy = L.bcy;
+    const BatchDims d = make_dims(Bt);
+    StepBatch sb;
+    long long cells = 0;
+    for (int g = 0; g < Bt.n; ++g) {
+        if (Bt.seg[g] < 1) return hipErrorInvalidValue;
+        cells += (long long)Bt.nx[g] * Bt.ny[g];
+    }
+    sb.nxcd = device_xcds();
+    if (sb.nxcd < 1) return hipErrorInvalidDevice;
+    sb.ctl = (unsigned char *)ws;
+    sb.w = (char *)ws + STEP_BATCH_CTL_BYTES;
+    sb.w_stride = (long long)(step_batch_plane(cells, L.dtype) / sizeof(T));
+    sb.spin_limit = spin_limit;
+    sb.wait_extra = wait_extra;
+    hipLaunchKernelGGL(step_batch_init_kernel, dim3(1), dim3(256), 0, s, d, sb.ctl, sb.nxcd, L.smax_out);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // resident pool: 4 four-wave workgroups per CU (4 waves per SIMD),
+    // dealt round robin to the XCDs by the hardware (a workgroup without an
+    // item left on its XCD exits at once); progress does not depend on it
+    const unsigned nwg = (unsigned)(Bt.workgroups > 0 ? Bt.workgroups : 256 * 4);
+    hipLaunchKernelGGL((euler_step_batch_kernel<T, A, G14>), dim3(nwg), dim3(256), 0, s, a, d, sb);
+    return hipGetLastError();
+}
+
+hipError_t launch_euler_step_batch(const EulerLaunch &L, const EulerBatch &Bt, void *ws, int spin_limit,
+                                   unsigned wait_extra, hipStream_t s) {
+    if (Bt.n < 1 || Bt.n > HFAV_MAX_BATCH || !ws || spin_limit < 0) return hipErrorInvalidValue;
+    const bool g14 = L.gamma == 1.4;
+    if (L.dtype == HFAV_F64)
+        return g14 ? step_batch_dispatch<double, double, true>(L, Bt, ws, spin_limit, wait_extra, s)
+                   : step_batch_dispatch<double, double, false>(L, Bt, ws, spin_limit, wait_extra, s);
+    if (L.precision == HFAV_PREC_F32_F64ACC)
+        return g14 ? step_batch_dispatch<float, double, true>(L, Bt, ws, spin_limit, wait_extra, s)
+                   : step_batch_dispatch<float, double, false>(L, Bt, ws, spin_limit, wait_extra, s);
+    return g14 ? step_batch_dispatch<float, float, true>(L, Bt, ws, spin_limit, wait_extra, s)
+               : step_batch_dispatch<float, float, false>(L, Bt, ws, spin_limit, wait_extra, s);
 }
 
 hipError_t launch_euler_smax_batch(const void *const *U, const EulerBatch &Bt, double gamma, double *out, int dtype,

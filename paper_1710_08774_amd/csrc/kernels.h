@@ -57,6 +57,22 @@ hipError_t launch_euler_batch(const EulerLaunch &L, const EulerBatch &B, bool x_
 hipError_t launch_euler_smax_batch(const void *const *U, const EulerBatch &B, double gamma, double *out,
                                    int dtype, hipStream_t s);
 hipError_t launch_fill_batch(double *p, int n, double v, hipStream_t s);
+// Both sweeps of a time step for every grid of a batch in one persistent
+// launch (after a one-workgroup launch that zeroes its control block and
+// the CFL slots and deals the grids to the XCDs).  in/out in the physical
+// frame (rho, mx, my, E), bc along x, bcy along y, B.seg rows per y item.
+// Workspace: the control block (status word at byte 0: bit 0 set when a y
+// item gave up waiting for its grid's x items, bit 1 when an XCD's items
+// were not all taken; per-grid counters from STEP_BATCH_CNT_OFFSET), then
+// the x-swept state.  A y item polls at most spin_limit times; wait_extra
+// (0 in use) is added to the count it awaits.
+constexpr size_t STEP_BATCH_CTL_BYTES = 4096;
+constexpr size_t STEP_BATCH_CNT_OFFSET = 256;
+constexpr int STEP_BATCH_SPIN_LIMIT = 1 << 18;
+constexpr int EULER_STEP_TEST_GIVEUP = 128;     // configuration variant bit
+size_t step_batch_ws_bytes(long long cells, int dtype);
+hipError_t launch_euler_step_batch(const EulerLaunch &L, const EulerBatch &B, void *ws, int spin_limit,
+                                   unsigned wait_extra, hipStream_t s);
 
 // smax = max over cells of max(|u|+c, |v|+c); *out must hold 0 beforehand.
 hipError_t launch_euler_smax(const void *const *U, int n, double gamma, double *out,

@@ -1232,9 +1232,11 @@ extern "C" int hfav_plan_batch(hfav_chain *chain, const hfav_plan_opts *opts, in
     }
     if (rc != HFAV_OK) return rc;
     HPlan &p = chain->plan;
-    if (p.family != HFAV_FAMILY_EULER_X && p.family != HFAV_FAMILY_EULER_Y && p.family != HFAV_FAMILY_SMAX) {
+    if (p.family != HFAV_FAMILY_EULER_X && p.family != HFAV_FAMILY_EULER_Y && p.family != HFAV_FAMILY_SMAX &&
+        p.family != HFAV_FAMILY_EULER_XY) {
         p.valid = false;
-        return hfav_fail(HFAV_EUNSUP, "batches are implemented for the Euler sweeps and their CFL reduction");
+        return hfav_fail(HFAV_EUNSUP, "batches are implemented for the Euler sweeps, the time step of both "
+                                      "sweeps and the CFL reduction");
     }
     p.batch = true;
     p.bnx.resize(n_grids);
@@ -1259,12 +1261,22 @@ extern "C" int hfav_plan_batch(hfav_chain *chain, const hfav_plan_opts *opts, in
         p.bseg[g] = seg > 255 ? 255 : seg;
     }
     p.btotal = off;
+    // the time step of both sweeps runs as one persistent launch whose y
+    // items read the x-swept state from the workspace
+    const bool step = p.family == HFAV_FAMILY_EULER_XY;
+    if (step) {
+        p.ws_bytes = hfav::step_batch_ws_bytes(p.btotal, chain->dtype);
+        p.info.workspace_bytes = p.ws_bytes;
+        if (info) info->workspace_bytes = p.ws_bytes;
+    }
     // record the batch in the plan's JSON: grid count and y segment lengths
     if (!p.json.empty() && p.json.back() == '}') {
         std::ostringstream bj;
         bj << ",\"batch\":{\"grids\":" << n_grids << ",\"y_seg\":[";
         for (int g = 0; g < n_grids; ++g) bj << (g ? "," : "") << (int)p.bseg[g];
-        bj << "]}";
+        bj << "]";
+        if (step) bj << ",\"one_launch_step\":1,\"workspace_bytes\":" << p.ws_bytes;
+        bj << "}";
         p.json.insert(p.json.size() - 1, bj.str());
     }
     return HFAV_OK;

@@ -108,11 +108,16 @@ class EulerBatchStepper:
     """Many independent grids advanced together by the persistent batched
     sweeps.  Fields are packed: plane q of grid g is U[q, off_g : off_g +
     nx_g*ny_g] (row-major (ny_g, nx_g)).  Each grid has its own dt and CFL
-    slot.  `capture(steps)` records `steps` (even) steps into a HIP graph."""
+    slot.  `capture(steps)` records `steps` (even) steps into a HIP graph.
+
+    fused_step=True runs each step as ONE chain (both sweeps) planned for
+    the batch: one persistent launch per step whose y items wait for their
+    grid's x items, the x-swept state in the workspace; otherwise one
+    persistent launch per sweep."""
 
     def __init__(self, sizes, dtype=torch.float64, gamma=1.4, cfl=0.5, niter=10, bc=H.BC_PERIODIC,
                  precision=H.PREC_NATIVE, config_source=H.CONFIG_DEFAULT, forced_y=None, device="cuda",
-                 forced_x=None):
+                 forced_x=None, fused_step=False, forced_xy=None):
         self.sizes = [(int(a), int(b)) for a, b in sizes]
         self.dtype = dtype
         cd = H.F64 if dtype == torch.float64 else H.F32
@@ -129,10 +134,19 @@ class EulerBatchStepper:
         src_y = H.CONFIG_FORCED if forced_y is not None else config_source
         self.iy = self.cy.plan_batch(self.sizes, (bc, bc), precision=precision, config_source=src_y,
                                      forced=forced_y)
+        self.cxy = self.ixy = None
+        if fused_step:
+            self.cxy = H.Chain(H.euler_step_spec(gamma, niter, cfl, "smax", True, cd))
+            src = H.CONFIG_FORCED if forced_xy is not None else config_source
+            self.ixy = self.cxy.plan_batch(self.sizes, (bc, bc), precision=precision, config_source=src,
+                                           forced=forced_xy)
         self.off = [self.cx.batch_offset(g) for g in range(self.n)]
         self.total = self.off[-1] + self.sizes[-1][0] * self.sizes[-1][1]
         self.U = [torch.empty((4, self.total), dtype=dtype, device=device) for _ in range(2)]
         self.smax = torch.zeros((2, self.n), dtype=torch.float64, device=device)
+        ws = self.ixy.workspace_bytes if self.ixy is not None else 0
+        self.ws = torch.empty(ws, dtype=torch.uint8, device=device) if ws else None
+        self.cur = 0
         self.slot = 0
         self.graph = None
 
@@ -149,16 +163,30 @@ class EulerBatchStepper:
             nx, ny = self.sizes[g]
             host[:, self.off[g]:self.off[g] + nx * ny] = torch.as_tensor(U, dtype=self.dtype).reshape(4, -1)
         self.U[0].copy_(host)
+        self.cur = 0
         self.slot = 0
         self.smax_chain.execute(list(self.U[0]), [self.smax[0]])
 
     def step(self, n=1):
-        a, b = self.U
         for _ in range(n):
+            a, b = self.U[self.cur], self.U[1 - self.cur]
             s0, s1 = self.smax[self.slot], self.smax[1 - self.slot]
-            self.cx.execute([a[0], a[1], a[2], a[3], s0], [b[0], b[1], b[2], b[3]])
-            self.cy.execute([b[0], b[1], b[2], b[3], s0], [a[0], a[1], a[2], a[3], s1])
+            if self.cxy is not None:
+                self.cxy.execute([a[0], a[1], a[2], a[3], s0], [b[0], b[1], b[2], b[3], s1], self.ws)
+                self.cur = 1 - self.cur
+            else:
+                self.cx.execute([a[0], a[1], a[2], a[3], s0], [b[0], b[1], b[2], b[3]])
+                self.cy.execute([b[0], b[1], b[2], b[3], s0], [a[0], a[1], a[2], a[3], s1])
             self.slot = 1 - self.slot
+
+    def step_status(self):
+        """Status word of the last one-launch step (synchronises): 0, or bit
+        0 set when a y item gave up waiting for its grid's x items (its
+        cells are then not updated and its grid's CFL slot holds NaN)."""
+        if self.ws is None:
+            return 0
+        torch.cuda.synchronize()
+        return int(self.ws[:4].cpu().view(torch.int32)[0])
 
     def capture(self, steps):
         """Record `steps` steps (an even number, so the dt slots line up on
@@ -167,10 +195,10 @@ class EulerBatchStepper:
         torch.cuda.synchronize()
         g = torch.cuda.CUDAGraph()
         side = torch.cuda.Stream()
-        slot0 = self.slot
+        slot0, cur0 = self.slot, self.cur
         with torch.cuda.graph(g, stream=side):
             self.step(steps)
-        self.slot = slot0
+        self.slot, self.cur = slot0, cur0
         self.graph = g
         return g
 
@@ -179,4 +207,4 @@ class EulerBatchStepper:
 
     def grid(self, g):
         nx, ny = self.sizes[g]
-        return self.U[0][:, self.off[g]:self.off[g] + nx * ny].reshape(4, ny, nx)
+        return self.U[self.cur][:, self.off[g]:self.off[g] + nx * ny].reshape(4, ny, nx)

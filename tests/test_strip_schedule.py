@@ -72,8 +72,9 @@ def races(acc):
 
 
 # the kernels' shapes: y strips of 64 lines x 2, 4 or 8 rows; x strips of
-# one line x 64, 128 or 256 cells
-SHAPES = [(2, 64), (4, 64), (8, 64), (64, 1), (128, 1), (256, 1)]
+# one line x 64, 128 or 256 cells, and of 4 lines x 64 cells (the x items of
+# the one-launch batch step: a wave holds 16 cells of each of the 4 lines)
+SHAPES = [(2, 64), (4, 64), (8, 64), (64, 1), (128, 1), (256, 1), (64, 4)]
 
 
 @pytest.mark.parametrize("C,W", SHAPES)
