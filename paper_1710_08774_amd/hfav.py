@@ -245,6 +245,35 @@ def _ptr(x):
     return x.data_ptr()
 
 
+class BoundExecute:
+    """hfav_execute with buffers checked once (Chain.bind)."""
+
+    def __init__(self, chain, axioms, goals, workspace):
+        self._chain = chain
+        self._gen = chain._plan_gen
+        self._keep = (list(axioms), list(goals), workspace)
+        self._ax = (C.c_void_p * len(axioms))(*[_ptr(a) for a in axioms])
+        self._go = (C.c_void_p * len(goals))(*[_ptr(g) for g in goals])
+        self._ws = _ptr(workspace)
+        self._fn = lib().hfav_execute
+
+    def stale(self):
+        """True once the chain has been planned again."""
+        return self._chain._plan_gen != self._gen
+
+    def __call__(self, stream=None):
+        if self._chain._plan_gen != self._gen:
+            raise HfavError(ENOPLAN, "the chain was planned again after bind()")
+        if stream is None:
+            import torch
+            s = torch.cuda.current_stream().cuda_stream
+        else:
+            s = stream if isinstance(stream, int) else stream.cuda_stream
+        rc = self._fn(self._chain._h, self._ax, self._go, self._ws, s)
+        if rc != OK:
+            raise HfavError(rc, last_error())
+
+
 class Chain:
     """A created chain handle (hfav_chain_create) with plan and execute."""
 
@@ -257,6 +286,7 @@ class Chain:
         _check(create(C.byref(d), C.byref(h)))
         self._h = h
         self.info = None
+        self._plan_gen = 0          # bumped by every (re)plan: bound executes check it
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -266,6 +296,7 @@ class Chain:
 
     def alias(self, goal: str, axiom: str):
         """Declare an in-place pair: `goal` is written over `axiom`."""
+        self._plan_gen += 1
         _check(lib().hfav_chain_alias(self._h, goal.encode(), axiom.encode()))
 
     def plan(self, dims, boundary=(BC_PERIODIC,) * 3, mode=MODE_AUTO, precision=PREC_NATIVE,
@@ -275,6 +306,7 @@ class Chain:
         f = hfav_config(*(tuple(forced) + (0,) * (5 - len(forced)) if forced is not None else (0,) * 5))
         o = hfav_plan_opts((C.c_int * 3)(*dims), (C.c_int * 3)(*bnd), mode, precision, config_source, f)
         info = hfav_plan_info()
+        self._plan_gen += 1
         _check(lib().hfav_plan(self._h, C.byref(o), C.byref(info)))
         self.info = info
         self.dims = dims
@@ -289,6 +321,7 @@ class Chain:
         f = hfav_config(*(tuple(forced) + (0,) * (5 - len(forced)) if forced is not None else (0,) * 5))
         o = hfav_plan_opts((C.c_int * 3)(1, 1, 1), (C.c_int * 3)(*bnd), MODE_FUSED, precision, config_source, f)
         info = hfav_plan_info()
+        self._plan_gen += 1
         _check(lib().hfav_plan_batch(self._h, C.byref(o), len(sizes), flat, C.byref(info)))
         self.info = info
         self.sizes = list(sizes)
@@ -351,6 +384,14 @@ class Chain:
         else:
             s = stream.cuda_stream
         _check(lib().hfav_execute(self._h, ax, go, _ptr(workspace), s))
+
+    def bind(self, axioms, goals, workspace=None):
+        """Validate the buffers once and return a callable that enqueues this
+        execute with them (`call(stream=None)`): the per-call host work of a
+        time-stepping loop is then one C call.  The binding holds the
+        tensors; it refuses to run after the chain is planned again."""
+        self._validate(axioms, goals, workspace)
+        return BoundExecute(self, axioms, goals, workspace)
 
     def execute_noalloc(self, axioms, goals, stream=None):
         """hfav_execute_noalloc: the workspace is the library's static device

@@ -48,3 +48,20 @@ def test_noalloc_refuses_before_touching_a_device():
     assert info.workspace_bytes > H.STATIC_WORKSPACE_BYTES
     assert c.execute_noalloc_status([1], [2]) == H.ESIZE
     assert "static workspace" in H.last_error()
+
+
+def test_bound_execute_refuses_after_a_replan():
+    """Chain.bind checks the buffers once; after the chain is planned again
+    the binding is stale and refuses before any device call."""
+    c = H.Chain(H.hdiff_spec())
+    c.plan((64, 32, 2))
+    b = c.bind([0x100000], [0x900000])
+    assert not b.stale()
+    c.plan((64, 32, 4))
+    assert b.stale()
+    try:
+        b(stream=0)
+    except H.HfavError as e:
+        assert e.code == H.ENOPLAN
+    else:
+        raise AssertionError("a stale binding ran")
