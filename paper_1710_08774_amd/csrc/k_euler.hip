@@ -704,6 +704,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void e
 // totals.
 __global__ __launch_bounds__(256) void step_batch_init_kernel(BatchDims d, unsigned char *ctl, int nxcd, double *smax) {
     __shared__ unsigned long long s_x[SB_MAX_XCD], s_y[SB_MAX_XCD];
+    __shared__ long long s_cells[HFAV_MAX_BATCH];
     const int n = d.n, t = threadIdx.x;
     unsigned *w32 = (unsigned *)ctl;
     for (int q = t; q < SB_XTOT / 4; q += 256) w32[q] = 0u;                 // status, exit, cursors
@@ -711,12 +712,15 @@ __global__ __launch_bounds__(256) void step_batch_init_kernel(BatchDims d, unsig
     if (smax)
         for (int q = t; q < n; q += 256) smax[q] = 0.0;
     if (t < SB_MAX_XCD) s_x[t] = s_y[t] = 0ull;
+    // the cells of every grid in LDS: the rank loop below reads them all
+    for (int g = t; g < n; g += 256) s_cells[g] = (long long)d.nx[g] * d.ny[g];
     __syncthreads();
     for (int g = t; g < n; g += 256) {
-        const long long cg = (long long)d.nx[g] * d.ny[g];
+        const long long cg = s_cells[g];
         int r = 0;
+#pragma unroll 8
         for (int h = 0; h < n; ++h) {
-            const long long ch = (long long)d.nx[h] * d.ny[h];
+            const long long ch = s_cells[h];
             r += ch > cg || (ch == cg && h < g);
         }
         const int p = r % (2 * nxcd), k = p < nxcd ? p : 2 * nxcd - 1 - p;
