@@ -56,16 +56,16 @@ hfav_config hfav_default_config(int family, int dtype, const int dims[3]) {
     }
     case HFAV_FAMILY_EULER_Y: {
         // LDS-ring strips of 64 columns x 4 rows per chunk (4-wave
-        // workgroups reach 5 waves per SIMD, 8-wave ones only 4).  A segment
-        // of seg rows walks seg + 1 chunk rows, so seg = 4k - 1 leaves no
-        // chunk row idle; 15-row segments while they still give about
-        // three rounds of 1280 resident workgroups, else 7, else 3 (2048^2
-        // FP64: 0.183 ms against 0.192 with 8 x 127; 512^2: 0.025 ms
-        // against 0.035)
+        // workgroups; 2- and 8-wave ones measured slower).  A segment of seg
+        // rows walks seg + 1 chunk rows, so seg = 4k - 1 leaves no chunk row
+        // idle; the longest of 19 and 15 rows that still gives three rounds
+        // of the 1024 resident workgroups (4 per CU), else 7, else 3 (2048^2
+        // FP64: 19 rows 0.147-0.149 ms, 15 rows 0.150-0.153, 23 rows 0.151,
+        // 31 rows 0.153-0.156; 512^2: 7 rows 0.025 ms against 0.035 with 15)
         const double cols = (dims[0] + 63) / 64;
         auto wgs = [&](int seg) { return cols * ((dims[1] + seg - 1) / seg); };
         c.block = 256;
-        c.seg = wgs(15) >= 3840 ? 15 : wgs(7) >= 512 ? 7 : 3;
+        c.seg = wgs(19) >= 3072 ? 19 : wgs(15) >= 3072 ? 15 : wgs(7) >= 512 ? 7 : 3;
         c.variant = 3;
         break;
     }

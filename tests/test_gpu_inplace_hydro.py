@@ -59,8 +59,9 @@ def test_in_place_footprint_halves_the_state():
     state = 4 * nx * ny * 8
     assert a.footprint_bytes() == 2 * state
     # one state plus the saved segment halos: 4 cells x 4 fields per line
-    # and boundary (y: ceil(2048 / 15) = 137 boundaries of 2048 columns)
+    # and boundary (y: ceil(2048 / seg) boundaries of 2048 columns)
     ws = max(b.ix.workspace_bytes, b.iy.workspace_bytes)
     assert b.footprint_bytes() == state + ws
-    assert ws == 4 * 137 * 4 * 2048 * 8
+    nsg = -(-ny // b.iy.config.seg)
+    assert ws == 4 * nsg * 4 * nx * 8
     assert b.footprint_bytes() < 0.65 * a.footprint_bytes()

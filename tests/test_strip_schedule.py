@@ -78,7 +78,7 @@ SHAPES = [(2, 64), (4, 64), (8, 64), (64, 1), (128, 1), (256, 1), (64, 4)]
 
 
 @pytest.mark.parametrize("C,W", SHAPES)
-@pytest.mark.parametrize("seg", [1, 3, 7, 15, 16, 63, 127, 191, 255])
+@pytest.mark.parametrize("seg", [1, 3, 7, 15, 16, 19, 63, 127, 191, 255])
 def test_strip_schedule_has_no_lds_race(C, W, seg):
     assert races(schedule(C, W, 10, 10 + seg)) == []
 
