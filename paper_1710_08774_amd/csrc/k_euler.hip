@@ -272,6 +272,9 @@ struct SLds {
     // plus-face state of cell p, replaced (once its reader has it) by the
     // flux F(p+1/2): one ring serves both windows
     T fF[4][RF][W];
+    // conserved state as loaded, for the update two cells behind (another
+    // lane's load: through LDS instead of a second read through the caches)
+    T u[4][RW][W];
 };
 
 // index along the sweep with the boundary applied (division only off the grid)
@@ -343,6 +346,10 @@ __device__ __forceinline__ double strip(const EArgs<T> &a, const EView<T> &v, bo
         T u0[4];
         load_u(j0 - 2 + k, u0);
         put(fs(j0 - 2 + k), euler_prim(u0[0], u0[1], u0[2], u0[3], g));
+        if (k == 2) {
+#pragma unroll
+            for (int f = 0; f < 4; ++f) S.u[f][fs(j0)][wl] = u0[f];
+        }
     }
     __syncthreads();
     if (lact && q == 0) {
@@ -371,7 +378,12 @@ __device__ __forceinline__ double strip(const EArgs<T> &a, const EView<T> &v, bo
         // passed since (the prologue's reads: the barrier before the loop)
         T un[4];
         if (act) load_u(p + 1, un);
-        if (act) put(sl(1), euler_prim(un[0], un[1], un[2], un[3], g));
+        if (act) {
+            const int s1 = sl(1);
+            put(s1, euler_prim(un[0], un[1], un[2], un[3], g));
+#pragma unroll
+            for (int f = 0; f < 4; ++f) S.u[f][s1][wl] = un[f];
+        }
         __syncthreads();
         // stage 2: slopes and trace of cell p; the plus face goes to the
         // lane of cell p+1 through LDS, the minus face stays in registers
@@ -403,14 +415,16 @@ __device__ __forceinline__ double strip(const EArgs<T> &a, const EView<T> &v, bo
         }
         __syncthreads();
         // stage 4: conservative update of cell p-1 (inside the grid: no wrap)
-        // from F(p-1/2) (slot of p-1) and F(p-3/2) (slot of p-2)
+        // from F(p-1/2) (slot of p-1) and F(p-3/2) (slot of p-2); the state
+        // of p-1 from its slot of the conserved-state ring, which the next
+        // chunk's stage 1 of this same lane is the first to overwrite
         if (act && p > j0) {
             const size_t o = lb + (size_t)(p - 1) * sa;
             const int s1 = sl(-1), s2 = sl(-2);
-            const T r = euler_update(v.rho[o], S.fF[0][s1][wl], S.fF[0][s2][wl], nuA);
-            const T mn = euler_update(v.mn[o], S.fF[1][s1][wl], S.fF[1][s2][wl], nuA);
-            const T mt = euler_update(v.mt[o], S.fF[2][s1][wl], S.fF[2][s2][wl], nuA);
-            const T e = euler_update(v.E[o], S.fF[3][s1][wl], S.fF[3][s2][wl], nuA);
+            const T r = euler_update(S.u[0][s1][wl], S.fF[0][s1][wl], S.fF[0][s2][wl], nuA);
+            const T mn = euler_update(S.u[1][s1][wl], S.fF[1][s1][wl], S.fF[1][s2][wl], nuA);
+            const T mt = euler_update(S.u[2][s1][wl], S.fF[2][s1][wl], S.fF[2][s2][wl], nuA);
+            const T e = euler_update(S.u[3][s1][wl], S.fF[3][s1][wl], S.fF[3][s2][wl], nuA);
             v.orho[o] = r; v.omn[o] = mn; v.omt[o] = mt; v.oE[o] = e;
             if (want_smax) smax = fmax(smax, (double)euler_speed(r, mt, mn, e, g));
         }

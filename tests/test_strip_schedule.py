@@ -6,12 +6,14 @@ rings hold C + 2 cells (slot = (cell - j0 + 2) mod (C + 2)); lane group q
 of a chunk at c0 owns the cell p = c0 + q of its W lines, and q runs on
 wave q W / 64 (W = 64 lines: one wave per q; W = 1: 64 values of q per
 wave, in program order).  The model follows the kernel's
-stages: prologue (three primitive states, then the first plus face by
-wave 0), then per chunk: (1) the primitive state of p + 1, (2) slopes and
+stages: prologue (three primitive states and the conserved state of j0,
+then the first plus face by wave 0), then per chunk: (1) the primitive and
+conserved state of p + 1, (2) slopes and
 trace of p from p - 1, p, p + 1 and its plus face, (3) the left state
 (plus face of p - 1) and then, with no barrier between, the flux at
 p - 1/2 into that slot, (4) the update of p - 1 from the fluxes in the
-slots of p - 1 and p - 2."""
+slots of p - 1 and p - 2 and the conserved state of p - 1 from its slot
+of the conserved-state ring (a third ring of C + 2 slots)."""
 import itertools
 
 import pytest
@@ -30,6 +32,8 @@ def schedule(C, W, j0, j1, prologue_barrier=True):
 
     for k in range(3):                     # prologue: cells j0-2 .. j0
         acc.append((ep, wave(k % C), "w", slot(j0 - 2 + k), True))
+        if k == 2:                         # the conserved state of cell j0
+            acc.append((ep, wave(k % C), "u", slot(j0), True))
     barrier()
     for c in (j0 - 2, j0 - 1, j0):
         acc.append((ep, 0, "w", slot(c), False))
@@ -40,6 +44,7 @@ def schedule(C, W, j0, j1, prologue_barrier=True):
         waves = [(q, c0 + q) for q in range(C) if c0 + q <= j1]
         for q, p in waves:
             acc.append((ep, wave(q), "w", slot(p + 1), True))
+            acc.append((ep, wave(q), "u", slot(p + 1), True))
         barrier()
         for q, p in waves:
             for c in (p - 1, p, p + 1):
@@ -55,6 +60,7 @@ def schedule(C, W, j0, j1, prologue_barrier=True):
             if p > j0:
                 acc.append((ep, wave(q), "f", slot(p - 1), False))
                 acc.append((ep, wave(q), "f", slot(p - 2), False))
+                acc.append((ep, wave(q), "u", slot(p - 1), False))
         # no barrier before the next chunk's stage 1
     return acc
 
