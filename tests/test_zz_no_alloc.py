@@ -127,6 +127,39 @@ def test_unfused_hydro_sweep_two_sizes():
         assert np.array_equal(got, host(o_ws))
 
 
+def test_batch_step_two_batches():
+    """The one-launch batch step: its control block (cursors, per-grid
+    counters, the deal of grids to XCDs) and the x-swept state live in the
+    static array; the step's own first launch zeroes what must start at
+    zero, so the second call does not see the first one's counters."""
+    for sizes in ([(64, 64), (100, 37), (1, 1), (300, 5), (191, 4)], [(40, 30), (7, 9)]):
+        print("noalloc batch step", sizes, flush=True)
+        states = inputs.batch_ic(sizes=sizes, seed=len(sizes))
+        c = H.Chain(H.euler_step_spec(with_smax=True))
+        info = c.plan_batch(sizes)
+        assert 0 < info.workspace_bytes <= H.STATIC_WORKSPACE_BYTES
+        off = [c.batch_offset(g) for g in range(len(sizes))]
+        packed = np.zeros((4, off[-1] + sizes[-1][0] * sizes[-1][1]))
+        for g, ((nx, ny), U) in enumerate(zip(sizes, states)):
+            packed[:, off[g]:off[g] + nx * ny] = np.asarray(U).reshape(4, -1)
+        u = dev(packed)
+        sm = H.Chain(H.smax_spec())
+        sm.plan_batch(sizes)
+        smax0 = torch.zeros(len(sizes), dtype=torch.float64, device="cuda")
+        sm.execute(list(u), [smax0])
+        o_ws, o_na = torch.full_like(u, np.nan), torch.full_like(u, np.nan)
+        s_ws, s_na = torch.full_like(smax0, np.nan), torch.full_like(smax0, np.nan)
+        ws = _ws(info)
+        c.execute(list(u) + [smax0], list(o_ws) + [s_ws], ws)
+        c.execute_noalloc(list(u) + [smax0], list(o_na) + [s_na])
+        torch.cuda.synchronize()
+        assert int(ws[:4].cpu().view(torch.int32)[0]) == 0
+        got = host(o_na)
+        assert np.isfinite(got).all()
+        assert np.array_equal(got, host(o_ws))
+        assert torch.equal(s_na, s_ws)
+
+
 def test_oversized_plan_is_refused_and_enqueues_nothing():
     nk, nj, ni = 12, 512, 512
     c = H.Chain(H.hdiff_spec())
