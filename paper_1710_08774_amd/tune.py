@@ -267,6 +267,7 @@ def build_db(buckets=None, reps=5, log=None, batch=None):
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_DB = os.path.join(HERE, "tuning_db.json")            # MI355X autotuner results
+REPORT_DIR = os.environ.get("HFAV_REPORT_DIR", "reports")    # where new tables and studies are written
 DEFAULT_COSTMODEL = os.path.join(HERE, "costmodel_mi355x.json")  # MI355X-trained network
 
 
@@ -505,7 +506,7 @@ def main(argv=None):
     sub = ap.add_subparsers(dest="cmd", required=True)
     dbp = sub.add_parser("db", help="autotune the kernel families and write the tuning database")
     dbp.add_argument("--reps", type=int, default=5)
-    dbp.add_argument("--out", default="gpurun_out/tuning_db.json")
+    dbp.add_argument("--out", default=os.path.join(REPORT_DIR, "tuning_db.json"))
     dbp.add_argument("--families", nargs="*", default=None,
                      help="tune only these families (default: all, plus the batch segments)")
     dbp.add_argument("--merge", default=None,
@@ -516,7 +517,7 @@ def main(argv=None):
     st.add_argument("--reps", type=int, default=3)
     st.add_argument("--iters", type=int, default=3000)
     st.add_argument("--max-cells", type=int, default=0, help="cap grid cells per chain (0: none)")
-    st.add_argument("--out", default="gpurun_out/costmodel_study.json")
+    st.add_argument("--out", default=os.path.join(REPORT_DIR, "costmodel_study.json"))
     a = ap.parse_args(argv)
     if a.cmd == "db":
         buckets, batch = None, None

@@ -10,7 +10,7 @@ configurations bench.py times (the planner defaults).
   one kernel, 2 steps, within 1e-12;
 * the 512-grid batch: every grid after 2 steps, and 16 seeded grids after
   50 steps, against the oracle.
-The per-field reports go to gpurun_out/precision_*.json.
+The per-field reports go to $HFAV_REPORT_DIR (default reports/)/precision_*.json.
 """
 import json
 import os
@@ -30,8 +30,9 @@ U32 = 2.0 ** -24
 
 
 def _report(name, data):
-    os.makedirs("gpurun_out", exist_ok=True)
-    with open(os.path.join("gpurun_out", f"precision_{name}.json"), "w") as f:
+    out = os.environ.get("HFAV_REPORT_DIR", "reports")
+    os.makedirs(out, exist_ok=True)
+    with open(os.path.join(out, f"precision_{name}.json"), "w") as f:
         json.dump(data, f, indent=1)
     print(name, json.dumps(data), flush=True)
 

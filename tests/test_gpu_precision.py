@@ -11,7 +11,8 @@ component (rho, rho u, rho v, E) is bounded by 8 n u, a bound stated from
 measurement: the largest max-norm errors sit in the cells of the
 discontinuities, where a rounding moves a wave by a fraction of a cell, and
 the largest measured value (rho v at 2048^2 after 100 steps, 2.1e-5) is 2.3
-times below it.  Both are reported in the JSON report in gpurun_out/."""
+times below it.  Both are reported in the JSON report in $HFAV_REPORT_DIR (default
+reports/)."""
 import json
 import math
 import os
@@ -41,8 +42,9 @@ def maxnorm_bound(steps):
 
 
 def _report(name, data):
-    os.makedirs("gpurun_out", exist_ok=True)
-    with open(os.path.join("gpurun_out", f"precision_{name}.json"), "w") as f:
+    out = os.environ.get("HFAV_REPORT_DIR", "reports")
+    os.makedirs(out, exist_ok=True)
+    with open(os.path.join(out, f"precision_{name}.json"), "w") as f:
         json.dump(data, f, indent=1)
     print(name, json.dumps(data), flush=True)
 
