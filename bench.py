@@ -140,8 +140,9 @@ def run_gpu(mode, steps, warmup, U0, timing=True, dtype=None, in_place=False):
     # kernel names of the fused sweeps (variant 3 selects the strip kernels)
     out["x_kernel"] = "euler_x_strip_kernel" if st.ix.config.variant == 3 else "euler_x_kernel"
     out["y_kernel"] = "euler_y_strip_kernel" if st.iy.config.variant == 3 else "euler_y_kernel"
-    out["x_config"] = [st.ix.config.block, st.ix.config.seg, st.ix.config.variant]
-    out["y_config"] = [st.iy.config.block, st.iy.config.seg, st.iy.config.variant]
+    # (block, tile_y, seg, variant): tile_y is the y strip's columns per workgroup
+    out["x_config"] = [st.ix.config.block, st.ix.config.tile_y, st.ix.config.seg, st.ix.config.variant]
+    out["y_config"] = [st.iy.config.block, st.iy.config.tile_y, st.iy.config.seg, st.iy.config.variant]
     out["footprint_bytes"] = st.footprint_bytes()
     return out
 

@@ -223,13 +223,15 @@ typedef struct hfav_chain hfav_chain;   /* opaque */
 typedef struct {
     int block;      /* threads per workgroup (64, 128, 256, 512, 1024) */
     int tile_y;     /* family-specific second tile parameter (prefetch depth
-                       of the 7-point chain), or 1 */
+                       of the 7-point chain; columns per workgroup of the y
+                       strip kernel, 8, 16, 32 or 64), or 1 */
     int seg;        /* cells streamed per thread along the streamed axis */
     int variant;    /* family-specific kernel variant, 0 = default.
                        EULER_X / EULER_Y: 0 register budget free, 1 at least
                        4 waves per SIMD, 2 at least 5, 3 LDS-ring strip
-                       kernel (y: block = 64 columns x 2, 4 or 8 rows,
-                       segments of seg rows; x: one row, block = 64, 128
+                       kernel (y: tile_y columns (1: 64) x block / tile_y
+                       rows per chunk, 64 x 2, 4 or 8 or 32 x 8, 16 x 16,
+                       8 x 32; segments of seg rows; x: one row, block = 64, 128
                        or 256 cells per chunk, segments of seg cells, 0 =
                        whole rows; a segment of seg cells walks seg + 1
                        chunk positions); + 64 every Newton step of the

@@ -445,18 +445,22 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(4))) void eul
                                read_dt(a.dt_src, a.dt_mode, a.cfl), false, S);
 }
 
-// y pass as strips: 64 columns x C rows per chunk, segments of a.seg rows
-template <class T, class A, bool G14, int C, bool IP = false>
-__global__ __launch_bounds__(64 * C) __attribute__((amdgpu_waves_per_eu(4))) void euler_y_strip_kernel(EArgs<T> a) {
-    __shared__ SLds<T, 64, C> S;
-    const int ntx = (a.nx + 63) / 64, nsg = (a.ny + a.seg - 1) / a.seg;
+// y pass as strips: W columns x C rows per chunk (W * C lanes), segments of
+// a.seg rows.  A wave holds 64 / W rows of W columns: narrower tiles make
+// each wave's cells a more compact patch and a chunk cover more rows (fewer
+// barriers per cell); every row piece a wave reads stays W * 8 >= 128 bytes
+// for FP64.
+template <class T, class A, bool G14, int W, int C, bool IP = false>
+__global__ __launch_bounds__(W * C) __attribute__((amdgpu_waves_per_eu(4))) void euler_y_strip_kernel(EArgs<T> a) {
+    __shared__ SLds<T, W, C> S;
+    const int ntx = (a.nx + W - 1) / W, nsg = (a.ny + a.seg - 1) / a.seg;
     const int tile = xcd_tile(blockIdx.x, ntx * nsg, a.xcd);
-    const int i0 = (tile % ntx) * 64;
+    const int i0 = (tile % ntx) * W;
     const int j0 = (tile / ntx) * a.seg;
     const int j1 = min(j0 + a.seg, a.ny);
-    const double smax = strip<T, A, G14, 64, C, IP>(a, full_view(a), false, i0, j0, j1,
-                                                    read_dt(a.dt_src, a.dt_mode, a.cfl), a.smax_out != nullptr, S);
-    if (a.smax_out) block_max_to<64 * C>(smax, a.smax_out);
+    const double smax = strip<T, A, G14, W, C, IP>(a, full_view(a), false, i0, j0, j1,
+                                                   read_dt(a.dt_src, a.dt_mode, a.cfl), a.smax_out != nullptr, S);
+    if (a.smax_out) block_max_to<W * C>(smax, a.smax_out);
 }
 
 // Saves the state of the cells b-2 .. b+1 around every segment boundary
@@ -798,6 +802,14 @@ static EArgs<T> make_args(const EulerLaunch &L) {
     return a;
 }
 
+int euler_y_strip_cols(const hfav_config &cfg) { return cfg.tile_y > 1 ? cfg.tile_y : 64; }
+
+bool euler_y_strip_ok(const hfav_config &cfg) {
+    const int w = euler_y_strip_cols(cfg);
+    if (w == 64) return cfg.block == 128 || cfg.block == 256 || cfg.block == 512;
+    return (w == 32 || w == 16 || w == 8) && cfg.block == 256;
+}
+
 int euler_strip_seg(int n, int dir, const hfav_config &cfg) {
     if (dir == 0) return cfg.seg > 0 && cfg.seg < n ? cfg.seg : n;
     return cfg.seg > 0 ? cfg.seg : 16;
@@ -867,19 +879,26 @@ template <class T, class A, bool G14>
 static hipError_t euler_y_dispatch(const EulerLaunch &L, hipStream_t s) {
     EArgs<T> a = make_args<T>(L);
     if ((L.cfg.variant & ~EULER_NEWTON_ALL) == 3) {
-        // 64 columns per workgroup, block / 64 rows per chunk
-        dim3 grid(((L.nx + 63) / 64) * ((L.ny + a.seg - 1) / a.seg));
+        // W = tile_y columns per workgroup (64 when tile_y <= 1), block / W
+        // rows per chunk
+        const int W = euler_y_strip_cols(L.cfg);
+        if (!euler_y_strip_ok(L.cfg)) return hipErrorInvalidValue;
+        dim3 grid(((L.nx + W - 1) / W) * ((L.ny + a.seg - 1) / a.seg));
         if (L.halo) {
             if (L.cfg.block != 256) return hipErrorInvalidValue;
             const hipError_t e = save_halos(a, false, s);
             if (e != hipSuccess) return e;
-            hipLaunchKernelGGL((euler_y_strip_kernel<T, A, G14, 4, true>), grid, dim3(256), 0, s, a);
+            if (W == 16) hipLaunchKernelGGL((euler_y_strip_kernel<T, A, G14, 16, 16, true>), grid, dim3(256), 0, s, a);
+            else hipLaunchKernelGGL((euler_y_strip_kernel<T, A, G14, 64, 4, true>), grid, dim3(256), 0, s, a);
             return hipGetLastError();
         }
-        switch (L.cfg.block) {
-        case 128: hipLaunchKernelGGL((euler_y_strip_kernel<T, A, G14, 2>), grid, dim3(128), 0, s, a); break;
-        case 512: hipLaunchKernelGGL((euler_y_strip_kernel<T, A, G14, 8>), grid, dim3(512), 0, s, a); break;
-        default: hipLaunchKernelGGL((euler_y_strip_kernel<T, A, G14, 4>), grid, dim3(256), 0, s, a); break;
+        switch (W * 1024 + L.cfg.block) {
+        case 64 * 1024 + 128: hipLaunchKernelGGL((euler_y_strip_kernel<T, A, G14, 64, 2>), grid, dim3(128), 0, s, a); break;
+        case 64 * 1024 + 512: hipLaunchKernelGGL((euler_y_strip_kernel<T, A, G14, 64, 8>), grid, dim3(512), 0, s, a); break;
+        case 32 * 1024 + 256: hipLaunchKernelGGL((euler_y_strip_kernel<T, A, G14, 32, 8>), grid, dim3(256), 0, s, a); break;
+        case 16 * 1024 + 256: hipLaunchKernelGGL((euler_y_strip_kernel<T, A, G14, 16, 16>), grid, dim3(256), 0, s, a); break;
+        case 8 * 1024 + 256: hipLaunchKernelGGL((euler_y_strip_kernel<T, A, G14, 8, 32>), grid, dim3(256), 0, s, a); break;
+        default: hipLaunchKernelGGL((euler_y_strip_kernel<T, A, G14, 64, 4>), grid, dim3(256), 0, s, a); break;
         }
         return hipGetLastError();
     }

@@ -900,6 +900,11 @@ int hfav_plan_impl(hfav_chain *c, const hfav_plan_opts *o, hfav_plan_info *info)
         if (p.family == HFAV_FAMILY_STAR_CHAIN && star_model_choose(c, p, o->dims, &cfg)) src = HFAV_CONFIG_MODEL;
     }
 
+    // ---- EULER_Y strip kernel: the (columns, block) shapes that are built
+    if (p.family == HFAV_FAMILY_EULER_Y && (cfg.variant & 63) == 3 && !hfav::euler_y_strip_ok(cfg))
+        return hfav_fail(HFAV_EINVAL, "y strip configuration not built: tile_y columns 64 (or 1) with block 128, "
+                                      "256 or 512, or 32, 16, 8 with block 256");
+
     // ---- NORM: block and cells per thread from the field count and the
     // row length (variant 0 holds the row in registers when it fits)
     if (p.family == HFAV_FAMILY_NORM) {
@@ -965,14 +970,22 @@ int hfav_plan_impl(hfav_chain *c, const hfav_plan_opts *o, hfav_plan_info *info)
                 euler_ok = euler_ok && same_field;
             }
             // the in-place sweep runs the strip kernel: 64-cell chunks of
-            // one row along x, 64 columns x 4 rows along y
-            const int sblock = p.family == HFAV_FAMILY_EULER_X ? 64 : 256;
-            if (euler_ok && src != HFAV_CONFIG_FORCED && ((cfg.variant & 63) != 3 || cfg.block != sblock)) {
+            // one row along x, 64 columns x 4 rows or 16 x 16 along y
+            const bool ydir = p.family == HFAV_FAMILY_EULER_Y;
+            const int sblock = ydir ? 256 : 64;
+            auto ip_shape = [&](const hfav_config &k) {
+                return (k.variant & 63) == 3 && k.block == sblock &&
+                       (!ydir || hfav::euler_y_strip_cols(k) == 64 || hfav::euler_y_strip_cols(k) == 16);
+            };
+            if (euler_ok && src != HFAV_CONFIG_FORCED && !ip_shape(cfg)) {
                 cfg.variant = 3 | (cfg.variant & 64);
                 cfg.block = sblock;
-                if (p.family == HFAV_FAMILY_EULER_Y && cfg.seg <= 0) cfg.seg = 15;
+                if (ydir) {
+                    cfg.tile_y = 1;
+                    if (cfg.seg <= 0) cfg.seg = 15;
+                }
             }
-            euler_ok = euler_ok && (cfg.variant & 63) == 3 && cfg.block == sblock;
+            euler_ok = euler_ok && ip_shape(cfg);
             euler_ip = euler_ok;
         }
         if (!norm_ok && !hdiff_ok && !euler_ok) {

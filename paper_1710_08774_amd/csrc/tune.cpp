@@ -62,9 +62,23 @@ hfav_config hfav_default_config(int family, int dtype, const int dims[3]) {
         // of the 1024 resident workgroups (4 per CU), else 7, else 3 (2048^2
         // FP64: 19 rows 0.147-0.149 ms, 15 rows 0.150-0.153, 23 rows 0.151,
         // 31 rows 0.153-0.156; 512^2: 7 rows 0.025 ms against 0.035 with 15)
+        // Where they still give four rounds, 16 columns x 16 rows per chunk
+        // (a wave on a 16 x 4 patch, a chunk barrier per 16 rows) with 63- or
+        // 47-row segments (2048^2 FP64: 0.128-0.129 ms at 63 rows, 0.129-0.130
+        // at 47, against 0.139 for 64 x 4 at 19 rows on the same box; 32 x 8
+        // and 8 x 32 in between).
+        c.block = 256;
+        const double cols16 = (dims[0] + 15) / 16;
+        for (int seg : {63, 47}) {
+            if (cols16 * ((dims[1] + seg - 1) / seg) >= 4096) {
+                c.tile_y = 16;
+                c.seg = seg;
+                c.variant = 3;
+                return c;
+            }
+        }
         const double cols = (dims[0] + 63) / 64;
         auto wgs = [&](int seg) { return cols * ((dims[1] + seg - 1) / seg); };
-        c.block = 256;
         c.seg = wgs(19) >= 3072 ? 19 : wgs(15) >= 3072 ? 15 : wgs(7) >= 512 ? 7 : 3;
         c.variant = 3;
         break;

@@ -158,3 +158,31 @@ def test_in_place_batches_are_refused():
     with pytest.raises(H.HfavError) as e:
         c.plan_batch([(64, 32), (40, 50)])
     assert e.value.code == H.EUNSUP
+
+
+def test_hydro_in_place_y_strip_shapes():
+    """In place, the y strip runs 64 x 4 or 16 x 16 tiles; a forced other
+    shape falls back (AUTO) or is refused (FUSED); the default at 2048^2
+    (16 x 16) stays."""
+    c = _euler_in_place(1)
+    info = c.plan((2048, 2048))
+    assert info.fused and info.config.tile_y == 16 and info.config.block == 256
+    info = c.plan((128, 64), mode=H.MODE_FUSED, config_source=H.CONFIG_FORCED, forced=(256, 16, 15, 3))
+    assert info.fused
+    assert not c.plan((128, 64), config_source=H.CONFIG_FORCED, forced=(256, 32, 23, 3)).fused
+    with pytest.raises(H.HfavError) as e:
+        c.plan((128, 64), mode=H.MODE_FUSED, config_source=H.CONFIG_FORCED, forced=(256, 8, 31, 3))
+    assert e.value.code == H.EUNSUP
+
+
+def test_y_strip_shapes_not_built_are_refused():
+    c = H.Chain(H.euler_sweep_spec(1))
+    for forced in ((128, 16, 15, 3), (512, 32, 15, 3), (256, 12, 15, 3), (64, 1, 15, 3)):
+        with pytest.raises(H.HfavError) as e:
+            c.plan((128, 64), mode=H.MODE_FUSED, config_source=H.CONFIG_FORCED, forced=forced)
+        assert e.value.code == H.EINVAL, forced
+    # default at 2048^2: 16 x 16 with 63-row segments; small grids keep 64 x 4
+    cfg = c.plan((2048, 2048)).config
+    assert (cfg.block, cfg.tile_y, cfg.seg, cfg.variant) == (256, 16, 63, 3)
+    cfg = c.plan((512, 512)).config
+    assert (cfg.block, cfg.tile_y, cfg.variant) == (256, 1, 3)

@@ -77,10 +77,11 @@ def races(acc):
     return out
 
 
-# the kernels' shapes: y strips of 64 lines x 2, 4 or 8 rows; x strips of
-# one line x 64, 128 or 256 cells, and of 4 lines x 64 cells (the x items of
-# the one-launch batch step: a wave holds 16 cells of each of the 4 lines)
-SHAPES = [(2, 64), (4, 64), (8, 64), (64, 1), (128, 1), (256, 1), (64, 4)]
+# the kernels' shapes: y strips of 64 lines x 2, 4 or 8 rows and of 32 x 8,
+# 16 x 16 and 8 x 32 (a wave on 2, 4 or 8 rows of its tile); x strips of one
+# line x 64, 128 or 256 cells, and of 4 lines x 64 cells (the x items of the
+# one-launch batch step: a wave holds 16 cells of each of the 4 lines)
+SHAPES = [(2, 64), (4, 64), (8, 64), (8, 32), (16, 16), (32, 8), (64, 1), (128, 1), (256, 1), (64, 4)]
 
 
 @pytest.mark.parametrize("C,W", SHAPES)
@@ -89,7 +90,7 @@ def test_strip_schedule_has_no_lds_race(C, W, seg):
     assert races(schedule(C, W, 10, 10 + seg)) == []
 
 
-@pytest.mark.parametrize("C,W", [(2, 64), (4, 64), (8, 64), (128, 1), (256, 1)])
+@pytest.mark.parametrize("C,W", [(2, 64), (4, 64), (8, 64), (8, 32), (16, 16), (32, 8), (128, 1), (256, 1)])
 def test_without_the_prologue_barrier_multiwave_strips_race(C, W):
     # the first chunk's cell j0 + C takes the slot of cell j0 - 2, which
     # wave 0 reads in the prologue
