@@ -224,15 +224,17 @@ typedef struct {
     int block;      /* threads per workgroup (64, 128, 256, 512, 1024) */
     int tile_y;     /* family-specific second tile parameter (prefetch depth
                        of the 7-point chain; columns per workgroup of the y
-                       strip kernel, 8, 16, 32 or 64), or 1 */
+                       strip kernel, 8, 16, 32 or 64; rows per workgroup of
+                       the x strip kernel, 1 or 2), or 1 */
     int seg;        /* cells streamed per thread along the streamed axis */
     int variant;    /* family-specific kernel variant, 0 = default.
                        EULER_X / EULER_Y: 0 register budget free, 1 at least
                        4 waves per SIMD, 2 at least 5, 3 LDS-ring strip
                        kernel (y: tile_y columns (1: 64) x block / tile_y
                        rows per chunk, 64 x 2, 4 or 8 or 32 x 8, 16 x 16,
-                       8 x 32; segments of seg rows; x: one row, block = 64, 128
-                       or 256 cells per chunk, segments of seg cells, 0 =
+                       8 x 32; segments of seg rows; x: tile_y rows (1
+                       or 2) x block / tile_y cells per chunk, 1 x 64, 128
+                       or 256 or 2 x 32, segments of seg cells, 0 =
                        whole rows; a segment of seg cells walks seg + 1
                        chunk positions); + 64 every Newton step of the
                        Riemann solver is taken (by default the iteration

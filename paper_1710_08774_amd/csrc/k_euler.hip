@@ -432,16 +432,18 @@ __device__ __forceinline__ double strip(const EArgs<T> &a, const EView<T> &v, bo
     return smax;
 }
 
-// x pass as strips: one workgroup per segment of a.seg cells of a row
-// (W = 1, C = B lanes along it); a segment recomputes two halo cells and
-// one interface at its start, like a y segment
-template <class T, class A, bool G14, int B, bool IP = false>
-__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(4))) void euler_x_strip_kernel(EArgs<T> a) {
-    __shared__ SLds<T, 1, B> S;
-    const int nsg = (a.nx + a.seg - 1) / a.seg;
-    const int tile = xcd_tile(blockIdx.x, a.ny * nsg, a.xcd);
-    const int j = tile / nsg, i0 = (tile % nsg) * a.seg;
-    strip<T, A, G14, 1, B, IP>(a, full_view(a), true, j, i0, min(i0 + a.seg, a.nx),
+// x pass as strips: one workgroup per segment of a.seg cells of W adjacent
+// rows (C = block / W lanes along each row); a segment recomputes two halo
+// cells and one interface at its start, like a y segment.  W = 2 with one
+// wave (32 cells of 2 rows per chunk) gives each wave a more compact patch
+// of interfaces than W = 1.
+template <class T, class A, bool G14, int W, int C, bool IP = false>
+__global__ __launch_bounds__(W * C) __attribute__((amdgpu_waves_per_eu(4))) void euler_x_strip_kernel(EArgs<T> a) {
+    __shared__ SLds<T, W, C> S;
+    const int nsg = (a.nx + a.seg - 1) / a.seg, nb = (a.ny + W - 1) / W;
+    const int tile = xcd_tile(blockIdx.x, nb * nsg, a.xcd);
+    const int j = (tile / nsg) * W, i0 = (tile % nsg) * a.seg;
+    strip<T, A, G14, W, C, IP>(a, full_view(a), true, j, i0, min(i0 + a.seg, a.nx),
                                read_dt(a.dt_src, a.dt_mode, a.cfl), false, S);
 }
 
@@ -802,6 +804,14 @@ static EArgs<T> make_args(const EulerLaunch &L) {
     return a;
 }
 
+int euler_x_strip_rows(const hfav_config &cfg) { return cfg.tile_y > 1 ? cfg.tile_y : 1; }
+
+bool euler_x_strip_ok(const hfav_config &cfg) {
+    const int w = euler_x_strip_rows(cfg);
+    if (w == 1) return cfg.block == 64 || cfg.block == 128 || cfg.block == 256;
+    return w == 2 && cfg.block == 64;
+}
+
 int euler_y_strip_cols(const hfav_config &cfg) { return cfg.tile_y > 1 ? cfg.tile_y : 64; }
 
 bool euler_y_strip_ok(const hfav_config &cfg) {
@@ -849,20 +859,25 @@ static hipError_t euler_x_dispatch(const EulerLaunch &L, hipStream_t s) {
     EArgs<T> a = make_args<T>(L);
     dim3 grid(L.ny);
     if ((L.cfg.variant & ~EULER_NEWTON_ALL) == 3) {
-        // segments of cfg.seg cells (0: whole rows)
+        // segments of cfg.seg cells (0: whole rows) of W = tile_y rows (1
+        // when tile_y <= 1), block / W lanes along each row
+        if (!euler_x_strip_ok(L.cfg)) return hipErrorInvalidValue;
+        const int W = euler_x_strip_rows(L.cfg);
         a.seg = euler_strip_seg(L.nx, 0, L.cfg);
-        grid = dim3((unsigned)(L.ny * ((L.nx + a.seg - 1) / a.seg)));
+        grid = dim3((unsigned)(((L.ny + W - 1) / W) * ((L.nx + a.seg - 1) / a.seg)));
         if (L.halo) {
             if (L.cfg.block != 64) return hipErrorInvalidValue;
             const hipError_t e = save_halos(a, true, s);
             if (e != hipSuccess) return e;
-            hipLaunchKernelGGL((euler_x_strip_kernel<T, A, G14, 64, true>), grid, dim3(64), 0, s, a);
+            if (W == 2) hipLaunchKernelGGL((euler_x_strip_kernel<T, A, G14, 2, 32, true>), grid, dim3(64), 0, s, a);
+            else hipLaunchKernelGGL((euler_x_strip_kernel<T, A, G14, 1, 64, true>), grid, dim3(64), 0, s, a);
             return hipGetLastError();
         }
-        switch (L.cfg.block) {
-        case 64: hipLaunchKernelGGL((euler_x_strip_kernel<T, A, G14, 64>), grid, dim3(64), 0, s, a); break;
-        case 128: hipLaunchKernelGGL((euler_x_strip_kernel<T, A, G14, 128>), grid, dim3(128), 0, s, a); break;
-        default: hipLaunchKernelGGL((euler_x_strip_kernel<T, A, G14, 256>), grid, dim3(256), 0, s, a); break;
+        switch (W * 1024 + L.cfg.block) {
+        case 2 * 1024 + 64: hipLaunchKernelGGL((euler_x_strip_kernel<T, A, G14, 2, 32>), grid, dim3(64), 0, s, a); break;
+        case 1 * 1024 + 128: hipLaunchKernelGGL((euler_x_strip_kernel<T, A, G14, 1, 128>), grid, dim3(128), 0, s, a); break;
+        case 1 * 1024 + 256: hipLaunchKernelGGL((euler_x_strip_kernel<T, A, G14, 1, 256>), grid, dim3(256), 0, s, a); break;
+        default: hipLaunchKernelGGL((euler_x_strip_kernel<T, A, G14, 1, 64>), grid, dim3(64), 0, s, a); break;
         }
         return hipGetLastError();
     }

@@ -37,6 +37,10 @@ struct EulerLaunch {
 size_t euler_inplace_bytes(int nx, int ny, int dir, int dtype, const hfav_config &cfg);
 // segment length a strip sweep runs with (the configuration's, or its default)
 int euler_strip_seg(int n, int dir, const hfav_config &cfg);
+// x strip: rows per workgroup (tile_y, 1 when tile_y <= 1), and whether
+// the (rows, block) pair is built: 1 x 64/128/256, 2 x 64
+int euler_x_strip_rows(const hfav_config &cfg);
+bool euler_x_strip_ok(const hfav_config &cfg);
 // y strip: columns per workgroup (tile_y, 64 when tile_y <= 1), and whether
 // the (columns, block) pair is built: 64 x 128/256/512, 32/16/8 x 256
 int euler_y_strip_cols(const hfav_config &cfg);

@@ -900,10 +900,13 @@ int hfav_plan_impl(hfav_chain *c, const hfav_plan_opts *o, hfav_plan_info *info)
         if (p.family == HFAV_FAMILY_STAR_CHAIN && star_model_choose(c, p, o->dims, &cfg)) src = HFAV_CONFIG_MODEL;
     }
 
-    // ---- EULER_Y strip kernel: the (columns, block) shapes that are built
+    // ---- EULER_X / EULER_Y strip kernels: the shapes that are built
     if (p.family == HFAV_FAMILY_EULER_Y && (cfg.variant & 63) == 3 && !hfav::euler_y_strip_ok(cfg))
         return hfav_fail(HFAV_EINVAL, "y strip configuration not built: tile_y columns 64 (or 1) with block 128, "
                                       "256 or 512, or 32, 16, 8 with block 256");
+    if (p.family == HFAV_FAMILY_EULER_X && (cfg.variant & 63) == 3 && !hfav::euler_x_strip_ok(cfg))
+        return hfav_fail(HFAV_EINVAL, "x strip configuration not built: tile_y rows 1 with block 64, 128 or 256, "
+                                      "or 2 with block 64");
 
     // ---- NORM: block and cells per thread from the field count and the
     // row length (variant 0 holds the row in registers when it fits)
@@ -974,16 +977,15 @@ int hfav_plan_impl(hfav_chain *c, const hfav_plan_opts *o, hfav_plan_info *info)
             const bool ydir = p.family == HFAV_FAMILY_EULER_Y;
             const int sblock = ydir ? 256 : 64;
             auto ip_shape = [&](const hfav_config &k) {
-                return (k.variant & 63) == 3 && k.block == sblock &&
-                       (!ydir || hfav::euler_y_strip_cols(k) == 64 || hfav::euler_y_strip_cols(k) == 16);
+                if ((k.variant & 63) != 3 || k.block != sblock) return false;
+                if (ydir) return hfav::euler_y_strip_cols(k) == 64 || hfav::euler_y_strip_cols(k) == 16;
+                return hfav::euler_x_strip_rows(k) == 1 || hfav::euler_x_strip_rows(k) == 2;
             };
             if (euler_ok && src != HFAV_CONFIG_FORCED && !ip_shape(cfg)) {
                 cfg.variant = 3 | (cfg.variant & 64);
                 cfg.block = sblock;
-                if (ydir) {
-                    cfg.tile_y = 1;
-                    if (cfg.seg <= 0) cfg.seg = 15;
-                }
+                cfg.tile_y = 1;
+                if (ydir && cfg.seg <= 0) cfg.seg = 15;
             }
             euler_ok = euler_ok && ip_shape(cfg);
             euler_ip = euler_ok;

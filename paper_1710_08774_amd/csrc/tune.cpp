@@ -52,6 +52,11 @@ hfav_config hfav_default_config(int family, int dtype, const int dims[3]) {
         c.block = 64;
         c.variant = 3;
         c.seg = (double)dims[1] * ((dims[0] + 190) / 191) >= 16384 ? 191 : 63;
+        // one wave on 2 rows x 32 cells per chunk where that still gives
+        // 8192 workgroups of 191-cell segments (2048^2 FP64: 0.127-0.128 ms
+        // against 0.129 for one row x 64 cells; 4 x 16 and 8 x 8 slower, the
+        // shorter chunks cost more than the compact patch saves)
+        if (c.seg == 191 && (double)((dims[1] + 1) / 2) * ((dims[0] + 190) / 191) >= 8192) c.tile_y = 2;
         break;
     }
     case HFAV_FAMILY_EULER_Y: {

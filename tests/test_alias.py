@@ -186,3 +186,18 @@ def test_y_strip_shapes_not_built_are_refused():
     assert (cfg.block, cfg.tile_y, cfg.seg, cfg.variant) == (256, 16, 63, 3)
     cfg = c.plan((512, 512)).config
     assert (cfg.block, cfg.tile_y, cfg.variant) == (256, 1, 3)
+
+
+def test_x_strip_shapes_not_built_are_refused_and_default():
+    c = H.Chain(H.euler_sweep_spec(0))
+    for forced in ((128, 2, 191, 3), (64, 4, 191, 3), (256, 2, 63, 3)):
+        with pytest.raises(H.HfavError) as e:
+            c.plan((128, 64), mode=H.MODE_FUSED, config_source=H.CONFIG_FORCED, forced=forced)
+        assert e.value.code == H.EINVAL, forced
+    cfg = c.plan((2048, 2048)).config
+    assert (cfg.block, cfg.tile_y, cfg.seg, cfg.variant) == (64, 2, 191, 3)
+    cfg = c.plan((512, 512)).config
+    assert (cfg.block, cfg.tile_y, cfg.variant) == (64, 1, 3)
+    ip = _euler_in_place(0)
+    info = ip.plan((2048, 2048))
+    assert info.fused and info.config.tile_y == 2

@@ -80,8 +80,9 @@ def races(acc):
 # the kernels' shapes: y strips of 64 lines x 2, 4 or 8 rows and of 32 x 8,
 # 16 x 16 and 8 x 32 (a wave on 2, 4 or 8 rows of its tile); x strips of one
 # line x 64, 128 or 256 cells, and of 4 lines x 64 cells (the x items of the
-# one-launch batch step: a wave holds 16 cells of each of the 4 lines)
-SHAPES = [(2, 64), (4, 64), (8, 64), (8, 32), (16, 16), (32, 8), (64, 1), (128, 1), (256, 1), (64, 4)]
+# one-launch batch step: a wave holds 16 cells of each of the 4 lines) and
+# of 2 lines x 32 cells in one wave
+SHAPES = [(2, 64), (4, 64), (8, 64), (8, 32), (16, 16), (32, 8), (64, 1), (128, 1), (256, 1), (64, 4), (32, 2)]
 
 
 @pytest.mark.parametrize("C,W", SHAPES)
