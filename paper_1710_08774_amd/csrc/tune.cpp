@@ -44,34 +44,34 @@ hfav_config hfav_default_config(int family, int dtype, const int dims[3]) {
         break;
     }
     case HFAV_FAMILY_EULER_X: {
-        // LDS-ring strips, one wave per row segment of seg cells (64 per
-        // chunk; seg = 64k - 1 leaves no chunk lane idle): 191-cell
+        // LDS-ring strips, one wave per segment of seg cells of a row (64
+        // per chunk; seg = 64k - 1 leaves no chunk lane idle): 191-cell
         // segments while they give at least 16384 workgroups, else 63
         // (2048^2 FP64: 0.153 ms against 0.162 for one 4-wave workgroup
-        // per row, whose 2048 workgroups fill 1.6 rounds of the chip)
-        c.block = 64;
-        c.variant = 3;
-        c.seg = (double)dims[1] * ((dims[0] + 190) / 191) >= 16384 ? 191 : 63;
-        // one wave on 2 rows x 32 cells per chunk where that still gives
+        // per row, whose 2048 workgroups fill 1.6 rounds of the chip).  The
+        // wave on 2 rows x 32 cells per chunk instead where that still gives
         // 8192 workgroups of 191-cell segments (2048^2 FP64: 0.127-0.128 ms
         // against 0.129 for one row x 64 cells; 4 x 16 and 8 x 8 slower, the
         // shorter chunks cost more than the compact patch saves)
+        c.block = 64;
+        c.variant = 3;
+        c.seg = (double)dims[1] * ((dims[0] + 190) / 191) >= 16384 ? 191 : 63;
         if (c.seg == 191 && (double)((dims[1] + 1) / 2) * ((dims[0] + 190) / 191) >= 8192) c.tile_y = 2;
         break;
     }
     case HFAV_FAMILY_EULER_Y: {
-        // LDS-ring strips of 64 columns x 4 rows per chunk (4-wave
-        // workgroups; 2- and 8-wave ones measured slower).  A segment of seg
-        // rows walks seg + 1 chunk rows, so seg = 4k - 1 leaves no chunk row
-        // idle; the longest of 19 and 15 rows that still gives three rounds
-        // of the 1024 resident workgroups (4 per CU), else 7, else 3 (2048^2
-        // FP64: 19 rows 0.147-0.149 ms, 15 rows 0.150-0.153, 23 rows 0.151,
-        // 31 rows 0.153-0.156; 512^2: 7 rows 0.025 ms against 0.035 with 15)
-        // Where they still give four rounds, 16 columns x 16 rows per chunk
-        // (a wave on a 16 x 4 patch, a chunk barrier per 16 rows) with 63- or
-        // 47-row segments (2048^2 FP64: 0.128-0.129 ms at 63 rows, 0.129-0.130
-        // at 47, against 0.139 for 64 x 4 at 19 rows on the same box; 32 x 8
-        // and 8 x 32 in between).
+        // LDS-ring strips of 256 lanes.  A segment of seg rows walks seg + 1
+        // chunk rows, so seg = Ck - 1 leaves no chunk row idle (C rows per
+        // chunk).  Where they still give four rounds of the 1024 resident
+        // workgroups (4 per CU): 16 columns x 16 rows per chunk (a wave on a
+        // 16 x 4 patch, a chunk barrier per 16 rows) with 63- or 47-row
+        // segments (2048^2 FP64: 0.128-0.129 ms at 63 rows, 0.129-0.130 at
+        // 47, against 0.139 for 64 x 4 at 19 rows on the same box; 32 x 8
+        // and 8 x 32 in between).  Else 64 columns x 4 rows (2- and 8-wave
+        // workgroups measured slower) with the longest of 19 and 15 rows that
+        // still gives three rounds, else 7, else 3 (2048^2 FP64, 64 x 4: 19
+        // rows 0.147-0.149 ms, 15 rows 0.150-0.153, 23 rows 0.151, 31 rows
+        // 0.153-0.156; 512^2: 7 rows 0.025 ms against 0.035 with 15).
         c.block = 256;
         const double cols16 = (dims[0] + 15) / 16;
         for (int seg : {63, 47}) {
