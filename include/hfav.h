@@ -431,10 +431,13 @@ const char *hfav_build_id(void);
  * grid term is then ONE packed device buffer holding grid g at element
  * offset hfav_batch_offset(chain, g), and every 0-D term is a device array of
  * n_grids doubles (one dt / CFL slot per grid).  The y-sweep segment length
- * of each grid (rows per work item of 64 columns, 1..255; default 15) comes
+ * of each grid (rows per y work item, 1..255; default 15) comes
  * from the configuration source (the tuning table is consulted with that
  * grid's own size; a forced configuration gives every grid its seg).  Host
  * only; allocates nothing.
+ *
+ * The per-sweep form's work items: x, one wave on 2 rows x 191 cells; y,
+ * 16 columns x the grid's segment of rows.
  *
  * The time step in one launch (Design, "Fusing iteration nests": the two
  * sweeps' nests fused; the x-swept state is not contracted across grids'

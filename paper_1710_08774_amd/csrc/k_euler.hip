@@ -520,43 +520,50 @@ __device__ __forceinline__ EView<T> grid_view(const EArgs<T> &a, const BatchDims
                     a.orho + c.off, a.omn + c.off, a.omt + c.off, a.oE + c.off, d.nx[c.g], d.ny[c.g]};
 }
 
-// x items: segments of BATCH_XSEG cells of one row, one wave each (the
-// strip body with W = 1, C = 64, as the single-grid x sweep)
-constexpr int BATCH_XSEG = 191;
+// x items: segments of BATCH_XSEG cells of two rows, one wave each (the
+// strip body with W = 2, C = 32, as the single-grid x sweep's default: each
+// wave on a compact patch of 32 cells x 2 rows)
+constexpr int BATCH_XSEG = 191, BATCH_XROWS = 2, BATCH_YCOLS = 16;
+
+__device__ __forceinline__ long long pool_x_items(const BatchDims &d, int g) {
+    return (long long)((d.ny[g] + BATCH_XROWS - 1) / BATCH_XROWS) * ((d.nx[g] + BATCH_XSEG - 1) / BATCH_XSEG);
+}
+
+__device__ __forceinline__ long long pool_y_items(const BatchDims &d, int g) {
+    return (long long)((d.nx[g] + BATCH_YCOLS - 1) / BATCH_YCOLS) * ((d.ny[g] + d.seg[g] - 1) / d.seg[g]);
+}
 
 template <class T, class A, bool G14>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void euler_x_batch_kernel(EArgs<T> a, BatchDims d, long long items) {
-    __shared__ SLds<T, 1, 64> S;
+    __shared__ SLds<T, BATCH_XROWS, 64 / BATCH_XROWS> S;
     Cursor c{0, 0, 0};
-    auto segs = [&](int g) { return (long long)d.ny[g] * ((d.nx[g] + BATCH_XSEG - 1) / BATCH_XSEG); };
     for (long long it = blockIdx.x; it < items; it += gridDim.x) {
-        advance(c, it, d, segs);
+        advance(c, it, d, [&](int g) { return pool_x_items(d, g); });
         const EView<T> v = grid_view(a, d, c);
         const int nsg = (v.nx + BATCH_XSEG - 1) / BATCH_XSEG;
         const int local = (int)(it - c.base);
-        const int j = local / nsg, i0 = (local % nsg) * BATCH_XSEG;
+        const int j = (local / nsg) * BATCH_XROWS, i0 = (local % nsg) * BATCH_XSEG;
         const double dt = read_dt(a.dt_src + c.g, a.dt_mode, a.cfl);
-        strip<T, A, G14, 1, 64>(a, v, true, j, i0, min(i0 + BATCH_XSEG, v.nx), dt, false, S);
+        strip<T, A, G14, BATCH_XROWS, 64 / BATCH_XROWS>(a, v, true, j, i0, min(i0 + BATCH_XSEG, v.nx), dt, false, S);
     }
 }
 
-// y items: tiles of 64 columns x seg[g] rows, 4-wave strips (C = 4)
+// y items: tiles of 16 columns x seg[g] rows in chunks of 16 rows (the
+// single-grid y sweep's default shape)
 template <class T, class A, bool G14>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void euler_y_batch_kernel(EArgs<T> a, BatchDims d, long long items) {
-    __shared__ SLds<T, 64, 4> S;
+    __shared__ SLds<T, BATCH_YCOLS, 256 / BATCH_YCOLS> S;
     Cursor c{0, 0, 0};
-    auto tiles = [&](int g) {
-        return (long long)((d.nx[g] + 63) / 64) * ((d.ny[g] + d.seg[g] - 1) / d.seg[g]);
-    };
     for (long long it = blockIdx.x; it < items; it += gridDim.x) {
-        advance(c, it, d, tiles);
+        advance(c, it, d, [&](int g) { return pool_y_items(d, g); });
         const EView<T> v = grid_view(a, d, c);
-        const int ntx = (v.nx + 63) / 64;
+        const int ntx = (v.nx + BATCH_YCOLS - 1) / BATCH_YCOLS;
         const int tile = (int)(it - c.base);
-        const int i0 = (tile % ntx) * 64, j0 = (tile / ntx) * d.seg[c.g];
+        const int i0 = (tile % ntx) * BATCH_YCOLS, j0 = (tile / ntx) * d.seg[c.g];
         const int j1 = min(j0 + (int)d.seg[c.g], v.ny);
         const double dt = read_dt(a.dt_src + c.g, a.dt_mode, a.cfl);
-        const double smax = strip<T, A, G14, 64, 4>(a, v, false, i0, j0, j1, dt, a.smax_out != nullptr, S);
+        const double smax = strip<T, A, G14, BATCH_YCOLS, 256 / BATCH_YCOLS>(a, v, false, i0, j0, j1, dt,
+                                                                              a.smax_out != nullptr, S);
         if (a.smax_out) block_max_to<256>(smax, a.smax_out + c.g);
     }
 }
@@ -993,8 +1000,8 @@ static hipError_t batch_dispatch(const EulerLaunch &L, const EulerBatch &Bt, boo
     long long items = 0;
     for (int g = 0; g < Bt.n; ++g) {
         if (Bt.seg[g] < 1) return hipErrorInvalidValue;
-        items += x ? (long long)Bt.ny[g] * ((Bt.nx[g] + BATCH_XSEG - 1) / BATCH_XSEG)
-                   : (long long)((Bt.nx[g] + 63) / 64) * ((Bt.ny[g] + Bt.seg[g] - 1) / Bt.seg[g]);
+        items += x ? (long long)((Bt.ny[g] + BATCH_XROWS - 1) / BATCH_XROWS) * ((Bt.nx[g] + BATCH_XSEG - 1) / BATCH_XSEG)
+                   : (long long)((Bt.nx[g] + BATCH_YCOLS - 1) / BATCH_YCOLS) * ((Bt.ny[g] + Bt.seg[g] - 1) / Bt.seg[g]);
     }
     // resident pool: 4 waves per SIMD on 256 CUs (the register budget at
     // which the sweep bodies run without spilling: at 5 waves the unrolled
