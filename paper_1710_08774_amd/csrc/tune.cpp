@@ -49,14 +49,19 @@ hfav_config hfav_default_config(int family, int dtype, const int dims[3]) {
         // segments while they give at least 16384 workgroups, else 63
         // (2048^2 FP64: 0.153 ms against 0.162 for one 4-wave workgroup
         // per row, whose 2048 workgroups fill 1.6 rounds of the chip).  The
-        // wave on 2 rows x 32 cells per chunk instead where that still gives
-        // 8192 workgroups of 191-cell segments (2048^2 FP64: 0.127-0.128 ms
-        // against 0.129 for one row x 64 cells; 4 x 16 and 8 x 8 slower, the
-        // shorter chunks cost more than the compact patch saves)
+        // wave on 2 rows x 32 cells per chunk instead, with 159-cell
+        // segments, where that still gives 8192 workgroups (2048^2 FP64:
+        // 0.127-0.128 ms against 0.130-0.132 with 191-cell segments and 0.129
+        // for one row x 64 cells; 127-cell segments 0.129, 255 and longer
+        // 0.138-0.145; 4 x 16 and 8 x 8 slower, the shorter chunks cost more
+        // than the compact patch saves)
         c.block = 64;
         c.variant = 3;
         c.seg = (double)dims[1] * ((dims[0] + 190) / 191) >= 16384 ? 191 : 63;
-        if (c.seg == 191 && (double)((dims[1] + 1) / 2) * ((dims[0] + 190) / 191) >= 8192) c.tile_y = 2;
+        if (c.seg == 191 && (double)((dims[1] + 1) / 2) * ((dims[0] + 158) / 159) >= 8192) {
+            c.tile_y = 2;
+            c.seg = 159;
+        }
         break;
     }
     case HFAV_FAMILY_EULER_Y: {

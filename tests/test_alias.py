@@ -195,7 +195,7 @@ def test_x_strip_shapes_not_built_are_refused_and_default():
             c.plan((128, 64), mode=H.MODE_FUSED, config_source=H.CONFIG_FORCED, forced=forced)
         assert e.value.code == H.EINVAL, forced
     cfg = c.plan((2048, 2048)).config
-    assert (cfg.block, cfg.tile_y, cfg.seg, cfg.variant) == (64, 2, 191, 3)
+    assert (cfg.block, cfg.tile_y, cfg.seg, cfg.variant) == (64, 2, 159, 3)
     cfg = c.plan((512, 512)).config
     assert (cfg.block, cfg.tile_y, cfg.variant) == (64, 1, 3)
     ip = _euler_in_place(0)
